@@ -1,0 +1,238 @@
+/*
+ * cpca.h -- C ABI of the MI355X (gfx950) library for the graph-regularised
+ * low-rank solvers of Compressive PCA on graphs (Shahid, Perraudin, Puy,
+ * Vandergheynst, arXiv 1602.02070).
+ *
+ * Notation (Sections II-V of the paper):
+ *   Y, X          p x n data / low-rank matrices; rows are features (row graph
+ *                 G_r, Laplacian L_r, p x p), columns are samples (column graph
+ *                 G_c, Laplacian L_c, n x n).
+ *   Omega_r/_c    sampled row / column indices (eq. (Mc)), rho_r = |Omega_r|,
+ *                 rho_c = |Omega_c|; Y~ = M_r Y M_c is rho_r x rho_c and its
+ *                 row a / column b is row Omega_r[a] / column Omega_c[b] of Y.
+ *   L~_r, L~_c    Laplacians of the graphs on the sampled rows / columns.
+ *
+ * Conventions shared by every entry point:
+ *   - Dense matrices are row-major (the column index is contiguous) and live
+ *     in caller-owned DEVICE memory. Inputs are never modified; outputs
+ *     (*_out) are written on CPCA_OK and, for iterative calls, on
+ *     CPCA_ENOCONV (then they hold the last iterate).
+ *   - Element type follows the mode: double for CPCA_FP64, float for
+ *     CPCA_FP32 and CPCA_FP32_IR. CSR values are always double.
+ *   - CSR matrices (cpca_csr) are square, symmetric positive semi-definite
+ *     (graph Laplacians), int32 row pointers / column indices in device
+ *     memory, with at most INT32_MAX non-zeros. Symmetry is assumed, not
+ *     checked: row j of L_c is used as column j. Structure (monotone row
+ *     pointers, indices in range) and finiteness are checked on every call.
+ *   - Index sets are int32 device arrays whose entries are distinct and in
+ *     range (checked on every call).
+ *   - Every call is synchronous with respect to the host: it enqueues work
+ *     on the handle's stream and returns after that work has finished, so
+ *     `info` is valid on return. Calls on one handle must not overlap.
+ *   - Argument checks happen before any device work; CPCA_EINVAL leaves the
+ *     outputs untouched. cpca_last_error() describes the last failure of the
+ *     calling thread.
+ *   - No exception or abort crosses this interface.
+ */
+#ifndef CPCA_H
+#define CPCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpca_handle_s* cpca_handle;
+
+typedef enum {
+  CPCA_OK = 0,
+  CPCA_EINVAL = 1,   /* invalid argument (nothing was written)               */
+  CPCA_ENOCONV = 2,  /* max_iter reached before the tolerance                */
+  CPCA_ENOTSPD = 3,  /* CG breakdown: <p, A p> <= 0 (operator not definite)  */
+  CPCA_ENAN = 4,     /* NaN or Inf met during the iteration                  */
+  CPCA_EHIP = 5,     /* HIP runtime error                                    */
+  CPCA_ENOMEM = 6    /* device or pinned-host allocation failed              */
+} cpca_status;
+
+typedef enum {
+  CPCA_FP64 = 0,     /* everything in FP64                                   */
+  CPCA_FP32 = 1,     /* FP32 vectors and sparse products, FP64 CG scalars    */
+  CPCA_FP32_IR = 2   /* FP32 inner CG inside FP64 iterative refinement: the
+                        residual B - A(X) and the solution accumulate in FP64 */
+} cpca_mode;
+
+typedef struct {
+  int64_t n;               /* order of the square matrix                     */
+  int64_t nnz;             /* number of stored entries                       */
+  const int32_t* rowptr;   /* n + 1 entries, rowptr[0] = 0, rowptr[n] = nnz  */
+  const int32_t* colind;   /* nnz column indices in [0, n)                   */
+  const double* vals;      /* nnz values                                     */
+} cpca_csr;
+
+typedef struct {
+  int32_t iters;           /* FISTA iterations run / total CG iterations     */
+  int32_t outer_iters;     /* refinement steps (CPCA_FP32_IR), else 0        */
+  int32_t status;          /* same value as the call's return code           */
+  int32_t reserved;
+  double rel_residual;     /* decode: FP64 ||B - A(X)||_F / ||B||_F of the
+                              returned X; frpcag: last ||Z+ - Z||^2/||Z||^2  */
+  double objective;        /* frpcag: objective of eq. (frpcag_small) at the
+                              returned X~; decode: 0                          */
+  double ms;               /* wall time of the call                          */
+} cpca_info;
+
+/* Library version string ("major.minor.patch"). */
+const char* cpca_version(void);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* cpca_last_error(void);
+
+/*
+ * Create a handle bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL means the legacy default stream). The handle owns all
+ * workspace; it grows on demand and is released by cpca_destroy.
+ * Errors: EINVAL (h == NULL), EHIP, ENOMEM.
+ */
+cpca_status cpca_create(cpca_handle* h, void* hip_stream);
+cpca_status cpca_destroy(cpca_handle h);
+
+/* Re-bind the handle to another stream of the same device. */
+cpca_status cpca_set_stream(cpca_handle h, void* hip_stream);
+
+/*
+ * FRPCAG on the sampled matrix by FISTA (Section IV.B, Algorithm 1):
+ *
+ *   min_X ||Y~ - X||_1 + gamma_c tr(X L~_c X^T) + gamma_r tr(X^T L~_r X)
+ *
+ * Ytil        rho_r x rho_c input (double for FP64, float otherwise).
+ * Lr_til      rho_r x rho_r Laplacian; Lc_til rho_c x rho_c Laplacian.
+ * gamma_r/_c  >= 0 and finite.
+ * lmax_r/_c   spectral norms ||L~_r||_2, ||L~_c||_2 (largest eigenvalues),
+ *             > 0 when the matching gamma is > 0. The step is 1/beta' with
+ *             beta' = 2 gamma_c lmax_c + 2 gamma_r lmax_r; beta' = 0 returns Y~.
+ * max_iter    J >= 0. eps >= 0: stop after iteration j when
+ *             ||Z_{j+1} - Z_j||_F^2 < eps ||Z_j||_F^2; eps = 0 runs exactly J
+ *             iterations.
+ * Xtil_out    rho_r x rho_c output: the last prox iterate S_j.
+ * The iteration state is FP64 in every mode (the FP32 modes only convert the
+ * input and the output).
+ * Returns OK (also when J iterations ran with eps > 0 unmet), EINVAL, ENAN,
+ * EHIP, ENOMEM.
+ */
+cpca_status cpca_frpcag(cpca_handle h, cpca_mode mode,
+                        const void* Ytil, int64_t rho_r, int64_t rho_c,
+                        const cpca_csr* Lr_til, const cpca_csr* Lc_til,
+                        double gamma_r, double gamma_c,
+                        double lmax_r, double lmax_c,
+                        int32_t max_iter, double eps,
+                        void* Xtil_out, cpca_info* info);
+
+/*
+ * Alternate decoder (Section V.B, eq. alternatedecoder) solved by conjugate
+ * gradient on its normal equations
+ *
+ *   (m_r m_c^T) o X + gamma_r L_r X + gamma_c X L_c = M_r^T X~ M_c^T,
+ *
+ * where m_r / m_c are the 0/1 indicators of Omega_r / Omega_c.
+ * Xtil        rho_r x rho_c (row a, column b belongs at (omega_r[a], omega_c[b])).
+ * omega_r/_c  rho_r / rho_c distinct int32 indices in [0, p) / [0, n).
+ * Lr, Lc      p x p and n x n Laplacians; gamma_r/_c >= 0 and finite.
+ * tol         > 0: stop when ||B - A(X)||_F <= tol ||B||_F, measured on the CG
+ *             recursive residual (FP64 and FP32 modes) or on the true FP64
+ *             residual of each refinement step (FP32_IR). info.rel_residual
+ *             always reports the true FP64 residual of the returned X.
+ * max_iter    > 0: cap on CG iterations (in FP32_IR: per inner solve; at
+ *             most 40 refinement steps).
+ * X0          optional p x n warm start (NULL: zero).
+ * X_out       p x n solution.
+ * Returns OK, EINVAL, ENOCONV, ENOTSPD (gamma = 0 with partial sampling can
+ * make A singular; CG from zero still returns the minimum-norm solution when
+ * the right-hand side is consistent), ENAN, EHIP, ENOMEM.
+ */
+cpca_status cpca_decode(cpca_handle h, cpca_mode mode,
+                        const void* Xtil, int64_t rho_r, int64_t rho_c,
+                        const int32_t* omega_r, const int32_t* omega_c,
+                        int64_t p, int64_t n,
+                        const cpca_csr* Lr, const cpca_csr* Lc,
+                        double gamma_r, double gamma_c,
+                        double tol, int32_t max_iter,
+                        const void* X0, void* X_out, cpca_info* info);
+
+/*
+ * Adjoint of cpca_decode. Given G = dl/dX at the decoder solution X, solves
+ * A Lambda = G (A is symmetric) with the same solver and returns
+ *   dXtil_out = Lambda[Omega_r, Omega_c]            (rho_r x rho_c),
+ *   *dgamma_r = -<Lambda, L_r X>,  *dgamma_c = -<Lambda, X L_c>   (FP64),
+ * which follow from differentiating A(gamma) X = M_r^T X~ M_c^T.
+ * G, X: p x n device arrays of the mode's type; dgamma_r/_c: host pointers.
+ */
+cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode,
+                                 const void* G, const void* X,
+                                 int64_t rho_r, int64_t rho_c,
+                                 const int32_t* omega_r, const int32_t* omega_c,
+                                 int64_t p, int64_t n,
+                                 const cpca_csr* Lr, const cpca_csr* Lc,
+                                 double gamma_r, double gamma_c,
+                                 double tol, int32_t max_iter,
+                                 void* dXtil_out, double* dgamma_r,
+                                 double* dgamma_c, cpca_info* info);
+
+/*
+ * One application of the decoder operator (the fused two-sided sparse
+ * product of eq. alternatedecoder's normal equations):
+ *   Q = (m_r m_c^T) o P + gamma_r L_r P + gamma_c P L_c,  *pq = <P, Q> (FP64).
+ * With rho_r = rho_c = 0 (omega pointers may then be NULL) the mask term is
+ * zero. P, Q: p x n of the mode's type (FP32_IR behaves as FP32). pq may be
+ * NULL.
+ */
+cpca_status cpca_apply(cpca_handle h, cpca_mode mode, const void* P, void* Q,
+                       int64_t p, int64_t n,
+                       const int32_t* omega_r, int64_t rho_r,
+                       const int32_t* omega_c, int64_t rho_c,
+                       const cpca_csr* Lr, const cpca_csr* Lc,
+                       double gamma_r, double gamma_c, double* pq);
+
+/*
+ * Host-side structural checks, exposed so that they can be exercised
+ * without a GPU. Pointers are HOST memory here.
+ *   cpca_check_csr_host: rowptr monotone with rowptr[0] = 0 and
+ *     rowptr[n] = nnz, every column index in [0, n), every value finite
+ *     (vals may be NULL to skip the value check).
+ *   cpca_check_index_set_host: `count` distinct indices in [0, dim).
+ * Return OK or EINVAL (message in cpca_last_error).
+ */
+cpca_status cpca_check_csr_host(int64_t n, int64_t nnz, const int32_t* rowptr,
+                                const int32_t* colind, const double* vals);
+cpca_status cpca_check_index_set_host(int64_t count, int64_t dim,
+                                      const int32_t* idx);
+
+/*
+ * Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch of the named kernel family. Families: "apply" (the fused
+ * two-sided sparse product with the CG epilogue), "update" (the CG x/r
+ * update), "fista" (the fused FISTA step), "other" (the fused product with
+ * any other epilogue: residual, objective, adjoint dots, plain apply).
+ * Enabling resets the counters.
+ * cpca_get_profile returns the number of timed launches and their summed
+ * duration in milliseconds.
+ */
+cpca_status cpca_set_profiling(cpca_handle h, int32_t enable);
+cpca_status cpca_get_profile(cpca_handle h, const char* family,
+                             int64_t* launches, double* total_ms);
+
+/*
+ * Launch shape of the fused two-sided product on this handle:
+ * rows_per_block in {0, 1, 2, 4, 8} (0 = automatic choice), use_lds in
+ * {-1, 0, 1} (-1 = automatic; 1 = stage the block's rows in LDS when they
+ * fit in 64 KiB, 0 = gather X L_c operands from global memory).
+ * Results do not depend on the shape beyond floating-point summation order
+ * of the X L_c term (which stays fixed per shape).
+ */
+cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_block, int32_t use_lds);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPCA_H */

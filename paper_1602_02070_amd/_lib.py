@@ -1,0 +1,85 @@
+"""ctypes view of libcpca.so (the C ABI declared in include/cpca.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcpca.so")
+
+OK, EINVAL, ENOCONV, ENOTSPD, ENAN, EHIP, ENOMEM = range(7)
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOCONV: "ENOCONV", ENOTSPD: "ENOTSPD",
+                ENAN: "ENAN", EHIP: "EHIP", ENOMEM: "ENOMEM"}
+MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2}
+
+EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
+           "cpca_set_stream", "cpca_frpcag", "cpca_decode", "cpca_decode_backward",
+           "cpca_apply", "cpca_check_csr_host", "cpca_check_index_set_host",
+           "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config"]
+
+
+class CpcaCsr(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("nnz", c_int64), ("rowptr", c_void_p),
+                ("colind", c_void_p), ("vals", c_void_p)]
+
+
+class CpcaInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("outer_iters", c_int32), ("status", c_int32),
+                ("reserved", c_int32), ("rel_residual", c_double),
+                ("objective", c_double), ("ms", c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def _declare(lib):
+    st = c_int32
+    P = c_void_p
+    csr = POINTER(CpcaCsr)
+    info = POINTER(CpcaInfo)
+    sig = {
+        "cpca_version": (c_char_p, []),
+        "cpca_last_error": (c_char_p, []),
+        "cpca_create": (st, [POINTER(c_void_p), P]),
+        "cpca_destroy": (st, [P]),
+        "cpca_set_stream": (st, [P, P]),
+        "cpca_frpcag": (st, [P, c_int32, P, c_int64, c_int64, csr, csr, c_double, c_double,
+                             c_double, c_double, c_int32, c_double, P, info]),
+        "cpca_decode": (st, [P, c_int32, P, c_int64, c_int64, P, P, c_int64, c_int64, csr, csr,
+                             c_double, c_double, c_double, c_int32, P, P, info]),
+        "cpca_decode_backward": (st, [P, c_int32, P, P, c_int64, c_int64, P, P, c_int64, c_int64,
+                                      csr, csr, c_double, c_double, c_double, c_int32, P,
+                                      POINTER(c_double), POINTER(c_double), info]),
+        "cpca_apply": (st, [P, c_int32, P, P, c_int64, c_int64, P, c_int64, P, c_int64, csr, csr,
+                            c_double, c_double, POINTER(c_double)]),
+        "cpca_check_csr_host": (st, [c_int64, c_int64, P, P, P]),
+        "cpca_check_index_set_host": (st, [c_int64, c_int64, P]),
+        "cpca_set_profiling": (st, [P, c_int32]),
+        "cpca_get_profile": (st, [P, c_char_p, POINTER(c_int64), POINTER(c_double)]),
+        "cpca_set_apply_config": (st, [P, c_int32, c_int32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+def load(path: str | None = None):
+    """Load libcpca.so. Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    _lib = _declare(ctypes.CDLL(path))
+    return _lib
+
+
+def last_error() -> str:
+    return load().cpca_last_error().decode()

@@ -1,0 +1,992 @@
+// Host drivers and the C ABI of the CPCA solver library (gfx950).
+//
+//   cpca_frpcag          FISTA for FRPCAG on the sampled matrix (Alg. 1)
+//   cpca_decode          alternate decoder by CG / FP64 iterative refinement
+//   cpca_decode_backward adjoint CG solve + gather + FP64 gamma gradients
+//   cpca_apply           one application of the decoder operator
+//
+// Every call validates its arguments on the host, copies the (small) CSR
+// and index arrays to the host to check them and to build the device
+// layouts (CSR of L_r in the compute type, sliced ELL of L_c, 0/1 masks),
+// then runs entirely on the handle's stream. Convergence scalars stay on
+// the device; the host polls them at geometrically growing intervals.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cpca.h"
+#include "kernels.hpp"
+#include "validate.hpp"
+
+using namespace cpca;
+
+namespace {
+
+// apply: the CG operator application; other: residual / objective / dot launches
+enum Family { FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_COUNT = 4 };
+
+}  // namespace
+
+struct cpca_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;          // workspace (device)
+  size_t ws_cap = 0;
+  char* fixed = nullptr;       // counters + scalars (device), zeroed at creation
+  void* pinned = nullptr;      // host mirror of the scalars
+  int force_R = 0;             // tuning override (CPCA_APPLY_R)
+  int force_lds = -1;          // tuning override (CPCA_APPLY_LDS)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<int> ev_fam;
+  size_t ev_used = 0;
+  int64_t prof_n[FAM_COUNT] = {0, 0, 0, 0};
+  double prof_ms[FAM_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+// Layout of the `fixed` device block.
+constexpr size_t kOffCounter = 0;          // unsigned[16]
+constexpr size_t kOffCg = 256;             // CgScal[2]
+constexpr size_t kOffFista = 512;          // FistaScal
+constexpr size_t kOffResults = 768;        // double[32]
+constexpr size_t kFixedBytes = 1024;
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      return fail(_e == hipErrorOutOfMemory ? CPCA_ENOMEM : CPCA_EHIP,            \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));             \
+    }                                                                             \
+  } while (0)
+
+#define STCHK(expr)                   \
+  do {                                \
+    cpca_status _s = (expr);          \
+    if (_s != CPCA_OK) return _s;     \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Two-pass bump allocator: the first pass (base == nullptr) only measures.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+cpca_status ensure_ws(cpca_handle h, size_t bytes) {
+  if (bytes <= h->ws_cap) return CPCA_OK;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (h->ws) HIPCHK(hipFree(h->ws));
+  h->ws = nullptr;
+  h->ws_cap = 0;
+  const size_t cap = align_up(bytes + bytes / 8, 1 << 20);
+  HIPCHK(hipMalloc(&h->ws, cap));
+  h->ws_cap = cap;
+  return CPCA_OK;
+}
+
+unsigned* counter_ptr(cpca_handle h) { return reinterpret_cast<unsigned*>(h->fixed + kOffCounter); }
+CgScal* cg_ptr(cpca_handle h, int k = 0) { return reinterpret_cast<CgScal*>(h->fixed + kOffCg) + k; }
+FistaScal* fista_ptr(cpca_handle h) { return reinterpret_cast<FistaScal*>(h->fixed + kOffFista); }
+double* results_ptr(cpca_handle h) { return reinterpret_cast<double*>(h->fixed + kOffResults); }
+
+// Copy the fixed scalar block to the pinned mirror and wait.
+cpca_status read_fixed(cpca_handle h) {
+  HIPCHK(hipMemcpyAsync(h->pinned, h->fixed, kFixedBytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return CPCA_OK;
+}
+const CgScal& host_cg(cpca_handle h, int k = 0) {
+  return reinterpret_cast<const CgScal*>(static_cast<char*>(h->pinned) + kOffCg)[k];
+}
+const FistaScal& host_fista(cpca_handle h) {
+  return *reinterpret_cast<const FistaScal*>(static_cast<char*>(h->pinned) + kOffFista);
+}
+const double* host_results(cpca_handle h) {
+  return reinterpret_cast<const double*>(static_cast<char*>(h->pinned) + kOffResults);
+}
+
+// ---------------------------------------------------------------- profiling
+cpca_status prof_begin(cpca_handle h, int fam) {
+  if (!h->prof) return CPCA_OK;
+  if (2 * h->ev_used + 2 > h->ev.size()) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    h->ev.push_back(a);
+    h->ev.push_back(b);
+    h->ev_fam.push_back(fam);
+  }
+  h->ev_fam[h->ev_used] = fam;
+  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used], h->stream));
+  return CPCA_OK;
+}
+cpca_status prof_end(cpca_handle h) {
+  if (!h->prof) return CPCA_OK;
+  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream));
+  ++h->ev_used;
+  return CPCA_OK;
+}
+// Only after the stream has been synchronised.
+cpca_status prof_collect(cpca_handle h) {
+  if (!h->prof) return CPCA_OK;
+  for (size_t k = 0; k < h->ev_used; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
+    h->prof_n[h->ev_fam[k]] += 1;
+    h->prof_ms[h->ev_fam[k]] += ms;
+  }
+  h->ev_used = 0;
+  return CPCA_OK;
+}
+cpca_status sync_collect(cpca_handle h) {
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return prof_collect(h);
+}
+
+// ------------------------------------------------------------- preparation
+struct HostCsr {
+  int64_t n = 0, nnz = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+};
+
+cpca_status fetch_csr(const char* name, const cpca_csr* A, HostCsr& out) {
+  out.n = A->n;
+  out.nnz = A->nnz;
+  out.rp.resize((size_t)A->n + 1);
+  out.ci.resize((size_t)std::max<int64_t>(A->nnz, 1));
+  out.v.resize((size_t)std::max<int64_t>(A->nnz, 1));
+  HIPCHK(hipMemcpy(out.rp.data(), A->rowptr, sizeof(int32_t) * (A->n + 1), hipMemcpyDefault));
+  if (A->nnz > 0) {
+    HIPCHK(hipMemcpy(out.ci.data(), A->colind, sizeof(int32_t) * A->nnz, hipMemcpyDefault));
+    HIPCHK(hipMemcpy(out.v.data(), A->vals, sizeof(double) * A->nnz, hipMemcpyDefault));
+  }
+  return check_csr_host(name, out.n, out.nnz, out.rp.data(), out.ci.data(), out.v.data());
+}
+
+cpca_status fetch_index_set(const char* name, const int32_t* idx, int64_t count, int64_t dim,
+                            std::vector<uint8_t>& mask) {
+  std::vector<int32_t> h((size_t)std::max<int64_t>(count, 1));
+  if (count > 0) HIPCHK(hipMemcpy(h.data(), idx, sizeof(int32_t) * count, hipMemcpyDefault));
+  return check_index_set_host(name, count, dim, h.data(), &mask);
+}
+
+// Device image of one operator (L_r CSR, L_c SELL, masks) in type T, packed
+// into a single host staging buffer and copied with one transfer.
+template <typename T>
+struct DevGraph {
+  CsrDev<T> Lr{};
+  SellDev<T> Lc{};
+  const uint8_t* mr = nullptr;
+  const uint8_t* mc = nullptr;
+};
+
+struct Staging {
+  std::vector<char> buf;
+  size_t add(const void* src, size_t bytes) {
+    const size_t off = align_up(buf.size(), 256);
+    buf.resize(off + bytes);
+    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+    return off;
+  }
+};
+
+template <typename T>
+struct GraphImage {
+  size_t o_rp, o_ci, o_v, o_sp, o_sci, o_sv, o_mr, o_mc;
+};
+
+template <typename T>
+GraphImage<T> stage_graph(Staging& st, const HostCsr& Lr, const HostCsr& Lc,
+                          const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc) {
+  GraphImage<T> g{};
+  std::vector<T> vr(Lr.v.begin(), Lr.v.begin() + Lr.nnz);
+  g.o_rp = st.add(Lr.rp.data(), sizeof(int32_t) * Lr.rp.size());
+  g.o_ci = st.add(Lr.ci.data(), sizeof(int32_t) * std::max<int64_t>(Lr.nnz, 1));
+  g.o_v = st.add(vr.data(), sizeof(T) * vr.size());
+  // sliced ELL of L_c
+  const int64_t n = Lc.n;
+  const int64_t ns = (n + kSlice - 1) / kSlice;
+  std::vector<int32_t> sp((size_t)ns + 1, 0);
+  for (int64_t s = 0; s < ns; ++s) {
+    int w = 0;
+    for (int64_t j = s * kSlice; j < std::min<int64_t>(n, (s + 1) * kSlice); ++j)
+      w = std::max(w, Lc.rp[j + 1] - Lc.rp[j]);
+    sp[s + 1] = sp[s] + w * kSlice;
+  }
+  std::vector<int32_t> sci((size_t)std::max(sp[ns], 1));
+  std::vector<T> sv((size_t)std::max(sp[ns], 1), T(0));
+  for (int64_t s = 0; s < ns; ++s) {
+    const int w = (sp[s + 1] - sp[s]) / kSlice;
+    for (int lane = 0; lane < kSlice; ++lane) {
+      const int64_t j = s * kSlice + lane;
+      const int deg = j < n ? Lc.rp[j + 1] - Lc.rp[j] : 0;
+      for (int e = 0; e < w; ++e) {
+        const size_t pos = (size_t)sp[s] + (size_t)e * kSlice + lane;
+        if (e < deg) {
+          sci[pos] = Lc.ci[Lc.rp[j] + e];
+          sv[pos] = (T)Lc.v[Lc.rp[j] + e];
+        } else {
+          sci[pos] = j < n ? (int32_t)j : 0;
+          sv[pos] = T(0);
+        }
+      }
+    }
+  }
+  g.o_sp = st.add(sp.data(), sizeof(int32_t) * sp.size());
+  g.o_sci = st.add(sci.data(), sizeof(int32_t) * sci.size());
+  g.o_sv = st.add(sv.data(), sizeof(T) * sv.size());
+  g.o_mr = st.add(mr.data(), mr.size());
+  g.o_mc = st.add(mc.data(), mc.size());
+  return g;
+}
+
+template <typename T>
+DevGraph<T> bind_graph(const GraphImage<T>& g, const char* dev) {
+  DevGraph<T> d;
+  d.Lr.rp = reinterpret_cast<const int*>(dev + g.o_rp);
+  d.Lr.ci = reinterpret_cast<const int*>(dev + g.o_ci);
+  d.Lr.v = reinterpret_cast<const T*>(dev + g.o_v);
+  d.Lc.sp = reinterpret_cast<const int*>(dev + g.o_sp);
+  d.Lc.ci = reinterpret_cast<const int*>(dev + g.o_sci);
+  d.Lc.v = reinterpret_cast<const T*>(dev + g.o_sv);
+  d.mr = reinterpret_cast<const uint8_t*>(dev + g.o_mr);
+  d.mc = reinterpret_cast<const uint8_t*>(dev + g.o_mc);
+  return d;
+}
+
+// ------------------------------------------------------------------ launch
+struct ApplyCfg {
+  int R = 1;
+  bool lds = true;
+};
+
+ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem) {
+  ApplyCfg c;
+  const size_t row_bytes = (size_t)n * elem;
+  c.R = 1;
+  for (int R : {8, 4, 2}) {
+    if (R * row_bytes <= 32768 && (p + R - 1) / R >= 2048) {
+      c.R = R;
+      break;
+    }
+  }
+  if (h->force_R > 0) c.R = h->force_R;
+  c.lds = (size_t)c.R * row_bytes <= 65536;
+  if (h->force_lds == 0) c.lds = false;
+  if (h->force_lds == 1 && (size_t)c.R * row_bytes <= 65536) c.lds = true;
+  return c;
+}
+
+int vec_grid(size_t N) {
+  const size_t b = (N + kThreads - 1) / kThreads;
+  return (int)std::max<size_t>(1, std::min<size_t>(b, 2048));
+}
+
+template <typename T, int R, bool LDS, class Epi>
+hipError_t launch_apply_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
+                          const Epi& epi, RedSlot slot) {
+  const int nrb = (p + R - 1) / R;
+  const int per = (nrb + 7) / 8;
+  const size_t shmem = LDS ? (size_t)R * n * sizeof(T) : 0;
+  k_apply2<T, R, LDS, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
+      X, p, n, g.Lr, g.Lc, g.mr, g.mc, nrb, per, epi, slot);
+  return hipGetLastError();
+}
+
+template <typename T, class Epi>
+cpca_status launch_apply(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
+                         const DevGraph<T>& g, const Epi& epi, RedSlot slot, int fam) {
+  STCHK(prof_begin(h, fam));
+  hipError_t e;
+#define CPCA_CASE(RV)                                                             \
+  case RV:                                                                        \
+    e = cfg.lds ? launch_apply_t<T, RV, true>(h, X, p, n, g, epi, slot)           \
+                : launch_apply_t<T, RV, false>(h, X, p, n, g, epi, slot);         \
+    break;
+  switch (cfg.R) {
+    CPCA_CASE(1)
+    CPCA_CASE(2)
+    CPCA_CASE(4)
+    CPCA_CASE(8)
+    default:
+      return fail(CPCA_EINVAL, "unsupported rows per workgroup");
+  }
+#undef CPCA_CASE
+  if (e != hipSuccess) return fail(CPCA_EHIP, std::string("apply launch: ") + hipGetErrorString(e));
+  return prof_end(h);
+}
+
+int apply_grid(const ApplyCfg& cfg, int p) {
+  const int nrb = (p + cfg.R - 1) / cfg.R;
+  return 8 * ((nrb + 7) / 8);
+}
+
+#define LAUNCHCHK()                                                                        \
+  do {                                                                                     \
+    hipError_t _e = hipGetLastError();                                                     \
+    if (_e != hipSuccess) return fail(CPCA_EHIP, std::string("launch: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+// ---------------------------------------------------------------- CG core
+template <typename T>
+struct Operator {
+  int p = 0, n = 0;
+  DevGraph<T> g;
+  T gr = 0, gc = 0;
+  ApplyCfg cfg;
+};
+
+// Runs CG iterations on (x, r, p, q) whose state was initialised on the
+// device (cg scalars k). Returns the final done code via host_cg.
+template <typename T>
+cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, T* q,
+                       int max_iter, RedSlot slot) {
+  const size_t N = (size_t)op.p * op.n;
+  CgScal* sc = cg_ptr(h);
+  STCHK(read_fixed(h));
+  if (host_cg(h).done) return CPCA_OK;
+  int it = 0;
+  int chunk = 4;
+  const int vg = vec_grid(N / Vec16<T>::W + 1);
+  while (it < max_iter) {
+    const int m = std::min(chunk, max_iter - it);
+    for (int k = 0; k < m; ++k) {
+      EpiCg<T> epi{q, op.gr, op.gc, sc};
+      STCHK(launch_apply<T>(h, op.cfg, pv, op.p, op.n, op.g, epi, slot, FAM_APPLY));
+      STCHK(prof_begin(h, FAM_UPDATE));
+      k_cg_update<T><<<vg, kThreads, 0, h->stream>>>(x, r, pv, q, N, sc, slot);
+      LAUNCHCHK();
+      STCHK(prof_end(h));
+      k_cg_pupdate<T><<<vg, kThreads, 0, h->stream>>>(pv, r, N, sc);
+      LAUNCHCHK();
+    }
+    it += m;
+    STCHK(read_fixed(h));
+    STCHK(prof_collect(h));
+    if (host_cg(h).done) break;
+    chunk = std::min(chunk * 2, 64);
+  }
+  return CPCA_OK;
+}
+
+cpca_status done_status(int done) {
+  switch (done) {
+    case 1: return CPCA_OK;
+    case 2: return fail(CPCA_ENOTSPD, "CG breakdown: <p, A p> <= 0");
+    case 3: return fail(CPCA_ENAN, "NaN or Inf in the iteration");
+    default: return fail(CPCA_ENOCONV, "iteration limit reached before the tolerance");
+  }
+}
+
+void fill_info(cpca_info* info, cpca_status st, int iters, int outer, double rel, double obj,
+               std::chrono::steady_clock::time_point t0) {
+  if (!info) return;
+  info->iters = iters;
+  info->outer_iters = outer;
+  info->status = (int32_t)st;
+  info->reserved = 0;
+  info->rel_residual = rel;
+  info->objective = obj;
+  info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------- decode core
+// Problem preparation shared by decode, backward and apply.
+struct Prepared {
+  HostCsr Lr, Lc;
+  std::vector<uint8_t> mr, mc;
+};
+
+cpca_status prepare(cpca_handle h, const cpca_csr* Lr, const cpca_csr* Lc, const int32_t* om_r,
+                    int64_t rho_r, const int32_t* om_c, int64_t rho_c, int64_t p, int64_t n,
+                    Prepared& P) {
+  // inputs may still be in flight on the caller's stream
+  HIPCHK(hipStreamSynchronize(h->stream));
+  STCHK(fetch_csr("Lr", Lr, P.Lr));
+  STCHK(fetch_csr("Lc", Lc, P.Lc));
+  STCHK(fetch_index_set("omega_r", om_r, rho_r, p, P.mr));
+  STCHK(fetch_index_set("omega_c", om_c, rho_c, n, P.mc));
+  return CPCA_OK;
+}
+
+// Right-hand side: the scattered samples (decode) or a dense p x n matrix
+// (backward), in the mode's element type.
+struct Rhs {
+  const void* Xtil = nullptr;
+  const int32_t* om_r = nullptr;
+  const int32_t* om_c = nullptr;
+  int rho_r = 0, rho_c = 0;
+  const void* dense = nullptr;
+};
+
+struct SolveOut {
+  int iters = 0, outer = 0;
+  double rel = 0.0;
+  double bb = 0.0;
+  const double* x64 = nullptr;   // FP64 solution in the workspace
+  double* spare64 = nullptr;     // FP64 scratch of p*n (backward)
+  DevGraph<double> g64;          // FP64 operator image (backward dots)
+  ApplyCfg cfg64;
+  RedSlot slot{};
+};
+
+constexpr int kMaxOuter = 40;
+
+// Solves A(X) = B for the given mode. On return (OK or ENOCONV) the FP64
+// solution sits at so.x64 and, if `out` is given, the result is written to
+// it in the mode's element type.
+cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64_t p, int64_t n,
+                         double gr, double gc, double tol, int max_iter, const Rhs& rhs,
+                         const void* X0, void* out, bool want_spare, SolveOut& so) {
+  const size_t N = (size_t)p * n;
+  const bool f32 = mode != CPCA_FP64;
+  Staging stg;
+  const GraphImage<double> gi64 = stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc);
+  GraphImage<float> gi32{};
+  if (f32) gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc);
+  const ApplyCfg cfg64 = choose_cfg(h, p, n, sizeof(double));
+  const ApplyCfg cfg32 = choose_cfg(h, p, n, sizeof(float));
+  const int maxgrid = std::max({apply_grid(cfg64, (int)p), apply_grid(cfg32, (int)p), 2048});
+
+  char* img = nullptr;
+  double *part = nullptr, *B64 = nullptr, *X64 = nullptr, *r64 = nullptr, *p64 = nullptr,
+         *q64 = nullptr, *spare = nullptr;
+  float *B32 = nullptr, *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+  auto layout = [&](Arena& a) {
+    img = a.take<char>(stg.buf.size());
+    part = a.take<double>((size_t)maxgrid * 2);
+    B64 = a.take<double>(N);
+    X64 = a.take<double>(N);
+    if (mode == CPCA_FP64) {
+      r64 = a.take<double>(N);
+      p64 = a.take<double>(N);
+      q64 = a.take<double>(N);
+    } else {
+      if (mode == CPCA_FP32) B32 = a.take<float>(N);
+      x32 = a.take<float>(N);
+      r32 = a.take<float>(N);
+      p32 = a.take<float>(N);
+      q32 = a.take<float>(N);
+    }
+    spare = want_spare ? a.take<double>(N) : nullptr;
+  };
+  {
+    Arena a;
+    layout(a);
+    STCHK(ensure_ws(h, a.off));
+  }
+  Arena a;
+  a.base = h->ws;
+  layout(a);
+  HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
+  const DevGraph<double> g64 = bind_graph<double>(gi64, img);
+  DevGraph<float> g32{};
+  if (f32) g32 = bind_graph<float>(gi32, img);
+  RedSlot slot{part, counter_ptr(h)};
+  CgScal* sc = cg_ptr(h);
+  const int vg = vec_grid(N);
+  so.x64 = X64;
+  so.spare64 = spare;
+  so.g64 = g64;
+  so.cfg64 = cfg64;
+  so.slot = slot;
+
+  // B64 = right-hand side in FP64, bb = ||B||^2
+  if (rhs.dense) {
+    if (f32)
+      k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(B64, static_cast<const float*>(rhs.dense), N);
+    else
+      k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(B64, static_cast<const double*>(rhs.dense), N);
+    LAUNCHCHK();
+  } else {
+    k_fill<double><<<vg, kThreads, 0, h->stream>>>(B64, 0.0, N);
+    LAUNCHCHK();
+    const int sg = vec_grid((size_t)rhs.rho_r * rhs.rho_c);
+    if (f32)
+      k_scatter<float, double><<<sg, kThreads, 0, h->stream>>>(
+          B64, (int)n, static_cast<const float*>(rhs.Xtil), rhs.rho_r, rhs.rho_c, rhs.om_r, rhs.om_c);
+    else
+      k_scatter<double, double><<<sg, kThreads, 0, h->stream>>>(
+          B64, (int)n, static_cast<const double*>(rhs.Xtil), rhs.rho_r, rhs.rho_c, rhs.om_r, rhs.om_c);
+    LAUNCHCHK();
+  }
+  k_norm2<double><<<vg, kThreads, 0, h->stream>>>(B64, N, &sc->bb, slot);
+  LAUNCHCHK();
+  STCHK(read_fixed(h));
+  const double bb = host_cg(h).bb;
+  so.bb = bb;
+  if (!std::isfinite(bb)) return fail(CPCA_ENAN, "non-finite right-hand side");
+  if (bb == 0.0) {
+    // zero right-hand side: the (minimum-norm) solution is zero
+    k_fill<double><<<vg, kThreads, 0, h->stream>>>(X64, 0.0, N);
+    LAUNCHCHK();
+    if (out) {
+      if (f32) k_fill<float><<<vg, kThreads, 0, h->stream>>>(static_cast<float*>(out), 0.f, N);
+      else k_fill<double><<<vg, kThreads, 0, h->stream>>>(static_cast<double*>(out), 0.0, N);
+      LAUNCHCHK();
+    }
+    so.rel = 0.0;
+    STCHK(sync_collect(h));
+    return CPCA_OK;
+  }
+  const double thr = tol * tol * bb;
+  int done = 0;
+
+  if (mode == CPCA_FP64) {
+    Operator<double> op{(int)p, (int)n, g64, gr, gc, cfg64};
+    if (X0) {
+      k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(X64, static_cast<const double*>(X0), N);
+      LAUNCHCHK();
+      EpiResidual<double, double> epi{B64, r64, p64, nullptr, gr, gc, sc, thr, 0.0};
+      STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, slot, FAM_OTHER));
+    } else {
+      k_cg_init_zero<double><<<vg, kThreads, 0, h->stream>>>(X64, r64, p64, B64, N, sc, thr, slot);
+      LAUNCHCHK();
+    }
+    STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, slot));
+    so.iters = host_cg(h).iter;
+    done = host_cg(h).done;
+  } else if (mode == CPCA_FP32) {
+    Operator<float> op{(int)p, (int)n, g32, (float)gr, (float)gc, cfg32};
+    k_convert<double, float><<<vg, kThreads, 0, h->stream>>>(B32, B64, N);
+    LAUNCHCHK();
+    if (X0) {
+      k_convert<float, float><<<vg, kThreads, 0, h->stream>>>(x32, static_cast<const float*>(X0), N);
+      LAUNCHCHK();
+      EpiResidual<float, float> epi{B32, r32, p32, nullptr, (float)gr, (float)gc, sc, thr, 0.0};
+      STCHK(launch_apply<float>(h, cfg32, x32, op.p, op.n, g32, epi, slot, FAM_OTHER));
+    } else {
+      k_cg_init_zero<float><<<vg, kThreads, 0, h->stream>>>(x32, r32, p32, B32, N, sc, thr, slot);
+      LAUNCHCHK();
+    }
+    STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, slot));
+    so.iters = host_cg(h).iter;
+    done = host_cg(h).done;
+    k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
+    LAUNCHCHK();
+  } else {
+    // FP32 inner CG inside FP64 iterative refinement
+    Operator<float> op{(int)p, (int)n, g32, (float)gr, (float)gc, cfg32};
+    if (X0)
+      k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, static_cast<const float*>(X0), N);
+    else
+      k_fill<double><<<vg, kThreads, 0, h->stream>>>(X64, 0.0, N);
+    LAUNCHCHK();
+    double rel_prev = 1.0;
+    int total = 0;
+    done = 0;
+    for (int outer = 0;; ++outer) {
+      const double inner_tol = std::min(0.25, std::max(1e-5, 0.5 * tol / rel_prev));
+      EpiResidual<double, float> epi{B64, r32, p32, x32, gr, gc, sc, -1.0, inner_tol * inner_tol};
+      STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, slot, FAM_OTHER));
+      STCHK(read_fixed(h));
+      const CgScal cs = host_cg(h);
+      if (cs.done == 3 || !std::isfinite(cs.res2)) {
+        done = 3;
+        break;
+      }
+      const double rel = std::sqrt(cs.res2 / bb);
+      so.outer = outer;
+      if (rel <= tol) {
+        done = 1;
+        break;
+      }
+      if (outer >= kMaxOuter) {
+        done = 0;
+        break;
+      }
+      STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, slot));
+      const CgScal ci = host_cg(h);
+      total += ci.iter;
+      if (ci.done == 2 || ci.done == 3) {
+        done = ci.done;
+        break;
+      }
+      k_accumulate<float><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
+      LAUNCHCHK();
+      rel_prev = rel;
+    }
+    so.iters = total;
+  }
+
+  // FP64 residual of the FP64 solution
+  {
+    double* res = results_ptr(h) + 1;
+    EpiResNorm<double> epi{B64, gr, gc, res};
+    STCHK(launch_apply<double>(h, cfg64, X64, (int)p, (int)n, g64, epi, slot, FAM_OTHER));
+  }
+  if (out) {
+    if (f32)
+      k_convert<double, float><<<vg, kThreads, 0, h->stream>>>(static_cast<float*>(out), X64, N);
+    else
+      k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(static_cast<double*>(out), X64, N);
+    LAUNCHCHK();
+  }
+  STCHK(read_fixed(h));
+  STCHK(prof_collect(h));
+  so.rel = std::sqrt(host_results(h)[1] / bb);
+  return done_status(done);
+}
+
+cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t rho_r,
+                       int64_t rho_c, const cpca_csr* Lr_t, const cpca_csr* Lc_t, double gr,
+                       double gc, double lmax_r, double lmax_c, int max_iter, double eps,
+                       void* out, int* iters, double* objective, double* last_ratio) {
+  HostCsr Lr, Lc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  STCHK(fetch_csr("Lr_til", Lr_t, Lr));
+  STCHK(fetch_csr("Lc_til", Lc_t, Lc));
+  const size_t N = (size_t)rho_r * rho_c;
+  std::vector<uint8_t> mr((size_t)rho_r, 0), mc((size_t)rho_c, 0);
+  Staging stg;
+  const GraphImage<double> gi = stage_graph<double>(stg, Lr, Lc, mr, mc);
+  const ApplyCfg cfg = choose_cfg(h, rho_r, rho_c, sizeof(double));
+  const int maxgrid = std::max(apply_grid(cfg, (int)rho_r), 2048);
+  char* img = nullptr;
+  double *part = nullptr, *Y = nullptr, *S = nullptr, *Za = nullptr, *Zb = nullptr;
+  auto layout = [&](Arena& a) {
+    img = a.take<char>(stg.buf.size());
+    part = a.take<double>((size_t)maxgrid * 2);
+    Y = a.take<double>(N);
+    S = a.take<double>(N);
+    Za = a.take<double>(N);
+    Zb = a.take<double>(N);
+  };
+  {
+    Arena a;
+    layout(a);
+    STCHK(ensure_ws(h, a.off));
+  }
+  Arena a;
+  a.base = h->ws;
+  layout(a);
+  HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
+  const DevGraph<double> g = bind_graph<double>(gi, img);
+  RedSlot slot{part, counter_ptr(h)};
+  FistaScal* fs = fista_ptr(h);
+  const int vg = vec_grid(N);
+  const bool f32 = mode != CPCA_FP64;
+  if (f32)
+    k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(Y, static_cast<const float*>(Ytil), N);
+  else
+    k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(Y, static_cast<const double*>(Ytil), N);
+  LAUNCHCHK();
+  k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(S, Y, N);
+  LAUNCHCHK();
+  k_fill<int><<<1, kThreads, 0, h->stream>>>(reinterpret_cast<int*>(fs), 0,
+                                             sizeof(FistaScal) / sizeof(int));
+  LAUNCHCHK();
+  const double beta = 2.0 * gc * lmax_c + 2.0 * gr * lmax_r;
+  int ran = 0;
+  int done = 0;
+  if (beta > 0.0 && max_iter > 0) {
+    const double lam = 1.0 / beta;
+    k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(Za, Y, N);
+    LAUNCHCHK();
+    double t = 1.0;
+    const bool reduce = eps > 0.0;
+    int since_check = 0, check = 8;
+    for (int j = 1; j <= max_iter; ++j) {
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      const double c = (t - 1.0) / tn;
+      if (reduce) {
+        EpiFista<true> epi{Y, S, Zb, 2.0 * gr, 2.0 * gc, lam, c, eps, fs};
+        STCHK(launch_apply<double>(h, cfg, Za, (int)rho_r, (int)rho_c, g, epi, slot, FAM_FISTA));
+      } else {
+        EpiFista<false> epi{Y, S, Zb, 2.0 * gr, 2.0 * gc, lam, c, 0.0, fs};
+        STCHK(launch_apply<double>(h, cfg, Za, (int)rho_r, (int)rho_c, g, epi, slot, FAM_FISTA));
+      }
+      std::swap(Za, Zb);
+      t = tn;
+      ran = j;
+      if (reduce && ++since_check >= check) {
+        since_check = 0;
+        check = std::min(check * 2, 64);
+        STCHK(read_fixed(h));
+        STCHK(prof_collect(h));
+        if (host_fista(h).done) break;
+      }
+    }
+  }
+  // objective at S
+  {
+    EpiObjective epi{Y, gr, gc, fs};
+    STCHK(launch_apply<double>(h, cfg, S, (int)rho_r, (int)rho_c, g, epi, slot, FAM_OTHER));
+  }
+  if (f32)
+    k_convert<double, float><<<vg, kThreads, 0, h->stream>>>(static_cast<float*>(out), S, N);
+  else
+    k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(static_cast<double*>(out), S, N);
+  LAUNCHCHK();
+  STCHK(read_fixed(h));
+  STCHK(prof_collect(h));
+  const FistaScal fh = host_fista(h);
+  done = fh.done;
+  if (iters) *iters = (eps > 0.0 && beta > 0.0) ? fh.iter : ran;
+  if (objective) *objective = fh.obj_l1 + fh.obj_g;
+  if (last_ratio) *last_ratio = fh.z2 > 0 ? fh.dz2 / fh.z2 : 0.0;
+  if (done == 3 || !std::isfinite(fh.obj_l1 + fh.obj_g)) return fail(CPCA_ENAN, "NaN or Inf in FISTA");
+  return CPCA_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
+  clear_error();
+  if (!out) return fail(CPCA_EINVAL, "null handle pointer");
+  *out = nullptr;
+  cpca_handle h = new (std::nothrow) cpca_handle_s();
+  if (!h) return fail(CPCA_ENOMEM, "host allocation failed");
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->fixed), kFixedBytes);
+  if (e == hipSuccess) e = hipMemset(h->fixed, 0, kFixedBytes);
+  if (e == hipSuccess) e = hipHostMalloc(&h->pinned, kFixedBytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (h->fixed) (void)hipFree(h->fixed);
+    delete h;
+    return fail(e == hipErrorOutOfMemory ? CPCA_ENOMEM : CPCA_EHIP,
+                std::string("cpca_create: ") + hipGetErrorString(e));
+  }
+  h->stream = static_cast<hipStream_t>(stream);
+  if (const char* s = std::getenv("CPCA_APPLY_R")) h->force_R = std::atoi(s);
+  if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
+  *out = h;
+  return CPCA_OK;
+}
+
+extern "C" cpca_status cpca_destroy(cpca_handle h) {
+  clear_error();
+  if (!h) return CPCA_OK;
+  (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->fixed) (void)hipFree(h->fixed);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return CPCA_OK;
+}
+
+extern "C" cpca_status cpca_set_stream(cpca_handle h, void* stream) {
+  clear_error();
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->stream = static_cast<hipStream_t>(stream);
+  return CPCA_OK;
+}
+
+extern "C" cpca_status cpca_set_profiling(cpca_handle h, int32_t enable) {
+  clear_error();
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  STCHK(prof_collect(h));
+  h->prof = enable != 0;
+  for (int k = 0; k < FAM_COUNT; ++k) {
+    h->prof_n[k] = 0;
+    h->prof_ms[k] = 0;
+  }
+  return CPCA_OK;
+}
+
+extern "C" cpca_status cpca_get_profile(cpca_handle h, const char* family, int64_t* launches,
+                                        double* total_ms) {
+  clear_error();
+  if (!h || !family) return fail(CPCA_EINVAL, "null argument");
+  int k = -1;
+  if (!std::strcmp(family, "apply")) k = FAM_APPLY;
+  if (!std::strcmp(family, "update")) k = FAM_UPDATE;
+  if (!std::strcmp(family, "fista")) k = FAM_FISTA;
+  if (!std::strcmp(family, "other")) k = FAM_OTHER;
+  if (k < 0) return fail(CPCA_EINVAL, "unknown kernel family");
+  if (launches) *launches = h->prof_n[k];
+  if (total_ms) *total_ms = h->prof_ms[k];
+  return CPCA_OK;
+}
+
+extern "C" cpca_status cpca_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t rho_r,
+                                   int64_t rho_c, const cpca_csr* Lr_til, const cpca_csr* Lc_til,
+                                   double gamma_r, double gamma_c, double lmax_r, double lmax_c,
+                                   int32_t max_iter, double eps, void* Xtil_out, cpca_info* info) {
+  clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  STCHK(check_frpcag_args(mode, Ytil, rho_r, rho_c, Lr_til, Lc_til, gamma_r, gamma_c, lmax_r,
+                          lmax_c, max_iter, eps, Xtil_out));
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  int iters = 0;
+  double obj = 0.0, ratio = 0.0;
+  const cpca_status st = run_frpcag(h, mode, Ytil, rho_r, rho_c, Lr_til, Lc_til, gamma_r, gamma_c,
+                                    lmax_r, lmax_c, max_iter, eps, Xtil_out, &iters, &obj, &ratio);
+  fill_info(info, st, iters, 0, ratio, obj, t0);
+  return st;
+}
+
+extern "C" cpca_status cpca_decode(cpca_handle h, cpca_mode mode, const void* Xtil, int64_t rho_r,
+                                   int64_t rho_c, const int32_t* omega_r, const int32_t* omega_c,
+                                   int64_t p, int64_t n, const cpca_csr* Lr, const cpca_csr* Lc,
+                                   double gamma_r, double gamma_c, double tol, int32_t max_iter,
+                                   const void* X0, void* X_out, cpca_info* info) {
+  clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  STCHK(check_decode_args(mode, rho_r, rho_c, omega_r, omega_c, p, n, Lr, Lc, gamma_r, gamma_c,
+                          tol, max_iter));
+  if (!Xtil || !X_out) return fail(CPCA_EINVAL, "decode: null data pointer");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  Prepared P;
+  STCHK(prepare(h, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n, P));
+  Rhs rhs;
+  rhs.Xtil = Xtil;
+  rhs.om_r = omega_r;
+  rhs.om_c = omega_c;
+  rhs.rho_r = (int)rho_r;
+  rhs.rho_c = (int)rho_c;
+  SolveOut so;
+  const cpca_status st =
+      solve_decode(h, mode, P, p, n, gamma_r, gamma_c, tol, max_iter, rhs, X0, X_out, false, so);
+  fill_info(info, st, so.iters, so.outer, so.rel, 0.0, t0);
+  return st;
+}
+
+extern "C" cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode, const void* G,
+                                            const void* X, int64_t rho_r, int64_t rho_c,
+                                            const int32_t* omega_r, const int32_t* omega_c,
+                                            int64_t p, int64_t n, const cpca_csr* Lr,
+                                            const cpca_csr* Lc, double gamma_r, double gamma_c,
+                                            double tol, int32_t max_iter, void* dXtil_out,
+                                            double* dgamma_r, double* dgamma_c, cpca_info* info) {
+  clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  STCHK(check_decode_args(mode, rho_r, rho_c, omega_r, omega_c, p, n, Lr, Lc, gamma_r, gamma_c,
+                          tol, max_iter));
+  if (!G || !X || !dXtil_out || !dgamma_r || !dgamma_c)
+    return fail(CPCA_EINVAL, "decode_backward: null pointer");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  Prepared P;
+  STCHK(prepare(h, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n, P));
+  Rhs rhs;
+  rhs.dense = G;
+  SolveOut so;
+  const bool f32 = mode != CPCA_FP64;
+  cpca_status st =
+      solve_decode(h, mode, P, p, n, gamma_r, gamma_c, tol, max_iter, rhs, nullptr, nullptr, f32, so);
+  if (st != CPCA_OK && st != CPCA_ENOCONV) {
+    fill_info(info, st, so.iters, so.outer, so.rel, 0.0, t0);
+    return st;
+  }
+  const size_t N = (size_t)p * n;
+  const size_t ns = (size_t)rho_r * rho_c;
+  const int vg = vec_grid(N);
+  // dXtil = Lambda[Omega_r, Omega_c]
+  if (f32)
+    k_gather<double, float><<<vec_grid(ns), kThreads, 0, h->stream>>>(
+        static_cast<float*>(dXtil_out), so.x64, (int)n, (int)rho_r, (int)rho_c, omega_r, omega_c);
+  else
+    k_gather<double, double><<<vec_grid(ns), kThreads, 0, h->stream>>>(
+        static_cast<double*>(dXtil_out), so.x64, (int)n, (int)rho_r, (int)rho_c, omega_r, omega_c);
+  LAUNCHCHK();
+  // <Lambda, L_r X> and <Lambda, X L_c> in FP64
+  const double* X64 = static_cast<const double*>(X);
+  if (f32) {
+    k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(so.spare64, static_cast<const float*>(X), N);
+    LAUNCHCHK();
+    X64 = so.spare64;
+  }
+  double* dots = results_ptr(h) + 2;
+  EpiDot2<double> epi{so.x64, dots};
+  STCHK(launch_apply<double>(h, so.cfg64, X64, (int)p, (int)n, so.g64, epi, so.slot, FAM_OTHER));
+  STCHK(read_fixed(h));
+  STCHK(prof_collect(h));
+  *dgamma_r = -host_results(h)[2];
+  *dgamma_c = -host_results(h)[3];
+  fill_info(info, st, so.iters, so.outer, so.rel, 0.0, t0);
+  return st;
+}
+
+namespace {
+template <typename T>
+cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_t p, int64_t n,
+                      double gr, double gc, double* pq) {
+  Staging stg;
+  const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc);
+  const ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T));
+  char* img = nullptr;
+  double* part = nullptr;
+  auto layout = [&](Arena& a) {
+    img = a.take<char>(stg.buf.size());
+    part = a.take<double>((size_t)apply_grid(cfg, (int)p) * 2);
+  };
+  {
+    Arena a;
+    layout(a);
+    STCHK(ensure_ws(h, a.off));
+  }
+  Arena a;
+  a.base = h->ws;
+  layout(a);
+  HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
+  const DevGraph<T> g = bind_graph<T>(gi, img);
+  RedSlot slot{part, counter_ptr(h)};
+  EpiApply<T> epi{Q, (T)gr, (T)gc, results_ptr(h) + 4};
+  STCHK(launch_apply<T>(h, cfg, X, (int)p, (int)n, g, epi, slot, FAM_OTHER));
+  STCHK(read_fixed(h));
+  STCHK(prof_collect(h));
+  if (pq) *pq = host_results(h)[4];
+  return CPCA_OK;
+}
+}  // namespace
+
+extern "C" cpca_status cpca_apply(cpca_handle h, cpca_mode mode, const void* P, void* Q, int64_t p,
+                                  int64_t n, const int32_t* omega_r, int64_t rho_r,
+                                  const int32_t* omega_c, int64_t rho_c, const cpca_csr* Lr,
+                                  const cpca_csr* Lc, double gamma_r, double gamma_c, double* pq) {
+  clear_error();
+  STCHK(check_mode(mode));
+  STCHK(check_dims("P", p, n));
+  if (!P || !Q) return fail(CPCA_EINVAL, "apply: null data pointer");
+  if (rho_r < 0 || rho_c < 0 || rho_r > p || rho_c > n)
+    return fail(CPCA_EINVAL, "apply: sample counts out of range");
+  if ((rho_r > 0 && !omega_r) || (rho_c > 0 && !omega_c))
+    return fail(CPCA_EINVAL, "apply: null index set");
+  STCHK(check_csr_shape("Lr", Lr, p));
+  STCHK(check_csr_shape("Lc", Lc, n));
+  STCHK(check_gamma("gamma_r", gamma_r));
+  STCHK(check_gamma("gamma_c", gamma_c));
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  Prepared Pp;
+  STCHK(prepare(h, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n, Pp));
+  if (mode == CPCA_FP64)
+    return run_apply<double>(h, Pp, static_cast<const double*>(P), static_cast<double*>(Q), p, n,
+                             gamma_r, gamma_c, pq);
+  return run_apply<float>(h, Pp, static_cast<const float*>(P), static_cast<float*>(Q), p, n,
+                          gamma_r, gamma_c, pq);
+}
+
+extern "C" cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_block, int32_t use_lds) {
+  clear_error();
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  if (!(rows_per_block == 0 || rows_per_block == 1 || rows_per_block == 2 || rows_per_block == 4 ||
+        rows_per_block == 8))
+    return fail(CPCA_EINVAL, "rows_per_block must be 0, 1, 2, 4 or 8");
+  if (use_lds < -1 || use_lds > 1) return fail(CPCA_EINVAL, "use_lds must be -1, 0 or 1");
+  h->force_R = rows_per_block;
+  h->force_lds = use_lds;
+  return CPCA_OK;
+}

@@ -1,0 +1,123 @@
+"""C-ABI checks that run without a GPU: the library loads, exports every
+function include/cpca.h declares, and rejects bad arguments on the host
+before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1602_02070_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1602_02070_amd import _build
+        _build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "cpca.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpca_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_version(lib):
+    assert re.match(rb"^\d+\.\d+\.\d+$", lib.cpca_version())
+
+
+def _a(x, dt):
+    return np.ascontiguousarray(x, dtype=dt)
+
+
+def test_check_csr_host(lib):
+    rp, ci, v = _a([0, 2, 3, 5], np.int32), _a([0, 1, 1, 0, 2], np.int32), _a([2, -1, 1, -1, 1.], np.float64)
+    ok = lib.cpca_check_csr_host(3, 5, rp.ctypes.data, ci.ctypes.data, v.ctypes.data)
+    assert ok == _lib.OK and _lib.last_error() == ""
+    bad_idx = _a([0, 1, 3, 0, 2], np.int32)
+    assert lib.cpca_check_csr_host(3, 5, rp.ctypes.data, bad_idx.ctypes.data, v.ctypes.data) == _lib.EINVAL
+    assert "column index 3" in _lib.last_error()
+    dec = _a([0, 2, 1, 5], np.int32)
+    assert lib.cpca_check_csr_host(3, 5, dec.ctypes.data, ci.ctypes.data, v.ctypes.data) == _lib.EINVAL
+    assert "decreases" in _lib.last_error()
+    end = _a([0, 2, 3, 4], np.int32)
+    assert lib.cpca_check_csr_host(3, 5, end.ctypes.data, ci.ctypes.data, v.ctypes.data) == _lib.EINVAL
+    nan = _a([2, np.nan, 1, -1, 1.], np.float64)
+    assert lib.cpca_check_csr_host(3, 5, rp.ctypes.data, ci.ctypes.data, nan.ctypes.data) == _lib.EINVAL
+    assert "non-finite" in _lib.last_error()
+    assert lib.cpca_check_csr_host(0, 0, rp.ctypes.data, ci.ctypes.data, v.ctypes.data) == _lib.EINVAL
+    # empty rows are structurally valid
+    rp2 = _a([0, 0, 1, 1], np.int32)
+    assert lib.cpca_check_csr_host(3, 1, rp2.ctypes.data, _a([2], np.int32).ctypes.data, None) == _lib.OK
+
+
+def test_check_index_set_host(lib):
+    ok = _a([4, 0, 2], np.int32)
+    assert lib.cpca_check_index_set_host(3, 5, ok.ctypes.data) == _lib.OK
+    dup = _a([4, 0, 4], np.int32)
+    assert lib.cpca_check_index_set_host(3, 5, dup.ctypes.data) == _lib.EINVAL
+    assert "repeated" in _lib.last_error()
+    oob = _a([4, 5], np.int32)
+    assert lib.cpca_check_index_set_host(2, 5, oob.ctypes.data) == _lib.EINVAL
+    neg = _a([-1], np.int32)
+    assert lib.cpca_check_index_set_host(1, 5, neg.ctypes.data) == _lib.EINVAL
+    assert lib.cpca_check_index_set_host(6, 5, ok.ctypes.data) == _lib.EINVAL
+    assert lib.cpca_check_index_set_host(0, 5, None) == _lib.OK
+
+
+def _csr(n, nnz=1):
+    # descriptor with non-null (host, never dereferenced) pointers
+    buf = (ctypes.c_int32 * 8)()
+    vals = (ctypes.c_double * 8)()
+    return _lib.CpcaCsr(n, nnz, ctypes.addressof(buf), ctypes.addressof(buf),
+                        ctypes.addressof(vals)), (buf, vals)
+
+
+def test_entry_points_reject_bad_scalars_before_device_work(lib):
+    info = _lib.CpcaInfo()
+    dummy = ctypes.c_void_p(16)
+    Lr, k1 = _csr(10)
+    Lc, k2 = _csr(20)
+    args_ok = dict(mode=0, rho_r=5, rho_c=6, p=10, n=20, gr=1.0, gc=1.0, tol=1e-8, it=100)
+
+    def dec(**kw):
+        a = dict(args_ok, **kw)
+        return lib.cpca_decode(None, a["mode"], dummy, a["rho_r"], a["rho_c"], dummy, dummy,
+                               a["p"], a["n"], ctypes.byref(Lr), ctypes.byref(Lc), a["gr"],
+                               a["gc"], a["tol"], a["it"], None, dummy, ctypes.byref(info))
+
+    cases = [(dict(mode=7), "mode"), (dict(p=0), "size"), (dict(rho_r=11), "samples"),
+             (dict(gr=-1.0), "gamma_r"), (dict(gc=float("nan")), "gamma_c"),
+             (dict(tol=0.0), "tol"), (dict(it=0), "max_iter"), (dict(n=21), "Lc")]
+    for kw, word in cases:
+        assert dec(**kw) == _lib.EINVAL, kw
+        assert word in _lib.last_error(), (kw, _lib.last_error())
+    # every check passes: the null handle is the remaining problem
+    assert dec() == _lib.EINVAL and "null handle" in _lib.last_error()
+
+    def fr(**kw):
+        a = dict(dict(rr=10, rc=20, gr=1.0, gc=1.0, lr=1.5, lc=1.5, it=10, eps=0.0), **kw)
+        return lib.cpca_frpcag(None, 0, dummy, a["rr"], a["rc"], ctypes.byref(Lr), ctypes.byref(Lc),
+                               a["gr"], a["gc"], a["lr"], a["lc"], a["it"], a["eps"], dummy,
+                               ctypes.byref(info))
+
+    for kw, word in [(dict(lr=0.0), "lmax"), (dict(it=-1), "max_iter"), (dict(eps=-1.0), "eps"),
+                     (dict(rr=11), "Lr_til"), (dict(gc=float("inf")), "gamma_c")]:
+        assert fr(**kw) == _lib.EINVAL, kw
+        assert word in _lib.last_error(), (kw, _lib.last_error())
+    assert fr(gr=0.0, lr=0.0) == _lib.EINVAL and "null handle" in _lib.last_error()
+    assert lib.cpca_create(None, None) == _lib.EINVAL
+    assert lib.cpca_destroy(None) == _lib.OK

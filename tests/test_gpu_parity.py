@@ -1,0 +1,314 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Sizes are chosen so the oracle finishes in seconds while the GPU launches
+still span several row blocks, several 64-column SELL slices and ragged
+tails in both dimensions."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import paper_1602_02070_amd as cp
+import synth
+from oracle import decoder as OD
+from oracle import frpcag as OF
+from tests.gpu_util import dev_problem, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.cfg1_tiny(0)
+
+
+def _rand_sym_csr(n, rng, deg_lo=0, deg_hi=30, empty_frac=0.1):
+    """Random symmetric sparse matrix with skewed degrees and empty rows."""
+    rows, cols = [], []
+    for i in range(n):
+        if rng.random() < empty_frac:
+            continue
+        d = int(min(n - 1, rng.integers(deg_lo, deg_hi) * (1 + 5 * (rng.random() < 0.05))))
+        nb = rng.choice(n, size=d, replace=False)
+        rows += [i] * d
+        cols += list(nb)
+    A = sp.coo_matrix((rng.standard_normal(len(rows)), (rows, cols)), shape=(n, n)).tocsr()
+    A = (A + A.T).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+APPLY_SHAPES = [(1, 1), (7, 70), (63, 129), (130, 257), (300, 513), (1000, 64), (64, 1100)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", APPLY_SHAPES)
+def test_apply_matches_oracle_random_graphs(shape, dtype):
+    p, n = shape
+    _announce(f"apply {p}x{n} {dtype}")
+    rng = np.random.default_rng(p * 1000 + n)
+    Lr = _rand_sym_csr(p, rng)
+    Lc = _rand_sym_csr(n, rng)
+    om_r = np.sort(rng.choice(p, size=max(1, p // 3), replace=False)).astype(np.int32)
+    om_c = np.sort(rng.choice(n, size=max(1, n // 4), replace=False)).astype(np.int32)
+    P = rng.standard_normal((p, n))
+    gr, gc = 0.7, 1.9
+    m_r, m_c = OD.masks(p, n, om_r, om_c)
+    Q_ref = OD.apply_A(P, m_r, m_c, Lr, Lc, gr, gc)
+    Pt = torch.from_numpy(P).to(dtype).cuda()
+    Q, pq = cp.apply_operator(Pt, cp.Graph.from_scipy(Lr), cp.Graph.from_scipy(Lc), gr, gc,
+                              torch.from_numpy(om_r).cuda(), torch.from_numpy(om_c).cuda())
+    Qh = host(Q)
+    scale = np.abs(Q_ref).max() + 1e-30
+    tol = 1e-13 if dtype == torch.float64 else 3e-6
+    assert np.abs(Qh - Q_ref).max() <= tol * scale * 10
+    Ph = host(Pt)
+    assert np.isclose(pq, np.sum(Ph * OD.apply_A(Ph, m_r, m_c, Lr, Lc, gr, gc)),
+                      rtol=1e-12 if dtype == torch.float64 else 1e-5)
+
+
+@pytest.mark.parametrize("R,lds", [(1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (4, 0)])
+def test_apply_every_launch_shape(R, lds):
+    _announce(f"apply launch shape R={R} lds={lds}")
+    P_ = synth.small_problem(3, p_shape=(11, 13), n=333, rank=3, frac=0.3)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((P_.p, P_.n))
+    m_r, m_c = OD.masks(P_.p, P_.n, P_.omega_r, P_.omega_c)
+    ref = OD.apply_A(X, m_r, m_c, P_.Lr, P_.Lc, 1.3, 0.4)
+    d = dev_problem(P_)
+    cp.set_apply_config(R, lds)
+    try:
+        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+            Q, _ = cp.apply_operator(torch.from_numpy(X).to(dtype).cuda(), d["Lr"], d["Lc"], 1.3,
+                                     0.4, d["om_r"], d["om_c"])
+            assert np.abs(host(Q) - ref).max() <= tol * np.abs(ref).max() * 10
+    finally:
+        cp.set_apply_config(0, -1)
+
+
+def test_fista_trajectory_matches_oracle(cfg1):
+    P = cfg1
+    d = dev_problem(P)
+    args = (P.Lr_til, P.Lc_til, P.gamma_r, P.gamma_c, P.lmax_r_til, P.lmax_c_til)
+    rec = {j: None for j in (1, 2, 10, 100, 500)}
+    OF.fista(P.Ytil, *args, 500, record=rec)
+    for J in rec:
+        _announce(f"fista cfg1 J={J}")
+        X, info = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], P.gamma_r, P.gamma_c,
+                            P.lmax_r_til, P.lmax_c_til, max_iter=J)
+        assert info["iters"] == J
+        assert rel(host(X), rec[J]) <= 1e-11
+        assert np.isclose(info["objective"],
+                          OF.objective(rec[J], P.Ytil, P.Lr_til, P.Lc_til, P.gamma_r, P.gamma_c),
+                          rtol=1e-11)
+
+
+@pytest.mark.parametrize("seed,shape,n,gam", [(1, (12, 10), 150, (1.0, 1.0)),
+                                              (2, (9, 23), 333, (10.0, 0.1)),
+                                              (3, (40, 30), 90, (0.5, 3.0))])
+def test_fista_parity_small_problems(seed, shape, n, gam):
+    P = synth.small_problem(seed, p_shape=shape, n=n, frac=0.5, gamma=gam, fista_iters=200)
+    _announce(f"fista small seed={seed} {P.rho_r}x{P.rho_c}")
+    d = dev_problem(P)
+    ref, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, *gam, P.lmax_r_til, P.lmax_c_til, 200)
+    X, _ = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], *gam, P.lmax_r_til, P.lmax_c_til, 200)
+    assert rel(host(X), ref) <= 1e-11
+    # FP32 input/output, FP64 state
+    X32, _ = cp.frpcag(d["Ytil"].float(), d["Lr_til"], d["Lc_til"], *gam, P.lmax_r_til,
+                       P.lmax_c_til, 200)
+    ref32, _ = OF.fista(P.Ytil.astype(np.float32).astype(np.float64), P.Lr_til, P.Lc_til, *gam,
+                        P.lmax_r_til, P.lmax_c_til, 200)
+    assert rel(host(X32), ref32) <= 1e-6
+
+
+def test_fista_eps_stopping_matches_oracle(cfg1):
+    P = cfg1
+    d = dev_problem(P)
+    for eps in (1e-4, 1e-6):
+        _announce(f"fista eps={eps}")
+        ref, it = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, 1.0, 1.0, P.lmax_r_til, P.lmax_c_til,
+                           2000, eps=eps)
+        X, info = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], 1.0, 1.0, P.lmax_r_til,
+                            P.lmax_c_til, max_iter=2000, eps=eps)
+        assert info["iters"] == it
+        assert rel(host(X), ref) <= 1e-11
+
+
+def test_fista_gamma_zero_returns_Y(cfg1):
+    d = dev_problem(cfg1)
+    X, info = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], 0.0, 0.0, 0.0, 0.0, max_iter=50)
+    assert torch.equal(X, d["Ytil"]) and info["iters"] == 0
+
+
+def _decode_ref(P, Xtil, gr, gc):
+    return OD.decode(Xtil, P.p, P.n, P.omega_r, P.omega_c, P.Lr, P.Lc, gr, gc)
+
+
+def test_decode_cfg1_all_modes(cfg1):
+    P = cfg1
+    d = dev_problem(P)
+    Xtil, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, 1.0, 1.0, P.lmax_r_til, P.lmax_c_til, 500)
+    ref = _decode_ref(P, Xtil, 1.0, 1.0)
+    Xt = torch.from_numpy(Xtil).cuda()
+    _announce("decode cfg1 fp64")
+    X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0, tol=1e-12)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-11
+    assert rel(host(X), ref) <= 1e-9
+    _announce("decode cfg1 fp32_ir")
+    X, info = cp.decode(Xt.float(), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                        tol=1e-10, mode="fp32_ir")
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+    ref32 = _decode_ref(P, Xtil.astype(np.float32).astype(np.float64), 1.0, 1.0)
+    assert rel(host(X), ref32) <= 1e-5
+    _announce("decode cfg1 fp32")
+    X, info = cp.decode(Xt.float(), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                        tol=1e-5, mode="fp32")
+    assert info["status"] == 0
+    assert rel(host(X), ref32) <= 1e-3
+
+
+@pytest.mark.parametrize("seed,shape,n,gam,frac", [
+    (4, (12, 10), 150, (1.0, 1.0), 0.3),
+    (5, (7, 19), 257, (10.0, 0.1), 0.2),
+    (6, (33, 20), 65, (0.1, 10.0), 0.4),
+    (7, (10, 10), 300, (100.0, 100.0), 0.25),
+])
+def test_decode_parity_small(seed, shape, n, gam, frac):
+    P = synth.small_problem(seed, p_shape=shape, n=n, frac=frac, gamma=gam)
+    _announce(f"decode small seed={seed} p={P.p} n={P.n} gamma={gam}")
+    d = dev_problem(P)
+    rng = np.random.default_rng(seed)
+    Xtil = P.Ytil + 0.1 * rng.standard_normal(P.Ytil.shape)
+    ref = _decode_ref(P, Xtil, *gam)
+    Xt = torch.from_numpy(Xtil).cuda()
+    X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], *gam, tol=1e-13)
+    assert info["status"] == 0
+    assert rel(host(X), ref) <= 1e-8
+    X32, info = cp.decode(Xt.float(), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], *gam,
+                          tol=1e-11, mode="fp32_ir")
+    assert info["status"] == 0
+    ref32 = _decode_ref(P, Xtil.astype(np.float32).astype(np.float64), *gam)
+    assert rel(host(X32), ref32) <= 1e-5
+
+
+def test_decode_warm_start_and_zero_rhs(cfg1):
+    P = cfg1
+    d = dev_problem(P)
+    rng = np.random.default_rng(1)
+    Xtil = rng.standard_normal((P.rho_r, P.rho_c))
+    ref = _decode_ref(P, Xtil, 1.0, 1.0)
+    Xt = torch.from_numpy(Xtil).cuda()
+    X0 = torch.from_numpy(ref + 1e-3 * rng.standard_normal(ref.shape)).cuda()
+    _announce("decode warm start fp64")
+    X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                        tol=1e-12, X0=X0)
+    assert rel(host(X), ref) <= 1e-9
+    X, info2 = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0, tol=1e-12)
+    assert info["iters"] < info2["iters"]
+    _announce("decode warm start fp32_ir")
+    X, info = cp.decode(Xt.float(), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                        tol=1e-10, X0=X0.float())
+    assert rel(host(X), ref) <= 1e-5
+    _announce("decode zero rhs")
+    for mode in ("fp64", "fp32", "fp32_ir"):
+        dt = torch.float64 if mode == "fp64" else torch.float32
+        X, info = cp.decode(torch.zeros_like(Xt, dtype=dt), d["om_r"], d["om_c"], P.p, P.n,
+                            d["Lr"], d["Lc"], 1.0, 1.0, mode=mode)
+        assert info["status"] == 0 and torch.count_nonzero(X) == 0
+
+
+def test_decode_singular_gamma_zero_returns_scatter(cfg1):
+    P = cfg1
+    d = dev_problem(P)
+    Xt = torch.from_numpy(P.Ytil).cuda()
+    X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 0.0, 0.0)
+    B = OD.rhs(P.Ytil, P.p, P.n, P.omega_r, P.omega_c)
+    assert info["iters"] == 1 and np.array_equal(host(X), B)
+
+
+def test_decode_is_deterministic(cfg1):
+    P = cfg1
+    d = dev_problem(P)
+    Xt = torch.from_numpy(P.Ytil).cuda()
+    for mode in ("fp64", "fp32_ir"):
+        dt = torch.float64 if mode == "fp64" else torch.float32
+        a, _ = cp.decode(Xt.to(dt), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0)
+        b, _ = cp.decode(Xt.to(dt), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0)
+        assert torch.equal(a, b)
+
+
+def test_backward_matches_oracle():
+    P = synth.small_problem(18, p_shape=(6, 10), n=80, rank=3, frac=0.5, gamma=(1.0, 1.0))
+    _announce("backward p=60 n=80")
+    d = dev_problem(P)
+    rng = np.random.default_rng(3)
+    Xtil = rng.standard_normal((P.rho_r, P.rho_c))
+    Xtrue = rng.standard_normal((P.p, P.n))
+    X = _decode_ref(P, Xtil, 1.0, 1.0)
+    G = 2 * (X - Xtrue)
+    dX_ref, dgr_ref, dgc_ref = OD.decode_backward(G, X, P.p, P.n, P.omega_r, P.omega_c, P.Lr,
+                                                  P.Lc, 1.0, 1.0)
+    dX, dgr, dgc, info = cp.decode_backward(torch.from_numpy(G).cuda(), torch.from_numpy(X).cuda(),
+                                            d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"],
+                                            1.0, 1.0, tol=1e-13)
+    assert rel(host(dX), dX_ref) <= 1e-9
+    assert np.isclose(dgr, dgr_ref, rtol=1e-9) and np.isclose(dgc, dgc_ref, rtol=1e-9)
+    dX, dgr, dgc, info = cp.decode_backward(torch.from_numpy(G).float().cuda(),
+                                            torch.from_numpy(X).float().cuda(), d["om_r"],
+                                            d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                                            tol=1e-10, mode="fp32_ir")
+    assert rel(host(dX), dX_ref) <= 1e-5
+    assert np.isclose(dgr, dgr_ref, rtol=1e-5) and np.isclose(dgc, dgc_ref, rtol=1e-5)
+
+
+def test_autograd_decode_matches_finite_differences():
+    P = synth.small_problem(18, p_shape=(6, 10), n=80, rank=3, frac=0.5, gamma=(1.0, 1.0))
+    _announce("autograd decode")
+    d = dev_problem(P)
+    rng = np.random.default_rng(4)
+    Xtrue = torch.from_numpy(rng.standard_normal((P.p, P.n))).cuda()
+    prob = cp.DecodeProblem(d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], tol=1e-13)
+    Xt = torch.from_numpy(P.Ytil).cuda().requires_grad_(True)
+    gr = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    gc = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = ((cp.Decode.apply(Xt, gr, gc, prob) - Xtrue) ** 2).sum()
+    loss.backward()
+
+    def L(Xtil, a, b):
+        X = OD.decode(Xtil, P.p, P.n, P.omega_r, P.omega_c, P.Lr, P.Lc, a, b)
+        return float(np.sum((X - host(Xtrue)) ** 2))
+
+    h = 1e-4
+    V = rng.standard_normal(P.Ytil.shape)
+    fd = (L(P.Ytil + h * V, 1, 1) - L(P.Ytil - h * V, 1, 1)) / (2 * h)
+    assert np.isclose(float((Xt.grad.double().cpu().numpy() * V).sum()), fd, rtol=1e-6)
+    fd_r = (L(P.Ytil, 1 + h, 1) - L(P.Ytil, 1 - h, 1)) / (2 * h)
+    fd_c = (L(P.Ytil, 1, 1 + h) - L(P.Ytil, 1, 1 - h)) / (2 * h)
+    assert np.isclose(gr.grad.item(), fd_r, rtol=1e-6)
+    assert np.isclose(gc.grad.item(), fd_c, rtol=1e-6)
+
+
+def test_invalid_inputs_are_rejected_on_device(cfg1):
+    P = cfg1
+    d = dev_problem(P)
+    Xt = torch.from_numpy(P.Ytil).cuda()
+    dup = d["om_r"].clone()
+    dup[1] = dup[0]
+    with pytest.raises(cp.CpcaError, match="repeated"):
+        cp.decode(Xt, dup, d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0)
+    bad = cp.Graph(d["Lr"].rowptr, d["Lr"].colind.clone(), d["Lr"].vals, P.p)
+    bad.colind[3] = P.p + 5
+    with pytest.raises(cp.CpcaError, match="out of"):
+        cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, bad, d["Lc"], 1.0, 1.0)
+    with pytest.raises(cp.CpcaError, match="gamma"):
+        cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], -1.0, 1.0)
+    # iteration cap: ENOCONV returns the last iterate with a warning
+    with pytest.warns(RuntimeWarning):
+        X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                            tol=1e-14, max_iter=3)
+    assert info["status"] == 2 and info["iters"] == 3
