@@ -54,7 +54,6 @@ struct cpca_handle_s {
 namespace {
 
 // Layout of the `fixed` device block.
-constexpr size_t kOffCounter = 0;          // unsigned[16]
 constexpr size_t kOffCg = 256;             // CgScal[2]
 constexpr size_t kOffFista = 512;          // FistaScal
 constexpr size_t kOffResults = 768;        // double[32]
@@ -102,7 +101,6 @@ cpca_status ensure_ws(cpca_handle h, size_t bytes) {
   return CPCA_OK;
 }
 
-unsigned* counter_ptr(cpca_handle h) { return reinterpret_cast<unsigned*>(h->fixed + kOffCounter); }
 CgScal* cg_ptr(cpca_handle h, int k = 0) { return reinterpret_cast<CgScal*>(h->fixed + kOffCg) + k; }
 FistaScal* fista_ptr(cpca_handle h) { return reinterpret_cast<FistaScal*>(h->fixed + kOffFista); }
 double* results_ptr(cpca_handle h) { return reinterpret_cast<double*>(h->fixed + kOffResults); }
@@ -216,31 +214,31 @@ struct GraphImage {
 
 template <typename T>
 GraphImage<T> stage_graph(Staging& st, const HostCsr& Lr, const HostCsr& Lc,
-                          const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc) {
+                          const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int H) {
   GraphImage<T> g{};
   std::vector<T> vr(Lr.v.begin(), Lr.v.begin() + Lr.nnz);
   g.o_rp = st.add(Lr.rp.data(), sizeof(int32_t) * Lr.rp.size());
   g.o_ci = st.add(Lr.ci.data(), sizeof(int32_t) * std::max<int64_t>(Lr.nnz, 1));
   g.o_v = st.add(vr.data(), sizeof(T) * vr.size());
-  // sliced ELL of L_c
+  // sliced ELL of L_c, slice height H
   const int64_t n = Lc.n;
-  const int64_t ns = (n + kSlice - 1) / kSlice;
+  const int64_t ns = (n + H - 1) / H;
   std::vector<int32_t> sp((size_t)ns + 1, 0);
   for (int64_t s = 0; s < ns; ++s) {
     int w = 0;
-    for (int64_t j = s * kSlice; j < std::min<int64_t>(n, (s + 1) * kSlice); ++j)
+    for (int64_t j = s * H; j < std::min<int64_t>(n, (s + 1) * H); ++j)
       w = std::max(w, Lc.rp[j + 1] - Lc.rp[j]);
-    sp[s + 1] = sp[s] + w * kSlice;
+    sp[s + 1] = sp[s] + w * H;
   }
-  std::vector<int32_t> sci((size_t)std::max(sp[ns], 1));
+  std::vector<int32_t> sci((size_t)std::max(sp[ns], 1), 0);
   std::vector<T> sv((size_t)std::max(sp[ns], 1), T(0));
   for (int64_t s = 0; s < ns; ++s) {
-    const int w = (sp[s + 1] - sp[s]) / kSlice;
-    for (int lane = 0; lane < kSlice; ++lane) {
-      const int64_t j = s * kSlice + lane;
+    const int w = (sp[s + 1] - sp[s]) / H;
+    for (int lane = 0; lane < H; ++lane) {
+      const int64_t j = s * H + lane;
       const int deg = j < n ? Lc.rp[j + 1] - Lc.rp[j] : 0;
       for (int e = 0; e < w; ++e) {
-        const size_t pos = (size_t)sp[s] + (size_t)e * kSlice + lane;
+        const size_t pos = (size_t)sp[s] + (size_t)e * H + lane;
         if (e < deg) {
           sci[pos] = Lc.ci[Lc.rp[j] + e];
           sv[pos] = (T)Lc.v[Lc.rp[j] + e];
@@ -277,67 +275,78 @@ DevGraph<T> bind_graph(const GraphImage<T>& g, const char* dev) {
 struct ApplyCfg {
   int R = 1;
   bool lds = true;
+  int vec = 1;  // columns per thread (16-byte accesses when > 1)
 };
 
+// Launch shape of the fused product for a p x n operand of `elem` bytes.
 ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem) {
   ApplyCfg c;
+  const int W = (int)(16 / elem);
+  c.vec = (n % W == 0) ? W : 1;
   const size_t row_bytes = (size_t)n * elem;
   c.R = 1;
   for (int R : {8, 4, 2}) {
-    if (R * row_bytes <= 32768 && (p + R - 1) / R >= 2048) {
+    if ((p + R - 1) / R >= 2048) {
       c.R = R;
       break;
     }
   }
+  c.lds = false;
   if (h->force_R > 0) c.R = h->force_R;
-  c.lds = (size_t)c.R * row_bytes <= 65536;
-  if (h->force_lds == 0) c.lds = false;
   if (h->force_lds == 1 && (size_t)c.R * row_bytes <= 65536) c.lds = true;
+  if (h->force_lds == 0) c.lds = false;
   return c;
 }
+
+int slice_height(const ApplyCfg& c) { return kWave * c.vec; }
 
 int vec_grid(size_t N) {
   const size_t b = (N + kThreads - 1) / kThreads;
   return (int)std::max<size_t>(1, std::min<size_t>(b, 2048));
 }
 
-template <typename T, int R, bool LDS, class Epi>
+int apply_grid(const ApplyCfg& cfg, int p) {
+  const int nrb = (p + cfg.R - 1) / cfg.R;
+  return 8 * ((nrb + 7) / 8);
+}
+
+template <typename T, int R, bool LDS, int VEC, class Epi>
 hipError_t launch_apply_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
-                          const Epi& epi, RedSlot slot) {
+                          const Epi& epi) {
   const int nrb = (p + R - 1) / R;
   const int per = (nrb + 7) / 8;
   const size_t shmem = LDS ? (size_t)R * n * sizeof(T) : 0;
-  k_apply2<T, R, LDS, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
-      X, p, n, g.Lr, g.Lc, g.mr, g.mc, nrb, per, epi, slot);
+  k_apply2<T, R, LDS, VEC, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
+      X, p, n, g.Lr, g.Lc, g.mr, g.mc, nrb, per, epi);
   return hipGetLastError();
+}
+
+template <typename T, int R, class Epi>
+hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
+                          const DevGraph<T>& g, const Epi& epi) {
+  constexpr int W = (int)(16 / sizeof(T));
+  if (cfg.vec == W) {
+    return cfg.lds ? launch_apply_t<T, R, true, W>(h, X, p, n, g, epi)
+                   : launch_apply_t<T, R, false, W>(h, X, p, n, g, epi);
+  }
+  return cfg.lds ? launch_apply_t<T, R, true, 1>(h, X, p, n, g, epi)
+                 : launch_apply_t<T, R, false, 1>(h, X, p, n, g, epi);
 }
 
 template <typename T, class Epi>
 cpca_status launch_apply(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
-                         const DevGraph<T>& g, const Epi& epi, RedSlot slot, int fam) {
+                         const DevGraph<T>& g, const Epi& epi, int fam) {
   STCHK(prof_begin(h, fam));
   hipError_t e;
-#define CPCA_CASE(RV)                                                             \
-  case RV:                                                                        \
-    e = cfg.lds ? launch_apply_t<T, RV, true>(h, X, p, n, g, epi, slot)           \
-                : launch_apply_t<T, RV, false>(h, X, p, n, g, epi, slot);         \
-    break;
   switch (cfg.R) {
-    CPCA_CASE(1)
-    CPCA_CASE(2)
-    CPCA_CASE(4)
-    CPCA_CASE(8)
-    default:
-      return fail(CPCA_EINVAL, "unsupported rows per workgroup");
+    case 1: e = launch_apply_r<T, 1>(h, cfg, X, p, n, g, epi); break;
+    case 2: e = launch_apply_r<T, 2>(h, cfg, X, p, n, g, epi); break;
+    case 4: e = launch_apply_r<T, 4>(h, cfg, X, p, n, g, epi); break;
+    case 8: e = launch_apply_r<T, 8>(h, cfg, X, p, n, g, epi); break;
+    default: return fail(CPCA_EINVAL, "unsupported rows per workgroup");
   }
-#undef CPCA_CASE
   if (e != hipSuccess) return fail(CPCA_EHIP, std::string("apply launch: ") + hipGetErrorString(e));
   return prof_end(h);
-}
-
-int apply_grid(const ApplyCfg& cfg, int p) {
-  const int nrb = (p + cfg.R - 1) / cfg.R;
-  return 8 * ((nrb + 7) / 8);
 }
 
 #define LAUNCHCHK()                                                                        \
@@ -355,31 +364,43 @@ struct Operator {
   ApplyCfg cfg;
 };
 
-// Runs CG iterations on (x, r, p, q) whose state was initialised on the
-// device (cg scalars k). Returns the final done code via host_cg.
+// Partial-sum buffers: `a` for the fused product, `b` for the vector kernels.
+struct Partials {
+  double* a = nullptr;
+  double* b = nullptr;
+};
+
+// Runs CG iterations on (x, r, p, q) whose scalars were armed on the device.
+// The host launches chunks of iterations and polls the device flag between
+// chunks; kernels of a finished solve return immediately.
 template <typename T>
 cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, T* q,
-                       int max_iter, RedSlot slot) {
+                       int max_iter, const Partials& part) {
   const size_t N = (size_t)op.p * op.n;
   CgScal* sc = cg_ptr(h);
   STCHK(read_fixed(h));
   if (host_cg(h).done) return CPCA_OK;
   int it = 0;
   int chunk = 4;
-  const int vg = vec_grid(N / Vec16<T>::W + 1);
+  const int ag = apply_grid(op.cfg, op.p);
+  const int vg = vec_grid(N / V16<T>::W + 1);
   while (it < max_iter) {
     const int m = std::min(chunk, max_iter - it);
-    for (int k = 0; k < m; ++k) {
-      EpiCg<T> epi{q, op.gr, op.gc, sc};
-      STCHK(launch_apply<T>(h, op.cfg, pv, op.p, op.n, op.g, epi, slot, FAM_APPLY));
+    for (int k = 0; k < m; ++k, ++it) {
+      EpiCg<T> epi;
+      epi.Q = q;
+      epi.gr = op.gr;
+      epi.gc = op.gc;
+      epi.partials = part.a;
+      epi.sc = sc;
+      STCHK(launch_apply<T>(h, op.cfg, pv, op.p, op.n, op.g, epi, FAM_APPLY));
       STCHK(prof_begin(h, FAM_UPDATE));
-      k_cg_update<T><<<vg, kThreads, 0, h->stream>>>(x, r, pv, q, N, sc, slot);
+      k_cg_update<T><<<vg, kThreads, 0, h->stream>>>(x, r, pv, q, N, sc, it, part.a, ag, part.b);
       LAUNCHCHK();
       STCHK(prof_end(h));
-      k_cg_pupdate<T><<<vg, kThreads, 0, h->stream>>>(pv, r, N, sc);
+      k_cg_pupdate<T><<<vg, kThreads, 0, h->stream>>>(pv, r, N, sc, it, part.b, vg);
       LAUNCHCHK();
     }
-    it += m;
     STCHK(read_fixed(h));
     STCHK(prof_collect(h));
     if (host_cg(h).done) break;
@@ -446,7 +467,7 @@ struct SolveOut {
   double* spare64 = nullptr;     // FP64 scratch of p*n (backward)
   DevGraph<double> g64;          // FP64 operator image (backward dots)
   ApplyCfg cfg64;
-  RedSlot slot{};
+  Partials part;
 };
 
 constexpr int kMaxOuter = 40;
@@ -459,21 +480,22 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
                          const void* X0, void* out, bool want_spare, SolveOut& so) {
   const size_t N = (size_t)p * n;
   const bool f32 = mode != CPCA_FP64;
-  Staging stg;
-  const GraphImage<double> gi64 = stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc);
-  GraphImage<float> gi32{};
-  if (f32) gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc);
   const ApplyCfg cfg64 = choose_cfg(h, p, n, sizeof(double));
   const ApplyCfg cfg32 = choose_cfg(h, p, n, sizeof(float));
+  Staging stg;
+  const GraphImage<double> gi64 = stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg64));
+  GraphImage<float> gi32{};
+  if (f32) gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg32));
   const int maxgrid = std::max({apply_grid(cfg64, (int)p), apply_grid(cfg32, (int)p), 2048});
 
   char* img = nullptr;
-  double *part = nullptr, *B64 = nullptr, *X64 = nullptr, *r64 = nullptr, *p64 = nullptr,
-         *q64 = nullptr, *spare = nullptr;
+  double *pa = nullptr, *pb = nullptr, *B64 = nullptr, *X64 = nullptr, *r64 = nullptr,
+         *p64 = nullptr, *q64 = nullptr, *spare = nullptr;
   float *B32 = nullptr, *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   auto layout = [&](Arena& a) {
     img = a.take<char>(stg.buf.size());
-    part = a.take<double>((size_t)maxgrid * 2);
+    pa = a.take<double>((size_t)maxgrid * 2);
+    pb = a.take<double>((size_t)maxgrid * 2);
     B64 = a.take<double>(N);
     X64 = a.take<double>(N);
     if (mode == CPCA_FP64) {
@@ -501,14 +523,16 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
   const DevGraph<double> g64 = bind_graph<double>(gi64, img);
   DevGraph<float> g32{};
   if (f32) g32 = bind_graph<float>(gi32, img);
-  RedSlot slot{part, counter_ptr(h)};
+  const Partials part{pa, pb};
   CgScal* sc = cg_ptr(h);
   const int vg = vec_grid(N);
+  const int ag64 = apply_grid(cfg64, (int)p);
+  const int ag32 = apply_grid(cfg32, (int)p);
   so.x64 = X64;
   so.spare64 = spare;
   so.g64 = g64;
   so.cfg64 = cfg64;
-  so.slot = slot;
+  so.part = part;
 
   // B64 = right-hand side in FP64, bb = ||B||^2
   if (rhs.dense) {
@@ -529,7 +553,9 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
           B64, (int)n, static_cast<const double*>(rhs.Xtil), rhs.rho_r, rhs.rho_c, rhs.om_r, rhs.om_c);
     LAUNCHCHK();
   }
-  k_norm2<double><<<vg, kThreads, 0, h->stream>>>(B64, N, &sc->bb, slot);
+  k_norm2<double><<<vg, kThreads, 0, h->stream>>>(B64, N, pa);
+  LAUNCHCHK();
+  k_sum_partials<1><<<1, kThreads, 0, h->stream>>>(pa, vg, &sc->bb);
   LAUNCHCHK();
   STCHK(read_fixed(h));
   const double bb = host_cg(h).bb;
@@ -556,13 +582,16 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
     if (X0) {
       k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(X64, static_cast<const double*>(X0), N);
       LAUNCHCHK();
-      EpiResidual<double, double> epi{B64, r64, p64, nullptr, gr, gc, sc, thr, 0.0};
-      STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, slot, FAM_OTHER));
+      EpiResidual<double, double> epi{B64, r64, p64, nullptr, gr, gc, pa};
+      STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, FAM_OTHER));
+      k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag64, thr, 0.0);
     } else {
-      k_cg_init_zero<double><<<vg, kThreads, 0, h->stream>>>(X64, r64, p64, B64, N, sc, thr, slot);
+      k_cg_init_zero<double><<<vg, kThreads, 0, h->stream>>>(X64, r64, p64, B64, N, pa);
       LAUNCHCHK();
+      k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
-    STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, slot));
+    LAUNCHCHK();
+    STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, part));
     so.iters = host_cg(h).iter;
     done = host_cg(h).done;
   } else if (mode == CPCA_FP32) {
@@ -572,13 +601,16 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
     if (X0) {
       k_convert<float, float><<<vg, kThreads, 0, h->stream>>>(x32, static_cast<const float*>(X0), N);
       LAUNCHCHK();
-      EpiResidual<float, float> epi{B32, r32, p32, nullptr, (float)gr, (float)gc, sc, thr, 0.0};
-      STCHK(launch_apply<float>(h, cfg32, x32, op.p, op.n, g32, epi, slot, FAM_OTHER));
+      EpiResidual<float, float> epi{B32, r32, p32, nullptr, (float)gr, (float)gc, pa};
+      STCHK(launch_apply<float>(h, cfg32, x32, op.p, op.n, g32, epi, FAM_OTHER));
+      k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag32, thr, 0.0);
     } else {
-      k_cg_init_zero<float><<<vg, kThreads, 0, h->stream>>>(x32, r32, p32, B32, N, sc, thr, slot);
+      k_cg_init_zero<float><<<vg, kThreads, 0, h->stream>>>(x32, r32, p32, B32, N, pa);
       LAUNCHCHK();
+      k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
-    STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, slot));
+    LAUNCHCHK();
+    STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
     so.iters = host_cg(h).iter;
     done = host_cg(h).done;
     k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
@@ -596,8 +628,10 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
     done = 0;
     for (int outer = 0;; ++outer) {
       const double inner_tol = std::min(0.25, std::max(1e-5, 0.5 * tol / rel_prev));
-      EpiResidual<double, float> epi{B64, r32, p32, x32, gr, gc, sc, -1.0, inner_tol * inner_tol};
-      STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, slot, FAM_OTHER));
+      EpiResidual<double, float> epi{B64, r32, p32, x32, gr, gc, pa};
+      STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, FAM_OTHER));
+      k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag64, -1.0, inner_tol * inner_tol);
+      LAUNCHCHK();
       STCHK(read_fixed(h));
       const CgScal cs = host_cg(h);
       if (cs.done == 3 || !std::isfinite(cs.res2)) {
@@ -614,7 +648,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
         done = 0;
         break;
       }
-      STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, slot));
+      STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
       const CgScal ci = host_cg(h);
       total += ci.iter;
       if (ci.done == 2 || ci.done == 3) {
@@ -630,9 +664,10 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
 
   // FP64 residual of the FP64 solution
   {
-    double* res = results_ptr(h) + 1;
-    EpiResNorm<double> epi{B64, gr, gc, res};
-    STCHK(launch_apply<double>(h, cfg64, X64, (int)p, (int)n, g64, epi, slot, FAM_OTHER));
+    EpiResNorm<double> epi{B64, gr, gc, pa};
+    STCHK(launch_apply<double>(h, cfg64, X64, (int)p, (int)n, g64, epi, FAM_OTHER));
+    k_sum_partials<1><<<1, kThreads, 0, h->stream>>>(pa, ag64, results_ptr(h) + 1);
+    LAUNCHCHK();
   }
   if (out) {
     if (f32)
@@ -657,15 +692,17 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   STCHK(fetch_csr("Lc_til", Lc_t, Lc));
   const size_t N = (size_t)rho_r * rho_c;
   std::vector<uint8_t> mr((size_t)rho_r, 0), mc((size_t)rho_c, 0);
-  Staging stg;
-  const GraphImage<double> gi = stage_graph<double>(stg, Lr, Lc, mr, mc);
   const ApplyCfg cfg = choose_cfg(h, rho_r, rho_c, sizeof(double));
-  const int maxgrid = std::max(apply_grid(cfg, (int)rho_r), 2048);
+  Staging stg;
+  const GraphImage<double> gi = stage_graph<double>(stg, Lr, Lc, mr, mc, slice_height(cfg));
+  const int ag = apply_grid(cfg, (int)rho_r);
+  const int maxgrid = std::max(ag, 2048);
   char* img = nullptr;
-  double *part = nullptr, *Y = nullptr, *S = nullptr, *Za = nullptr, *Zb = nullptr;
+  double *pa = nullptr, *pb = nullptr, *Y = nullptr, *S = nullptr, *Za = nullptr, *Zb = nullptr;
   auto layout = [&](Arena& a) {
     img = a.take<char>(stg.buf.size());
-    part = a.take<double>((size_t)maxgrid * 2);
+    pa = a.take<double>((size_t)maxgrid * 2);
+    pb = a.take<double>((size_t)maxgrid * 2);
     Y = a.take<double>(N);
     S = a.take<double>(N);
     Za = a.take<double>(N);
@@ -681,7 +718,6 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   layout(a);
   HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
   const DevGraph<double> g = bind_graph<double>(gi, img);
-  RedSlot slot{part, counter_ptr(h)};
   FistaScal* fs = fista_ptr(h);
   const int vg = vec_grid(N);
   const bool f32 = mode != CPCA_FP64;
@@ -697,23 +733,24 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   LAUNCHCHK();
   const double beta = 2.0 * gc * lmax_c + 2.0 * gr * lmax_r;
   int ran = 0;
-  int done = 0;
+  double* fpart[2] = {pa, pb};
+  const bool reduce = eps > 0.0;
   if (beta > 0.0 && max_iter > 0) {
     const double lam = 1.0 / beta;
     k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(Za, Y, N);
     LAUNCHCHK();
     double t = 1.0;
-    const bool reduce = eps > 0.0;
     int since_check = 0, check = 8;
     for (int j = 1; j <= max_iter; ++j) {
       const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
       const double c = (t - 1.0) / tn;
       if (reduce) {
-        EpiFista<true> epi{Y, S, Zb, 2.0 * gr, 2.0 * gc, lam, c, eps, fs};
-        STCHK(launch_apply<double>(h, cfg, Za, (int)rho_r, (int)rho_c, g, epi, slot, FAM_FISTA));
+        EpiFista<true> epi{Y, S, Zb, 2.0 * gr, 2.0 * gc, lam, c, eps, fs, j,
+                           fpart[(j - 1) & 1], ag, fpart[j & 1]};
+        STCHK(launch_apply<double>(h, cfg, Za, (int)rho_r, (int)rho_c, g, epi, FAM_FISTA));
       } else {
-        EpiFista<false> epi{Y, S, Zb, 2.0 * gr, 2.0 * gc, lam, c, 0.0, fs};
-        STCHK(launch_apply<double>(h, cfg, Za, (int)rho_r, (int)rho_c, g, epi, slot, FAM_FISTA));
+        EpiFista<false> epi{Y, S, Zb, 2.0 * gr, 2.0 * gc, lam, c, 0.0, fs, j, nullptr, 0, nullptr};
+        STCHK(launch_apply<double>(h, cfg, Za, (int)rho_r, (int)rho_c, g, epi, FAM_FISTA));
       }
       std::swap(Za, Zb);
       t = tn;
@@ -729,8 +766,10 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   }
   // objective at S
   {
-    EpiObjective epi{Y, gr, gc, fs};
-    STCHK(launch_apply<double>(h, cfg, S, (int)rho_r, (int)rho_c, g, epi, slot, FAM_OTHER));
+    EpiObjective epi{Y, gr, gc, pa};
+    STCHK(launch_apply<double>(h, cfg, S, (int)rho_r, (int)rho_c, g, epi, FAM_OTHER));
+    k_sum_partials<2><<<1, kThreads, 0, h->stream>>>(pa, ag, &fs->obj_l1);
+    LAUNCHCHK();
   }
   if (f32)
     k_convert<double, float><<<vg, kThreads, 0, h->stream>>>(static_cast<float*>(out), S, N);
@@ -740,11 +779,11 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   STCHK(read_fixed(h));
   STCHK(prof_collect(h));
   const FistaScal fh = host_fista(h);
-  done = fh.done;
-  if (iters) *iters = (eps > 0.0 && beta > 0.0) ? fh.iter : ran;
+  if (iters) *iters = fh.done == 1 ? fh.iter : ran;
   if (objective) *objective = fh.obj_l1 + fh.obj_g;
-  if (last_ratio) *last_ratio = fh.z2 > 0 ? fh.dz2 / fh.z2 : 0.0;
-  if (done == 3 || !std::isfinite(fh.obj_l1 + fh.obj_g)) return fail(CPCA_ENAN, "NaN or Inf in FISTA");
+  if (last_ratio) *last_ratio = (fh.done == 1 && fh.z2 > 0) ? fh.dz2 / fh.z2 : 0.0;
+  if (fh.done == 3 || !std::isfinite(fh.obj_l1 + fh.obj_g))
+    return fail(CPCA_ENAN, "NaN or Inf in FISTA");
   return CPCA_OK;
 }
 
@@ -886,7 +925,7 @@ extern "C" cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode, const
   SolveOut so;
   const bool f32 = mode != CPCA_FP64;
   cpca_status st =
-      solve_decode(h, mode, P, p, n, gamma_r, gamma_c, tol, max_iter, rhs, nullptr, nullptr, f32, so);
+      solve_decode(h, mode, P, p, n, gamma_r, gamma_c, tol, max_iter, rhs, nullptr, nullptr, true, so);
   if (st != CPCA_OK && st != CPCA_ENOCONV) {
     fill_info(info, st, so.iters, so.outer, so.rel, 0.0, t0);
     return st;
@@ -902,16 +941,18 @@ extern "C" cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode, const
     k_gather<double, double><<<vec_grid(ns), kThreads, 0, h->stream>>>(
         static_cast<double*>(dXtil_out), so.x64, (int)n, (int)rho_r, (int)rho_c, omega_r, omega_c);
   LAUNCHCHK();
-  // <Lambda, L_r X> and <Lambda, X L_c> in FP64
-  const double* X64 = static_cast<const double*>(X);
-  if (f32) {
+  // <Lambda, L_r X> and <Lambda, X L_c> in FP64 (X copied into the
+  // workspace so that the vector loads see an aligned FP64 operand)
+  if (f32)
     k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(so.spare64, static_cast<const float*>(X), N);
-    LAUNCHCHK();
-    X64 = so.spare64;
-  }
-  double* dots = results_ptr(h) + 2;
-  EpiDot2<double> epi{so.x64, dots};
-  STCHK(launch_apply<double>(h, so.cfg64, X64, (int)p, (int)n, so.g64, epi, so.slot, FAM_OTHER));
+  else
+    k_convert<double, double><<<vg, kThreads, 0, h->stream>>>(so.spare64, static_cast<const double*>(X), N);
+  LAUNCHCHK();
+  EpiDot2<double> epi{so.x64, so.part.a};
+  STCHK(launch_apply<double>(h, so.cfg64, so.spare64, (int)p, (int)n, so.g64, epi, FAM_OTHER));
+  k_sum_partials<2><<<1, kThreads, 0, h->stream>>>(so.part.a, apply_grid(so.cfg64, (int)p),
+                                                    results_ptr(h) + 2);
+  LAUNCHCHK();
   STCHK(read_fixed(h));
   STCHK(prof_collect(h));
   *dgamma_r = -host_results(h)[2];
@@ -924,14 +965,17 @@ namespace {
 template <typename T>
 cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_t p, int64_t n,
                       double gr, double gc, double* pq) {
+  ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T));
+  // user buffers: fall back to scalar columns if they are not 16-byte aligned
+  if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Q)) % 16 != 0) cfg.vec = 1;
   Staging stg;
-  const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc);
-  const ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T));
+  const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg));
+  const int ag = apply_grid(cfg, (int)p);
   char* img = nullptr;
   double* part = nullptr;
   auto layout = [&](Arena& a) {
     img = a.take<char>(stg.buf.size());
-    part = a.take<double>((size_t)apply_grid(cfg, (int)p) * 2);
+    part = a.take<double>((size_t)ag * 2);
   };
   {
     Arena a;
@@ -943,9 +987,10 @@ cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_
   layout(a);
   HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
   const DevGraph<T> g = bind_graph<T>(gi, img);
-  RedSlot slot{part, counter_ptr(h)};
-  EpiApply<T> epi{Q, (T)gr, (T)gc, results_ptr(h) + 4};
-  STCHK(launch_apply<T>(h, cfg, X, (int)p, (int)n, g, epi, slot, FAM_OTHER));
+  EpiApply<T> epi{Q, (T)gr, (T)gc, part};
+  STCHK(launch_apply<T>(h, cfg, X, (int)p, (int)n, g, epi, FAM_OTHER));
+  k_sum_partials<1><<<1, kThreads, 0, h->stream>>>(part, ag, results_ptr(h) + 4);
+  LAUNCHCHK();
   STCHK(read_fixed(h));
   STCHK(prof_collect(h));
   if (pq) *pq = host_results(h)[4];

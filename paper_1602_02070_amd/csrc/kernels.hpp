@@ -4,23 +4,24 @@
 //     out(i, j) = mask(i, j) X(i, j) + a_r (L_r X)(i, j) + a_c (X L_c)(i, j)
 // which is the gradient of the graph term of FRPCAG (Section IV.B) and the
 // operator of the alternate decoder's normal equations (Section V.B). One
-// workgroup owns R consecutive rows of X and sweeps all n columns:
-//   * the R rows are staged in LDS, so the X L_c term gathers its operands
-//     from LDS;
-//   * L_c is held in a sliced ELL layout (SELL, one slice per 64 columns =
-//     one wavefront), so its index/value loads are coalesced and all lanes of
-//     a wave run the same trip count;
-//   * the L_r X term streams neighbour rows of X straight from memory with
-//     coalesced column accesses (row i's CSR entries are wave-uniform);
+// workgroup owns R consecutive rows of X and sweeps all n columns, VEC
+// consecutive columns per thread (16-byte accesses):
+//   * L_r X streams the neighbour rows of X with coalesced vector loads; the
+//     CSR entries of row i are uniform across the workgroup;
+//   * X L_c gathers from the R rows of X (staged in LDS, or read through the
+//     L1 when LDS staging is off); L_c is held as sliced ELL with one slice
+//     per wavefront (64 * VEC columns), so its index/value loads are 16-byte
+//     vector loads and every lane of a wave runs the same trip count;
 //   * the row-block index is remapped so that each XCD owns a contiguous
 //     range of rows and neighbour rows are shared through its L2.
 // What happens to out(i, j) is decided by an epilogue functor (CG apply,
 // FISTA step, residual, objective, adjoint dot products).
 //
-// Reductions are deterministic: FP64 per-thread partials, wave butterfly,
-// per-block partials in global memory, and the last block to finish (found
-// with an integer atomic counter) sums the block partials in a fixed order
-// and runs the epilogue's finaliser (CG alpha/beta, convergence flags).
+// Reductions use no atomics and no fences: every workgroup writes its FP64
+// partial sums, and the kernel that needs the total (the next kernel on the
+// stream) sums the partials itself, in a fixed order, redundantly in every
+// workgroup. Results are therefore bitwise reproducible, and scalars such as
+// the CG step lengths never leave the device.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,8 +30,7 @@
 namespace cpca {
 
 constexpr int kWave = 64;
-constexpr int kSlice = 64;        // SELL slice height (columns per slice)
-constexpr int kThreads = 256;     // threads per workgroup for all kernels
+constexpr int kThreads = 256;  // threads per workgroup for all kernels
 constexpr int kMaxWaves = kThreads / kWave;
 
 template <typename T>
@@ -40,9 +40,10 @@ struct CsrDev {
   const T* v;
 };
 
-// Sliced ELL: slice s covers columns [64 s, 64 s + 64); its entries start at
-// sp[s], width w_s = (sp[s+1] - sp[s]) / 64, entry e of column j sits at
-// sp[s] + 64 e + (j & 63). Padding entries carry value 0 and index j.
+// Sliced ELL with slice height H = 64 * VEC: slice s covers columns
+// [H s, H s + H); its entries start at sp[s], width w_s = (sp[s+1]-sp[s]) / H,
+// entry e of column j sits at sp[s] + H e + (j - H s). Padding entries carry
+// value 0 and a valid column index.
 template <typename T>
 struct SellDev {
   const int* sp;
@@ -50,36 +51,34 @@ struct SellDev {
   const T* v;
 };
 
-// Device-resident scalars of one CG solve (FP64).
+// Device-resident scalars of one CG solve (FP64). rr is double-buffered by
+// iteration parity: iteration `it` reads rr[it & 1] and the p-update writes
+// rr[(it + 1) & 1], so no workgroup reads a value another workgroup of the
+// same kernel is writing.
 struct CgScal {
-  double rr;      // current <r, r>
+  double rr[2];
   double thr;     // stop when rr <= thr
   double alpha;
   double beta;
   double pq;      // last <p, A p>
-  double bb;      // ||rhs||^2
   double res2;    // last FP64 residual norm^2 (refinement)
   double aux;     // last rounded-residual norm^2 (refinement)
+  double bb;      // ||rhs||^2
   int iter;       // iterations completed
   int done;       // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
-  int pad0, pad1;
 };
 
 // Device-resident scalars of one FISTA run.
 struct FistaScal {
-  double dz2;     // ||Z+ - Z||^2 of the last reduced step
-  double z2;      // ||Z||^2 of the last reduced step
+  double dz2;     // ||Z+ - Z||^2 of the step that stopped the run
+  double z2;
   double obj_l1;  // objective pieces
   double obj_g;
-  int iter;
+  int iter;       // iteration that met the stopping test (0: none)
   int done;       // 0 running, 1 stopped by eps, 3 NaN/Inf
-  int pad0, pad1;
 };
 
-struct RedSlot {
-  double* partials;   // gridDim.x * NV doubles
-  unsigned* counter;  // zero between launches
-};
+__device__ __forceinline__ bool bad(double x) { return !(x == x) || x - x != 0.0; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -87,45 +86,36 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ double load_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Deterministic grid reduction of NV FP64 values. Every thread of every
-// block must call it. Returns true in all threads of the block that finished
-// last; `tot` then holds the grid totals (in every thread of that block).
+// Writes the workgroup's NV partial sums to partials[blockIdx.x * NV + k].
 template <int NV>
-__device__ bool grid_reduce(double (&v)[NV], RedSlot slot, double (&tot)[NV]) {
+__device__ void block_partials(const double (&v)[NV], double* partials) {
   __shared__ double red[NV][kMaxWaves];
-  __shared__ int is_last;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const double s = wave_sum(v[k]);
     if (lane == 0) red[k][wid] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += red[k][w];
-      slot.partials[(size_t)blockIdx.x * NV + k] = s;
-    }
-    __threadfence();
-    const unsigned prev = atomicAdd(slot.counter, 1u);
-    is_last = (prev == gridDim.x - 1) ? 1 : 0;
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += red[threadIdx.x][w];
+    partials[(size_t)blockIdx.x * NV + threadIdx.x] = s;
   }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
+}
+
+// Sums nb * NV partials written by a previous kernel, in a fixed order.
+// Every thread of the workgroup receives the same totals.
+template <int NV>
+__device__ void sum_partials(const double* partials, int nb, double (&tot)[NV]) {
+  __shared__ double red[NV][kMaxWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-      s += load_agent(&slot.partials[(size_t)b * NV + k]);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partials[(size_t)b * NV + k];
     s = wave_sum(s);
     if (lane == 0) red[k][wid] = s;
   }
@@ -133,78 +123,94 @@ __device__ bool grid_reduce(double (&v)[NV], RedSlot slot, double (&tot)[NV]) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[k][w];
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += red[k][w];
     tot[k] = s;
   }
-  if (threadIdx.x == 0)
-    __hip_atomic_store(slot.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
+  __syncthreads();
 }
 
-__device__ __forceinline__ bool bad(double x) { return !(x == x) || x - x != 0.0; }
+// ------------------------------------------------------------ vector access
+template <typename T, int VEC> struct VecT;
+template <> struct VecT<float, 1> { using type = float; };
+template <> struct VecT<float, 2> { using type = float2; };
+template <> struct VecT<float, 4> { using type = float4; };
+template <> struct VecT<double, 1> { using type = double; };
+template <> struct VecT<double, 2> { using type = double2; };
+template <> struct VecT<int, 1> { using type = int; };
+template <> struct VecT<int, 2> { using type = int2; };
+template <> struct VecT<int, 4> { using type = int4; };
+
+template <typename T, int VEC>
+__device__ __forceinline__ void vld(const T* __restrict__ p, T (&v)[VEC]) {
+  using V = typename VecT<T, VEC>::type;
+  const V t = *reinterpret_cast<const V*>(p);
+  if constexpr (VEC == 1) {
+    v[0] = t;
+  } else if constexpr (VEC == 2) {
+    v[0] = t.x; v[1] = t.y;
+  } else {
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void vst(T* __restrict__ p, const T (&v)[VEC]) {
+  using V = typename VecT<T, VEC>::type;
+  V t;
+  if constexpr (VEC == 1) {
+    t = v[0];
+  } else if constexpr (VEC == 2) {
+    t.x = v[0]; t.y = v[1];
+  } else {
+    t.x = v[0]; t.y = v[1]; t.z = v[2]; t.w = v[3];
+  }
+  *reinterpret_cast<V*>(p) = t;
+}
 
 // ---------------------------------------------------------------------------
 // Epilogues of the fused two-sided product. Each one provides
-//   NV                      number of FP64 reduction values
-//   skip()                  device-side early exit (converged solves)
-//   operator()(i, j, idx, x, mx, accr, accc, acc)
-//                           x = X(i,j), mx = mask(i,j) * X(i,j),
-//                           accr = (L_r X)(i,j), accc = (X L_c)(i,j)
-//   finalize(tot)           runs once, in the last block, threads see tot
+//   NV                    number of FP64 partial sums it produces
+//   prologue()            called by the whole workgroup first; returns true to
+//                         skip the launch (converged solve); may sum partials
+//                         of the previous kernel
+//   apply<VEC>(i, idx, x, mx, accr, accc, acc)
+//                         VEC consecutive outputs of row i starting at flat
+//                         index idx: x = X, mx = mask o X, accr = (L_r X),
+//                         accc = (X L_c); acc receives the partial sums
+//   partials              where the workgroup partials go (may be null)
 // ---------------------------------------------------------------------------
 
-// Q = A(P), <P, Q> -> *pq (plain operator application).
+// Q = A(P), partial <P, Q> (plain operator application).
 template <typename T>
 struct EpiApply {
   static constexpr int NV = 1;
   T* Q;
   T gr, gc;
-  double* pq;
-  __device__ bool skip() const { return false; }
-  __device__ void operator()(int, int, size_t idx, T x, T mx, T accr, T accc,
-                             double* acc) const {
-    const T out = mx + gr * accr + gc * accc;
-    Q[idx] = out;
-    acc[0] += (double)x * (double)out;
-  }
-  __device__ void finalize(const double* tot) const {
-    if (threadIdx.x == 0 && pq) *pq = tot[0];
+  double* partials;
+  __device__ bool prologue() const { return false; }
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&x)[VEC], const T (&mx)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T out[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      out[v] = mx[v] + gr * accr[v] + gc * accc[v];
+      acc[0] += (double)x[v] * (double)out[v];
+    }
+    vst<T, VEC>(Q + idx, out);
   }
 };
 
-// CG: q = A(p), alpha = rr / <p, q>.
+// CG: q = A(p) and the partials of <p, q>; skipped once the solve is done.
 template <typename T>
-struct EpiCg {
-  static constexpr int NV = 1;
-  T* Q;
-  T gr, gc;
-  CgScal* sc;
-  __device__ bool skip() const { return sc->done != 0; }
-  __device__ void operator()(int, int, size_t idx, T x, T mx, T accr, T accc,
-                             double* acc) const {
-    const T out = mx + gr * accr + gc * accc;
-    Q[idx] = out;
-    acc[0] += (double)x * (double)out;
-  }
-  __device__ void finalize(const double* tot) const {
-    if (threadIdx.x != 0) return;
-    const double pq = tot[0];
-    sc->pq = pq;
-    if (bad(pq)) {
-      sc->done = 3;
-    } else if (!(pq > 0.0)) {
-      sc->done = 2;
-    } else {
-      sc->alpha = sc->rr / pq;
-    }
-  }
+struct EpiCg : EpiApply<T> {
+  const CgScal* sc;
+  __device__ bool prologue() const { return sc->done != 0; }
 };
 
 // Residual R = B - A(X) computed in T, stored rounded to TO into r_out and
 // p_out (initial residual and direction of a CG solve); x_out (the CG
-// iterate), if given, is cleared. Totals: ||R||^2 and ||round(R)||^2 (FP64).
-// The finaliser arms the CG scalars: rr = ||round(R)||^2 and the stop
-// threshold thr_abs, or rel_tol2 * rr when thr_abs < 0.
+// iterate), if given, is cleared. Partials: ||R||^2 and ||round(R)||^2.
 template <typename T, typename TO>
 struct EpiResidual {
   static constexpr int NV = 2;
@@ -213,48 +219,44 @@ struct EpiResidual {
   TO* p_out;
   TO* x_out;
   T gr, gc;
-  CgScal* sc;
-  double thr_abs;
-  double rel_tol2;
-  __device__ bool skip() const { return false; }
-  __device__ void operator()(int, int, size_t idx, T, T mx, T accr, T accc,
-                             double* acc) const {
-    const T R = B[idx] - (mx + gr * accr + gc * accc);
-    const TO Rt = (TO)R;
-    r_out[idx] = Rt;
-    p_out[idx] = Rt;
-    if (x_out) x_out[idx] = TO(0);
-    acc[0] += (double)R * (double)R;
-    acc[1] += (double)Rt * (double)Rt;
-  }
-  __device__ void finalize(const double* tot) const {
-    if (threadIdx.x != 0) return;
-    sc->res2 = tot[0];
-    sc->aux = tot[1];
-    sc->rr = tot[1];
-    sc->thr = thr_abs >= 0.0 ? thr_abs : rel_tol2 * tot[1];
-    sc->iter = 0;
-    sc->alpha = 0.0;
-    sc->beta = 0.0;
-    sc->done = (bad(tot[0]) || bad(tot[1])) ? 3 : (tot[1] <= sc->thr ? 1 : 0);
+  double* partials;
+  __device__ bool prologue() const { return false; }
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&)[VEC], const T (&mx)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T b[VEC];
+    vld<T, VEC>(B + idx, b);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const T R = b[v] - (mx[v] + gr * accr[v] + gc * accc[v]);
+      const TO Rt = (TO)R;
+      r_out[idx + v] = Rt;
+      p_out[idx + v] = Rt;
+      if (x_out) x_out[idx + v] = TO(0);
+      acc[0] += (double)R * (double)R;
+      acc[1] += (double)Rt * (double)Rt;
+    }
   }
 };
 
-// Residual norm only: ||B - A(X)||^2, X of any storage type, FP64 arithmetic.
+// Partials of ||B - A(X)||^2.
 template <typename T>
 struct EpiResNorm {
   static constexpr int NV = 1;
   const T* B;
-  double gr, gc;
-  double* out;
-  __device__ bool skip() const { return false; }
-  __device__ void operator()(int, int, size_t idx, T, T mx, T accr, T accc,
-                             double* acc) const {
-    const double R = (double)B[idx] - ((double)mx + gr * (double)accr + gc * (double)accc);
-    acc[0] += R * R;
-  }
-  __device__ void finalize(const double* tot) const {
-    if (threadIdx.x == 0) *out = tot[0];
+  T gr, gc;
+  double* partials;
+  __device__ bool prologue() const { return false; }
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&)[VEC], const T (&mx)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T b[VEC];
+    vld<T, VEC>(B + idx, b);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const double R = (double)b[v] - (double)(mx[v] + gr * accr[v] + gc * accc[v]);
+      acc[0] += R * R;
+    }
   }
 };
 
@@ -264,6 +266,9 @@ struct EpiResNorm {
 //   Z+ = S + c (S - S_prev),   c = (t_j - 1) / t_{j+1}
 // S overwrites S_prev in place (same element, same thread); Z+ goes to a
 // second buffer because neighbouring rows of Z are still being read.
+// With REDUCE, iteration j also produces the partials of ||Z+ - Z||^2 and
+// ||Z||^2, and iteration j + 1 evaluates the stopping test of iteration j in
+// its prologue (partial buffers alternate with the parity of j).
 template <bool REDUCE>
 struct EpiFista {
   static constexpr int NV = 2;
@@ -272,52 +277,67 @@ struct EpiFista {
   double* Zn;
   double two_gr, two_gc, lam, c, eps;
   FistaScal* fs;
-  __device__ bool skip() const { return fs->done != 0; }
-  __device__ void operator()(int, int, size_t idx, double z, double, double accr,
-                             double accc, double* acc) const {
-    const double g = z - lam * (two_gr * accr + two_gc * accc);
-    const double y = Y[idx];
-    const double d = g - y;
-    const double mag = fabs(d) - lam;
-    const double s = mag > 0.0 ? y + copysign(mag, d) : y;
-    const double sp = S[idx];
-    const double zn = s + c * (s - sp);
-    S[idx] = s;
-    Zn[idx] = zn;
-    if (REDUCE) {
-      const double dz = zn - z;
-      acc[0] += dz * dz;
-      acc[1] += z * z;
+  int j;                       // iteration index (1-based)
+  const double* prev_partials; // partials of iteration j - 1 (REDUCE, j > 1)
+  int prev_nb;
+  double* partials;
+  __device__ bool prologue() const {
+    if (fs->done != 0) return true;
+    if (!REDUCE || j == 1) return false;
+    double tot[2];
+    sum_partials<2>(prev_partials, prev_nb, tot);
+    const bool stop = bad(tot[0]) || bad(tot[1]) || tot[0] < eps * tot[1];
+    if (stop && blockIdx.x == 0 && threadIdx.x == 0) {
+      fs->dz2 = tot[0];
+      fs->z2 = tot[1];
+      fs->iter = j - 1;
+      fs->done = (bad(tot[0]) || bad(tot[1])) ? 3 : 1;
     }
+    return stop;
   }
-  __device__ void finalize(const double* tot) const {
-    if (threadIdx.x != 0) return;
-    fs->dz2 = tot[0];
-    fs->z2 = tot[1];
-    fs->iter += 1;
-    if (bad(tot[0]) || bad(tot[1]))
-      fs->done = 3;
-    else if (tot[0] < eps * tot[1])
-      fs->done = 1;
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const double (&z)[VEC], const double (&)[VEC],
+                        const double (&accr)[VEC], const double (&accc)[VEC],
+                        double* acc) const {
+    double y[VEC], sp[VEC], s[VEC], zn[VEC];
+    vld<double, VEC>(Y + idx, y);
+    vld<double, VEC>(S + idx, sp);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const double g = z[v] - lam * (two_gr * accr[v] + two_gc * accc[v]);
+      const double d = g - y[v];
+      const double mag = fabs(d) - lam;
+      s[v] = mag > 0.0 ? y[v] + copysign(mag, d) : y[v];
+      zn[v] = s[v] + c * (s[v] - sp[v]);
+      if (REDUCE) {
+        const double dz = zn[v] - z[v];
+        acc[0] += dz * dz;
+        acc[1] += z[v] * z[v];
+      }
+    }
+    vst<double, VEC>(S + idx, s);
+    vst<double, VEC>(Zn + idx, zn);
   }
 };
 
-// FRPCAG objective at X: ||Y - X||_1 + <X, gc X L_c + gr L_r X>.
+// FRPCAG objective pieces at X: ||Y - X||_1 and <X, gc X L_c + gr L_r X>.
 struct EpiObjective {
   static constexpr int NV = 2;
   const double* Y;
   double gr, gc;
-  FistaScal* fs;
-  __device__ bool skip() const { return false; }
-  __device__ void operator()(int, int, size_t idx, double x, double, double accr,
-                             double accc, double* acc) const {
-    acc[0] += fabs(Y[idx] - x);
-    acc[1] += x * (gr * accr + gc * accc);
-  }
-  __device__ void finalize(const double* tot) const {
-    if (threadIdx.x != 0) return;
-    fs->obj_l1 = tot[0];
-    fs->obj_g = tot[1];
+  double* partials;
+  __device__ bool prologue() const { return false; }
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const double (&x)[VEC], const double (&)[VEC],
+                        const double (&accr)[VEC], const double (&accc)[VEC],
+                        double* acc) const {
+    double y[VEC];
+    vld<double, VEC>(Y + idx, y);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      acc[0] += fabs(y[v] - x[v]);
+      acc[1] += x[v] * (gr * accr[v] + gc * accc[v]);
+    }
   }
 };
 
@@ -326,36 +346,37 @@ template <typename T>
 struct EpiDot2 {
   static constexpr int NV = 2;
   const T* Lam;
-  double* out;  // 2 doubles
-  __device__ bool skip() const { return false; }
-  __device__ void operator()(int, int, size_t idx, T, T, T accr, T accc,
-                             double* acc) const {
-    const double l = (double)Lam[idx];
-    acc[0] += l * (double)accr;
-    acc[1] += l * (double)accc;
-  }
-  __device__ void finalize(const double* tot) const {
-    if (threadIdx.x != 0) return;
-    out[0] = tot[0];
-    out[1] = tot[1];
+  double* partials;
+  __device__ bool prologue() const { return false; }
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&)[VEC], const T (&)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T l[VEC];
+    vld<T, VEC>(Lam + idx, l);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      acc[0] += (double)l[v] * (double)accr[v];
+      acc[1] += (double)l[v] * (double)accc[v];
+    }
   }
 };
 
 // ---------------------------------------------------------------------------
-// The fused two-sided product. R rows per workgroup, all n columns.
+// The fused two-sided product. R rows per workgroup, all n columns, VEC
+// consecutive columns per thread (n must be a multiple of VEC).
 //   LDS = true : the R rows live in LDS (R * n * sizeof(T) bytes).
-//   LDS = false: X L_c gathers from global memory (very wide rows).
-// Grid: 8 * per blocks; block b handles row block (b % 8) * per + b / 8, so
-// that each XCD (blocks are dealt to XCDs round-robin) owns `per`
-// consecutive row blocks. Blocks past the last row block only join the
-// reduction.
+//   LDS = false: X L_c gathers from global memory (through the L1).
+// Grid: 8 * per workgroups; workgroup b handles row block (b % 8) * per + b / 8
+// so that each XCD (workgroups are dealt to XCDs round-robin) owns `per`
+// consecutive row blocks. Workgroups past the last row block only write
+// zero partials.
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool LDS, class Epi>
+template <typename T, int R, bool LDS, int VEC, class Epi>
 __global__ void __launch_bounds__(kThreads)
 k_apply2(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc,
-         const uint8_t* __restrict__ mr, const uint8_t* __restrict__ mc,
-         int nrb, int per, Epi epi, RedSlot slot) {
-  if (epi.skip()) return;
+         const uint8_t* __restrict__ mr, const uint8_t* __restrict__ mc, int nrb, int per,
+         Epi epi) {
+  if (epi.prologue()) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* panel = reinterpret_cast<T*>(smem_raw);
   double acc[Epi::NV];
@@ -364,6 +385,8 @@ k_apply2(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc,
 
   const int b = blockIdx.x;
   const int rb = (b & 7) * per + (b >> 3);
+  constexpr int H = kWave * VEC;         // SELL slice height
+  constexpr int CPB = kThreads * VEC;    // columns per pass
   if (rb < nrb) {
     const int i0 = rb * R;
     const int rows = min(R, p - i0);
@@ -372,108 +395,131 @@ k_apply2(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc,
       for (int rr = 0; rr < R; ++rr) {
         if (rr < rows) {
           const T* src = X + (size_t)(i0 + rr) * n;
-          for (int j = threadIdx.x; j < n; j += blockDim.x) panel[rr * n + j] = src[j];
+          for (int c = threadIdx.x * VEC; c < n; c += CPB) {
+            T t[VEC];
+            vld<T, VEC>(src + c, t);
+            vst<T, VEC>(panel + rr * n + c, t);
+          }
         }
       }
       __syncthreads();
     }
-    for (int jb = 0; jb < n; jb += blockDim.x) {
-      const int j = jb + threadIdx.x;
-      if (j >= n) continue;
-      // X L_c: column j of L_c (= row j, L_c symmetric), shared by the R rows
-      T accc[R];
+    for (int c0 = threadIdx.x * VEC; c0 < n; c0 += CPB) {
+      // X L_c: columns c0 .. c0 + VEC - 1 of L_c (= rows, L_c symmetric),
+      // shared by the R rows of the block
+      T accc[R][VEC];
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) accc[rr] = T(0);
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) accc[rr][v] = T(0);
       {
-        const int s = j >> 6;
+        const int s = c0 / H;
         const int beg = Lc.sp[s];
-        const int w = (Lc.sp[s + 1] - beg) >> 6;
-        const int* ci = Lc.ci + beg + (j & 63);
-        const T* cv = Lc.v + beg + (j & 63);
-#pragma unroll 4
+        const int w = (Lc.sp[s + 1] - beg) / H;
+        const int off = beg + (c0 - s * H);
+#pragma unroll 2
         for (int e = 0; e < w; ++e) {
-          const int k = ci[e * kSlice];
-          const T v = cv[e * kSlice];
+          int kk[VEC];
+          T vv[VEC];
+          vld<int, VEC>(Lc.ci + off + e * H, kk);
+          vld<T, VEC>(Lc.v + off + e * H, vv);
 #pragma unroll
           for (int rr = 0; rr < R; ++rr) {
             if (rr < rows) {
-              const T xv = LDS ? panel[rr * n + k] : X[(size_t)(i0 + rr) * n + k];
-              accc[rr] += v * xv;
+              const T* rowp = LDS ? panel + rr * n : X + (size_t)(i0 + rr) * n;
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) accc[rr][v] += vv[v] * rowp[kk[v]];
             }
           }
         }
       }
-      const uint8_t mcj = mc[j];
+      uint8_t mcv[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) mcv[v] = mc[c0 + v];
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         if (rr < rows) {
           const int i = i0 + rr;
-          // L_r X: row i of L_r, neighbour rows of X, coalesced over j
-          T accr = T(0);
+          // L_r X: row i of L_r, neighbour rows of X, coalesced over columns
+          T accr[VEC];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) accr[v] = T(0);
           const int e0 = Lr.rp[i];
           const int e1 = Lr.rp[i + 1];
 #pragma unroll 4
-          for (int e = e0; e < e1; ++e) accr += Lr.v[e] * X[(size_t)Lr.ci[e] * n + j];
-          const size_t idx = (size_t)i * n + j;
-          const T x = LDS ? panel[rr * n + j] : X[idx];
-          const T mx = (mr[i] & mcj) ? x : T(0);
-          epi(i, j, idx, x, mx, accr, accc[rr], acc);
+          for (int e = e0; e < e1; ++e) {
+            const T w = Lr.v[e];
+            T xv[VEC];
+            vld<T, VEC>(X + (size_t)Lr.ci[e] * n + c0, xv);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) accr[v] += w * xv[v];
+          }
+          const size_t idx = (size_t)i * n + c0;
+          T x[VEC], mx[VEC];
+          if (LDS)
+            vld<T, VEC>(panel + rr * n + c0, x);
+          else
+            vld<T, VEC>(X + idx, x);
+          const uint8_t mri = mr[i];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) mx[v] = (mri & mcv[v]) ? x[v] : T(0);
+          epi.template apply<VEC>(i, idx, x, mx, accr, accc[rr], acc);
         }
       }
     }
   }
-  double tot[Epi::NV];
-  if (grid_reduce<Epi::NV>(acc, slot, tot)) epi.finalize(tot);
+  if (epi.partials) block_partials<Epi::NV>(acc, epi.partials);
 }
 
 // ---------------------------------------------------------------------------
-// CG vector kernels (grid-stride, 16-byte vector accesses where aligned).
+// CG vector kernels (grid-stride over 16-byte vectors; N % VEC tail scalar).
 // ---------------------------------------------------------------------------
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
+template <typename T> struct V16 { static constexpr int W = 16 / sizeof(T); };
 
-template <typename T>
-__device__ __forceinline__ void vload(const T* p, T (&v)[Vec16<T>::W]) {
-  using V = typename Vec16<T>::type;
-  const V t = *reinterpret_cast<const V*>(p);
-  if constexpr (Vec16<T>::W == 4) { v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w; }
-  else { v[0] = t.x; v[1] = t.y; }
-}
-template <typename T>
-__device__ __forceinline__ void vstore(T* p, const T (&v)[Vec16<T>::W]) {
-  using V = typename Vec16<T>::type;
-  V t;
-  if constexpr (Vec16<T>::W == 4) { t.x = v[0]; t.y = v[1]; t.z = v[2]; t.w = v[3]; }
-  else { t.x = v[0]; t.y = v[1]; }
-  *reinterpret_cast<V*>(p) = t;
-}
-
-// x += alpha p; r -= alpha q; rr_new = <r, r>; beta = rr_new / rr.
+// x += alpha p; r -= alpha q; partials of <r, r>.
+// alpha = rr / <p, q> is formed here from the apply kernel's partials.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-            const T* __restrict__ q, size_t N, CgScal* sc, RedSlot slot) {
+            const T* __restrict__ q, size_t N, CgScal* sc, int it,
+            const double* __restrict__ part_pq, int nb_pq, double* __restrict__ part_rr) {
   if (sc->done != 0) return;
-  const T alpha = (T)sc->alpha;
-  constexpr int W = Vec16<T>::W;
+  double t[1];
+  sum_partials<1>(part_pq, nb_pq, t);
+  const double pq = t[0];
+  const double rr = sc->rr[it & 1];
+  if (bad(pq) || !(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->iter = it;
+      sc->done = bad(pq) ? 3 : 2;
+    }
+    return;
+  }
+  const double alpha_d = rr / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->alpha = alpha_d;
+  }
+  const T alpha = (T)alpha_d;
+  constexpr int W = V16<T>::W;
   double acc[1] = {0.0};
   const size_t nv = N / W;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
     T xv[W], rv[W], pv[W], qv[W];
-    vload(x + v * W, xv);
-    vload(r + v * W, rv);
-    vload(p + v * W, pv);
-    vload(q + v * W, qv);
+    vld<T, W>(x + v * W, xv);
+    vld<T, W>(r + v * W, rv);
+    vld<T, W>(p + v * W, pv);
+    vld<T, W>(q + v * W, qv);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
       xv[k] += alpha * pv[k];
       rv[k] -= alpha * qv[k];
       acc[0] += (double)rv[k] * (double)rv[k];
     }
-    vstore(x + v * W, xv);
-    vstore(r + v * W, rv);
+    vst<T, W>(x + v * W, xv);
+    vst<T, W>(r + v * W, rv);
   }
   for (size_t e = nv * W + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
     x[e] += alpha * p[e];
@@ -481,47 +527,62 @@ k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
     r[e] = rn;
     acc[0] += (double)rn * (double)rn;
   }
-  double tot[1];
-  if (grid_reduce<1>(acc, slot, tot) && threadIdx.x == 0) {
-    const double rr_new = tot[0];
-    sc->iter += 1;
-    if (bad(rr_new)) {
-      sc->done = 3;
-    } else {
-      sc->beta = rr_new / sc->rr;
-      sc->rr = rr_new;
-      if (rr_new <= sc->thr) sc->done = 1;
-    }
-  }
+  block_partials<1>(acc, part_rr);
 }
 
-// p = r + beta p.
+// beta = rr_new / rr; p = r + beta p; convergence test rr_new <= thr.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_cg_pupdate(T* __restrict__ p, const T* __restrict__ r, size_t N, const CgScal* sc) {
+k_cg_pupdate(T* __restrict__ p, const T* __restrict__ r, size_t N, CgScal* sc, int it,
+             const double* __restrict__ part_rr, int nb_rr) {
   if (sc->done != 0) return;
-  const T beta = (T)sc->beta;
-  constexpr int W = Vec16<T>::W;
+  double t[1];
+  sum_partials<1>(part_rr, nb_rr, t);
+  const double rr_new = t[0];
+  const double rr = sc->rr[it & 1];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (bad(rr_new)) {
+    if (lead) {
+      sc->iter = it + 1;
+      sc->done = 3;
+    }
+    return;
+  }
+  if (rr_new <= sc->thr) {
+    if (lead) {
+      sc->rr[(it + 1) & 1] = rr_new;
+      sc->iter = it + 1;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double beta_d = rr_new / rr;
+  if (lead) {
+    sc->rr[(it + 1) & 1] = rr_new;
+    sc->beta = beta_d;
+    sc->iter = it + 1;
+  }
+  const T beta = (T)beta_d;
+  constexpr int W = V16<T>::W;
   const size_t nv = N / W;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
     T pv[W], rv[W];
-    vload(p + v * W, pv);
-    vload(r + v * W, rv);
+    vld<T, W>(p + v * W, pv);
+    vld<T, W>(r + v * W, rv);
 #pragma unroll
     for (int k = 0; k < W; ++k) pv[k] = rv[k] + beta * pv[k];
-    vstore(p + v * W, pv);
+    vst<T, W>(p + v * W, pv);
   }
   for (size_t e = nv * W + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride)
     p[e] = r[e] + beta * p[e];
 }
 
-// Start of a CG solve from x = 0: x = 0, r = p = B, rr = <B, B>.
+// Start of a CG solve from x = 0: x = 0, r = p = B; partials of <B, B>.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_cg_init_zero(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
-               const T* __restrict__ B, size_t N, CgScal* sc, double thr_abs,
-               RedSlot slot) {
+               const T* __restrict__ B, size_t N, double* part) {
   double acc[1] = {0.0};
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
@@ -531,28 +592,54 @@ k_cg_init_zero(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
     p[e] = b;
     acc[0] += (double)b * (double)b;
   }
-  double tot[1];
-  if (grid_reduce<1>(acc, slot, tot) && threadIdx.x == 0) {
-    sc->rr = tot[0];
-    sc->thr = thr_abs;
-    sc->iter = 0;
-    sc->alpha = sc->beta = 0.0;
-    sc->done = bad(tot[0]) ? 3 : (tot[0] == 0.0 ? 1 : 0);
-  }
+  block_partials<1>(acc, part);
 }
 
-// Squared norm of a vector into *out (FP64).
+// Arms the CG scalars from partials (one workgroup):
+//   NV = 1: rr = total (start from zero), threshold thr_abs;
+//   NV = 2: residual start, res2 = total[0], rr = aux = total[1],
+//           threshold thr_abs if >= 0 else rel_tol2 * rr.
+template <int NV>
+__global__ void __launch_bounds__(kThreads)
+k_cg_arm(CgScal* sc, const double* part, int nb, double thr_abs, double rel_tol2) {
+  double t[NV];
+  sum_partials<NV>(part, nb, t);
+  if (threadIdx.x != 0) return;
+  const double rr = t[NV - 1];
+  const double thr = thr_abs >= 0.0 ? thr_abs : rel_tol2 * rr;
+  if (NV == 2) {
+    sc->res2 = t[0];
+    sc->aux = t[1];
+  }
+  sc->rr[0] = rr;
+  sc->rr[1] = rr;
+  sc->thr = thr;
+  sc->iter = 0;
+  sc->alpha = 0.0;
+  sc->beta = 0.0;
+  sc->done = (bad(t[0]) || bad(rr)) ? 3 : (rr <= thr ? 1 : 0);
+}
+
+// out[k] = sum of the partials (one workgroup).
+template <int NV>
+__global__ void __launch_bounds__(kThreads)
+k_sum_partials(const double* part, int nb, double* out) {
+  double t[NV];
+  sum_partials<NV>(part, nb, t);
+  if (threadIdx.x < NV) out[threadIdx.x] = t[threadIdx.x];
+}
+
+// Partials of ||a||^2.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_norm2(const T* __restrict__ a, size_t N, double* out, RedSlot slot) {
+k_norm2(const T* __restrict__ a, size_t N, double* part) {
   double acc[1] = {0.0};
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
     const double v = (double)a[e];
     acc[0] += v * v;
   }
-  double tot[1];
-  if (grid_reduce<1>(acc, slot, tot) && threadIdx.x == 0) *out = tot[0];
+  block_partials<1>(acc, part);
 }
 
 // X64 += d (refinement update).

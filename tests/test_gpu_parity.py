@@ -228,7 +228,8 @@ def test_decode_singular_gamma_zero_returns_scatter(cfg1):
     Xt = torch.from_numpy(P.Ytil).cuda()
     X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 0.0, 0.0)
     B = OD.rhs(P.Ytil, P.p, P.n, P.omega_r, P.omega_c)
-    assert info["iters"] == 1 and np.array_equal(host(X), B)
+    # one CG step: X = alpha B with alpha = <B,B>/<B,A B> = 1 up to summation order
+    assert info["iters"] == 1 and rel(host(X), B) <= 1e-14
 
 
 def test_decode_is_deterministic(cfg1):
