@@ -275,30 +275,25 @@ DevGraph<T> bind_graph(const GraphImage<T>& g, const char* dev) {
 struct ApplyCfg {
   int R = 1;
   bool lds = true;
-  int vec = 1;  // columns per thread (16-byte accesses when > 1)
+  int vpt = 4;  // columns per thread per pass
 };
 
 // Launch shape of the fused product for a p x n operand of `elem` bytes.
 ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem) {
   ApplyCfg c;
-  const int W = (int)(16 / elem);
-  c.vec = (n % W == 0) ? W : 1;
   const size_t row_bytes = (size_t)n * elem;
+  c.vpt = n >= 4 * kThreads ? 4 : (n >= 2 * kThreads ? 2 : 1);
   c.R = 1;
-  for (int R : {8, 4, 2}) {
-    if ((p + R - 1) / R >= 2048) {
-      c.R = R;
-      break;
-    }
-  }
-  c.lds = false;
+  if (p >= 4 * 2048 && 2 * row_bytes <= 32768) c.R = 2;
+  c.lds = row_bytes * c.R <= 65536;
   if (h->force_R > 0) c.R = h->force_R;
-  if (h->force_lds == 1 && (size_t)c.R * row_bytes <= 65536) c.lds = true;
+  if (h->force_lds == 1) c.lds = (size_t)c.R * row_bytes <= 65536;
   if (h->force_lds == 0) c.lds = false;
+  if (h->force_lds == -1) c.lds = (size_t)c.R * row_bytes <= 65536;
   return c;
 }
 
-int slice_height(const ApplyCfg& c) { return kWave * c.vec; }
+int slice_height(const ApplyCfg&) { return kWave; }
 
 int vec_grid(size_t N) {
   const size_t b = (N + kThreads - 1) / kThreads;
@@ -310,13 +305,13 @@ int apply_grid(const ApplyCfg& cfg, int p) {
   return 8 * ((nrb + 7) / 8);
 }
 
-template <typename T, int R, bool LDS, int VEC, class Epi>
+template <typename T, int R, bool LDS, int VPT, class Epi>
 hipError_t launch_apply_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
                           const Epi& epi) {
   const int nrb = (p + R - 1) / R;
   const int per = (nrb + 7) / 8;
   const size_t shmem = LDS ? (size_t)R * n * sizeof(T) : 0;
-  k_apply2<T, R, LDS, VEC, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
+  k_apply2<T, R, LDS, VPT, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
       X, p, n, g.Lr, g.Lc, g.mr, g.mc, nrb, per, epi);
   return hipGetLastError();
 }
@@ -324,13 +319,17 @@ hipError_t launch_apply_t(cpca_handle h, const T* X, int p, int n, const DevGrap
 template <typename T, int R, class Epi>
 hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
                           const DevGraph<T>& g, const Epi& epi) {
-  constexpr int W = (int)(16 / sizeof(T));
-  if (cfg.vec == W) {
-    return cfg.lds ? launch_apply_t<T, R, true, W>(h, X, p, n, g, epi)
-                   : launch_apply_t<T, R, false, W>(h, X, p, n, g, epi);
+  switch (cfg.vpt) {
+    case 4:
+      return cfg.lds ? launch_apply_t<T, R, true, 4>(h, X, p, n, g, epi)
+                     : launch_apply_t<T, R, false, 4>(h, X, p, n, g, epi);
+    case 2:
+      return cfg.lds ? launch_apply_t<T, R, true, 2>(h, X, p, n, g, epi)
+                     : launch_apply_t<T, R, false, 2>(h, X, p, n, g, epi);
+    default:
+      return cfg.lds ? launch_apply_t<T, R, true, 1>(h, X, p, n, g, epi)
+                     : launch_apply_t<T, R, false, 1>(h, X, p, n, g, epi);
   }
-  return cfg.lds ? launch_apply_t<T, R, true, 1>(h, X, p, n, g, epi)
-                 : launch_apply_t<T, R, false, 1>(h, X, p, n, g, epi);
 }
 
 template <typename T, class Epi>
@@ -966,8 +965,6 @@ template <typename T>
 cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_t p, int64_t n,
                       double gr, double gc, double* pq) {
   ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T));
-  // user buffers: fall back to scalar columns if they are not 16-byte aligned
-  if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Q)) % 16 != 0) cfg.vec = 1;
   Staging stg;
   const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg));
   const int ag = apply_grid(cfg, (int)p);

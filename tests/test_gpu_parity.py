@@ -72,10 +72,12 @@ def test_apply_matches_oracle_random_graphs(shape, dtype):
                       rtol=1e-12 if dtype == torch.float64 else 1e-5)
 
 
+@pytest.mark.parametrize("n", [333, 600, 1100])
 @pytest.mark.parametrize("R,lds", [(1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (4, 0)])
-def test_apply_every_launch_shape(R, lds):
-    _announce(f"apply launch shape R={R} lds={lds}")
-    P_ = synth.small_problem(3, p_shape=(11, 13), n=333, rank=3, frac=0.3)
+def test_apply_every_launch_shape(R, lds, n):
+    # n = 333 / 600 / 1100 selects 1 / 2 / 4 columns per thread, all ragged
+    _announce(f"apply launch shape R={R} lds={lds} n={n}")
+    P_ = synth.small_problem(3, p_shape=(11, 13), n=n, rank=3, frac=0.3)
     rng = np.random.default_rng(5)
     X = rng.standard_normal((P_.p, P_.n))
     m_r, m_c = OD.masks(P_.p, P_.n, P_.omega_r, P_.omega_c)
