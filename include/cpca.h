@@ -223,13 +223,68 @@ cpca_status cpca_get_profile(cpca_handle h, const char* family,
 
 /*
  * Launch shape of the fused two-sided product on this handle:
- * rows_per_block in {0, 1, 2, 4, 8} (0 = automatic choice), use_lds in
- * {-1, 0, 1} (-1 = automatic; 1 = stage the block's rows in LDS when they
- * fit in 64 KiB, 0 = gather X L_c operands from global memory).
- * Results do not depend on the shape beyond floating-point summation order
- * of the X L_c term (which stays fixed per shape).
+ * rows_per_block in {-1, 0, 1, 2, 4, 8}: 0 = built-in default, -1 = autotune
+ * (each new shape is timed over the candidate shapes on the first solve and
+ * the fastest is kept in the handle; with the environment variable
+ * CPCA_TUNE_CACHE naming a file, choices are also appended to it and read
+ * back by cpca_create). use_lds in {-1, 0, 1}: -1 = automatic, 1 = stage the
+ * workgroup's rows in LDS when they fit in 64 KiB, 0 = gather the X L_c
+ * operands from global memory. Each output element is computed in the same
+ * order for every shape; only the grid-level reduction order of the CG
+ * scalars depends on the number of workgroups.
  */
 cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_block, int32_t use_lds);
+
+/*
+ * Batched solves (many instances of uneven sizes, each swept over several
+ * (gamma_r, gamma_c) pairs): for every task, FISTA on the instance's sampled
+ * matrix (Algorithm 1, fista_iters iterations, eps = 0) followed by the
+ * alternate decoder on its full graphs, both with the task's gammas. In
+ * FP32 modes the sampled estimate X~ is rounded to float between the two
+ * stages, exactly as a cpca_frpcag call followed by cpca_decode would do.
+ *
+ * All tasks are resident on the device together and advance through
+ * batched kernels (one launch covers every task); FISTA and chunks of CG
+ * iterations are captured as HIP graphs and replayed until every task has
+ * converged. Memory: about (5 FP64 + 4 FP32) words per decoded entry in
+ * FP32_IR mode, summed over tasks.
+ *
+ * instances   n_instances descriptors; all pointers are device memory with
+ *             the same conventions as cpca_frpcag / cpca_decode.
+ * tasks       n_tasks descriptors: instance index, gammas (>= 0), X_out
+ *             (p x n, required) and Xtil_out (rho_r x rho_c, may be NULL).
+ * tol, max_iter  as in cpca_decode (per task).
+ * infos       optional host array of n_tasks results.
+ * Returns OK when every task converged; otherwise the first error status
+ * among the tasks (ENOCONV if that is the only problem). Outputs are written
+ * for every task either way.
+ */
+typedef struct {
+  int64_t p, n;                 /* full matrix size                           */
+  int64_t rho_r, rho_c;         /* sample counts                              */
+  const int32_t* omega_r;       /* sampled rows, distinct, in [0, p)          */
+  const int32_t* omega_c;       /* sampled columns, distinct, in [0, n)       */
+  const cpca_csr* Lr;           /* p x p Laplacian                            */
+  const cpca_csr* Lc;           /* n x n Laplacian                            */
+  const cpca_csr* Lr_til;       /* rho_r x rho_r Laplacian of sampled rows    */
+  const cpca_csr* Lc_til;       /* rho_c x rho_c Laplacian of sampled columns */
+  double lmax_r_til, lmax_c_til;/* their largest eigenvalues                  */
+  const void* Ytil;             /* rho_r x rho_c sampled data                 */
+} cpca_instance;
+
+typedef struct {
+  int32_t instance;             /* index into the instance array              */
+  int32_t reserved;
+  double gamma_r, gamma_c;      /* used by FISTA and by the decoder           */
+  void* X_out;                  /* p x n decoded matrix (mode dtype)          */
+  void* Xtil_out;               /* rho_r x rho_c FISTA output or NULL         */
+} cpca_task;
+
+cpca_status cpca_solve_batched(cpca_handle h, cpca_mode mode,
+                               const cpca_instance* instances, int32_t n_instances,
+                               const cpca_task* tasks, int32_t n_tasks,
+                               int32_t fista_iters, double tol, int32_t max_iter,
+                               cpca_info* infos);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,8 @@ MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2}
 EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
            "cpca_set_stream", "cpca_frpcag", "cpca_decode", "cpca_decode_backward",
            "cpca_apply", "cpca_check_csr_host", "cpca_check_index_set_host",
-           "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config"]
+           "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config",
+           "cpca_solve_batched"]
 
 
 class CpcaCsr(ctypes.Structure):
@@ -30,6 +31,19 @@ class CpcaInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class CpcaInstance(ctypes.Structure):
+    _fields_ = [("p", c_int64), ("n", c_int64), ("rho_r", c_int64), ("rho_c", c_int64),
+                ("omega_r", c_void_p), ("omega_c", c_void_p),
+                ("Lr", ctypes.POINTER(CpcaCsr)), ("Lc", ctypes.POINTER(CpcaCsr)),
+                ("Lr_til", ctypes.POINTER(CpcaCsr)), ("Lc_til", ctypes.POINTER(CpcaCsr)),
+                ("lmax_r_til", c_double), ("lmax_c_til", c_double), ("Ytil", c_void_p)]
+
+
+class CpcaTask(ctypes.Structure):
+    _fields_ = [("instance", c_int32), ("reserved", c_int32), ("gamma_r", c_double),
+                ("gamma_c", c_double), ("X_out", c_void_p), ("Xtil_out", c_void_p)]
 
 
 _lib = None
@@ -60,6 +74,8 @@ def _declare(lib):
         "cpca_set_profiling": (st, [P, c_int32]),
         "cpca_get_profile": (st, [P, c_char_p, POINTER(c_int64), POINTER(c_double)]),
         "cpca_set_apply_config": (st, [P, c_int32, c_int32]),
+        "cpca_solve_batched": (st, [P, c_int32, POINTER(CpcaInstance), c_int32, POINTER(CpcaTask),
+                                    c_int32, c_int32, c_double, c_int32, POINTER(CpcaInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

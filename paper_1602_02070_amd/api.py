@@ -14,11 +14,11 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import CpcaCsr, CpcaInfo
+from ._lib import CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
 
 __all__ = ["CpcaError", "Graph", "handle", "frpcag", "decode", "decode_backward",
            "apply_operator", "Decode", "DecodeProblem", "profiling", "get_profile",
-           "mode_for", "set_apply_config"]
+           "mode_for", "set_apply_config", "Instance", "solve_batched"]
 
 
 class CpcaError(RuntimeError):
@@ -275,3 +275,59 @@ class Decode(torch.autograd.Function):
                                            ctx.g[0], ctx.g[1], prob.tol, prob.max_iter, prob.mode)
         return (dXt, torch.tensor(dgr, dtype=ctx.gdt[0], device=X.device),
                 torch.tensor(dgc, dtype=ctx.gdt[1], device=X.device), None)
+
+
+# ------------------------------------------------------------------ batched
+@dataclasses.dataclass
+class Instance:
+    """One problem of a batched solve: graphs, sampling sets and sampled data
+    (all on the GPU)."""
+    p: int
+    n: int
+    omega_r: torch.Tensor
+    omega_c: torch.Tensor
+    Lr: Graph
+    Lc: Graph
+    Lr_til: Graph
+    Lc_til: Graph
+    lmax_r_til: float
+    lmax_c_til: float
+    Ytil: torch.Tensor
+
+
+def solve_batched(instances, tasks, fista_iters: int = 500, tol: float = 1e-9,
+                  max_iter: int = 20000, mode: str | None = None, want_xtil: bool = False):
+    """FISTA + alternate decoder for every task (instance index, gamma_r,
+    gamma_c) in one batched run. Returns (X list, X~ list or None, infos)."""
+    if not instances or not tasks:
+        raise ValueError("need at least one instance and one task")
+    mode = mode_for(instances[0].Ytil.dtype, mode)
+    dt = _dtype_of(mode)
+    keep = []
+    cin = (CpcaInstance * len(instances))()
+    for k, I in enumerate(instances):
+        Y = _need(I.Ytil, f"instances[{k}].Ytil", dt)
+        om_r = _index(I.omega_r, "omega_r")
+        om_c = _index(I.omega_c, "omega_c")
+        keep += [Y, om_r, om_c]
+        cin[k] = CpcaInstance(int(I.p), int(I.n), om_r.numel(), om_c.numel(), om_r.data_ptr(),
+                              om_c.data_ptr(), ctypes.pointer(I.Lr.desc), ctypes.pointer(I.Lc.desc),
+                              ctypes.pointer(I.Lr_til.desc), ctypes.pointer(I.Lc_til.desc),
+                              float(I.lmax_r_til), float(I.lmax_c_til), Y.data_ptr())
+    outs, xts = [], []
+    ctk = (CpcaTask * len(tasks))()
+    for t, (inst, gr, gc) in enumerate(tasks):
+        I = instances[inst]
+        X = torch.empty((I.p, I.n), dtype=dt, device=I.Ytil.device)
+        Xt = (torch.empty((I.omega_r.numel(), I.omega_c.numel()), dtype=dt, device=X.device)
+              if want_xtil else None)
+        outs.append(X)
+        xts.append(Xt)
+        ctk[t] = CpcaTask(int(inst), 0, float(gr), float(gc), X.data_ptr(),
+                          None if Xt is None else Xt.data_ptr())
+    infos = (CpcaInfo * len(tasks))()
+    st = _lib.load().cpca_solve_batched(handle(instances[0].Ytil.device), _lib.MODES[mode], cin,
+                                        len(instances), ctk, len(tasks), int(fista_iters),
+                                        float(tol), int(max_iter), infos)
+    _check(st, "cpca_solve_batched")
+    return outs, (xts if want_xtil else None), [i.as_dict() for i in infos]

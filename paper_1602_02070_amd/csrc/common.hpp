@@ -1,0 +1,469 @@
+// Host-side internals shared by the single-problem drivers (engine.hip) and
+// the batched driver (batched.hip): the handle, workspace, profiling, graph
+// preparation (validation + device layouts) and launch helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cpca.h"
+#include "kernels.hpp"
+#include "validate.hpp"
+
+using namespace cpca;
+
+namespace {
+
+// apply: the CG operator application; other: residual / objective / dot launches
+enum Family { FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_COUNT = 4 };
+
+}  // namespace
+
+struct cpca_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;          // workspace (device)
+  size_t ws_cap = 0;
+  char* fixed = nullptr;       // counters + scalars (device), zeroed at creation
+  void* pinned = nullptr;      // host mirror of the scalars
+  int force_R = 0;             // launch-shape override (0: default, -1: autotune)
+  int force_lds = -1;          // LDS override (-1: default)
+  std::vector<std::pair<std::string, std::pair<int, int>>> tuned;  // autotuner cache
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<int> ev_fam;
+  size_t ev_used = 0;
+  int64_t prof_n[FAM_COUNT] = {0, 0, 0, 0};
+  double prof_ms[FAM_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+// Layout of the `fixed` device block.
+constexpr size_t kOffCg = 256;             // CgScal[2]
+constexpr size_t kOffFista = 512;          // FistaScal
+constexpr size_t kOffResults = 768;        // double[32]
+constexpr size_t kFixedBytes = 1024;
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      return fail(_e == hipErrorOutOfMemory ? CPCA_ENOMEM : CPCA_EHIP,            \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));             \
+    }                                                                             \
+  } while (0)
+
+#define STCHK(expr)                   \
+  do {                                \
+    cpca_status _s = (expr);          \
+    if (_s != CPCA_OK) return _s;     \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Two-pass bump allocator: the first pass (base == nullptr) only measures.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+cpca_status ensure_ws(cpca_handle h, size_t bytes) {
+  if (bytes <= h->ws_cap) return CPCA_OK;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (h->ws) HIPCHK(hipFree(h->ws));
+  h->ws = nullptr;
+  h->ws_cap = 0;
+  const size_t cap = align_up(bytes + bytes / 8, 1 << 20);
+  HIPCHK(hipMalloc(&h->ws, cap));
+  h->ws_cap = cap;
+  return CPCA_OK;
+}
+
+CgScal* cg_ptr(cpca_handle h, int k = 0) { return reinterpret_cast<CgScal*>(h->fixed + kOffCg) + k; }
+FistaScal* fista_ptr(cpca_handle h) { return reinterpret_cast<FistaScal*>(h->fixed + kOffFista); }
+double* results_ptr(cpca_handle h) { return reinterpret_cast<double*>(h->fixed + kOffResults); }
+
+// Copy the fixed scalar block to the pinned mirror and wait.
+cpca_status read_fixed(cpca_handle h) {
+  HIPCHK(hipMemcpyAsync(h->pinned, h->fixed, kFixedBytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return CPCA_OK;
+}
+const CgScal& host_cg(cpca_handle h, int k = 0) {
+  return reinterpret_cast<const CgScal*>(static_cast<char*>(h->pinned) + kOffCg)[k];
+}
+const FistaScal& host_fista(cpca_handle h) {
+  return *reinterpret_cast<const FistaScal*>(static_cast<char*>(h->pinned) + kOffFista);
+}
+const double* host_results(cpca_handle h) {
+  return reinterpret_cast<const double*>(static_cast<char*>(h->pinned) + kOffResults);
+}
+
+// ---------------------------------------------------------------- profiling
+cpca_status prof_begin(cpca_handle h, int fam) {
+  if (!h->prof) return CPCA_OK;
+  if (2 * h->ev_used + 2 > h->ev.size()) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    h->ev.push_back(a);
+    h->ev.push_back(b);
+    h->ev_fam.push_back(fam);
+  }
+  h->ev_fam[h->ev_used] = fam;
+  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used], h->stream));
+  return CPCA_OK;
+}
+cpca_status prof_end(cpca_handle h) {
+  if (!h->prof) return CPCA_OK;
+  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream));
+  ++h->ev_used;
+  return CPCA_OK;
+}
+// Only after the stream has been synchronised.
+cpca_status prof_collect(cpca_handle h) {
+  if (!h->prof) return CPCA_OK;
+  for (size_t k = 0; k < h->ev_used; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
+    h->prof_n[h->ev_fam[k]] += 1;
+    h->prof_ms[h->ev_fam[k]] += ms;
+  }
+  h->ev_used = 0;
+  return CPCA_OK;
+}
+cpca_status sync_collect(cpca_handle h) {
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return prof_collect(h);
+}
+
+// ------------------------------------------------------------- preparation
+struct HostCsr {
+  int64_t n = 0, nnz = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+};
+
+cpca_status fetch_csr(const char* name, const cpca_csr* A, HostCsr& out) {
+  out.n = A->n;
+  out.nnz = A->nnz;
+  out.rp.resize((size_t)A->n + 1);
+  out.ci.resize((size_t)std::max<int64_t>(A->nnz, 1));
+  out.v.resize((size_t)std::max<int64_t>(A->nnz, 1));
+  HIPCHK(hipMemcpy(out.rp.data(), A->rowptr, sizeof(int32_t) * (A->n + 1), hipMemcpyDefault));
+  if (A->nnz > 0) {
+    HIPCHK(hipMemcpy(out.ci.data(), A->colind, sizeof(int32_t) * A->nnz, hipMemcpyDefault));
+    HIPCHK(hipMemcpy(out.v.data(), A->vals, sizeof(double) * A->nnz, hipMemcpyDefault));
+  }
+  return check_csr_host(name, out.n, out.nnz, out.rp.data(), out.ci.data(), out.v.data());
+}
+
+cpca_status fetch_index_set(const char* name, const int32_t* idx, int64_t count, int64_t dim,
+                            std::vector<uint8_t>& mask) {
+  std::vector<int32_t> h((size_t)std::max<int64_t>(count, 1));
+  if (count > 0) HIPCHK(hipMemcpy(h.data(), idx, sizeof(int32_t) * count, hipMemcpyDefault));
+  return check_index_set_host(name, count, dim, h.data(), &mask);
+}
+
+// Device image of one operator (L_r CSR, L_c SELL, masks) in type T, packed
+// into a single host staging buffer and copied with one transfer.
+template <typename T>
+struct DevGraph {
+  CsrDev<T> Lr{};
+  SellDev<T> Lc{};
+  const uint8_t* mr = nullptr;
+  const uint8_t* mc = nullptr;
+};
+
+struct Staging {
+  std::vector<char> buf;
+  size_t add(const void* src, size_t bytes) {
+    const size_t off = align_up(buf.size(), 256);
+    buf.resize(off + bytes);
+    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+    return off;
+  }
+};
+
+template <typename T>
+struct GraphImage {
+  size_t o_rp, o_ci, o_v, o_sp, o_sci, o_sv, o_mr, o_mc;
+};
+
+template <typename T>
+GraphImage<T> stage_graph(Staging& st, const HostCsr& Lr, const HostCsr& Lc,
+                          const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int H) {
+  GraphImage<T> g{};
+  std::vector<T> vr(Lr.v.begin(), Lr.v.begin() + Lr.nnz);
+  g.o_rp = st.add(Lr.rp.data(), sizeof(int32_t) * Lr.rp.size());
+  g.o_ci = st.add(Lr.ci.data(), sizeof(int32_t) * std::max<int64_t>(Lr.nnz, 1));
+  g.o_v = st.add(vr.data(), sizeof(T) * vr.size());
+  // sliced ELL of L_c, slice height H
+  const int64_t n = Lc.n;
+  const int64_t ns = (n + H - 1) / H;
+  std::vector<int32_t> sp((size_t)ns + 1, 0);
+  for (int64_t s = 0; s < ns; ++s) {
+    int w = 0;
+    for (int64_t j = s * H; j < std::min<int64_t>(n, (s + 1) * H); ++j)
+      w = std::max(w, Lc.rp[j + 1] - Lc.rp[j]);
+    sp[s + 1] = sp[s] + w * H;
+  }
+  std::vector<int32_t> sci((size_t)std::max(sp[ns], 1), 0);
+  std::vector<T> sv((size_t)std::max(sp[ns], 1), T(0));
+  for (int64_t s = 0; s < ns; ++s) {
+    const int w = (sp[s + 1] - sp[s]) / H;
+    for (int lane = 0; lane < H; ++lane) {
+      const int64_t j = s * H + lane;
+      const int deg = j < n ? Lc.rp[j + 1] - Lc.rp[j] : 0;
+      for (int e = 0; e < w; ++e) {
+        const size_t pos = (size_t)sp[s] + (size_t)e * H + lane;
+        if (e < deg) {
+          sci[pos] = Lc.ci[Lc.rp[j] + e];
+          sv[pos] = (T)Lc.v[Lc.rp[j] + e];
+        } else {
+          sci[pos] = j < n ? (int32_t)j : 0;
+          sv[pos] = T(0);
+        }
+      }
+    }
+  }
+  g.o_sp = st.add(sp.data(), sizeof(int32_t) * sp.size());
+  g.o_sci = st.add(sci.data(), sizeof(int32_t) * sci.size());
+  g.o_sv = st.add(sv.data(), sizeof(T) * sv.size());
+  g.o_mr = st.add(mr.data(), mr.size());
+  g.o_mc = st.add(mc.data(), mc.size());
+  return g;
+}
+
+template <typename T>
+DevGraph<T> bind_graph(const GraphImage<T>& g, const char* dev) {
+  DevGraph<T> d;
+  d.Lr.rp = reinterpret_cast<const int*>(dev + g.o_rp);
+  d.Lr.ci = reinterpret_cast<const int*>(dev + g.o_ci);
+  d.Lr.v = reinterpret_cast<const T*>(dev + g.o_v);
+  d.Lc.sp = reinterpret_cast<const int*>(dev + g.o_sp);
+  d.Lc.ci = reinterpret_cast<const int*>(dev + g.o_sci);
+  d.Lc.v = reinterpret_cast<const T*>(dev + g.o_sv);
+  d.mr = reinterpret_cast<const uint8_t*>(dev + g.o_mr);
+  d.mc = reinterpret_cast<const uint8_t*>(dev + g.o_mc);
+  return d;
+}
+
+// ------------------------------------------------------------------ launch
+struct ApplyCfg {
+  int R = 1;
+  bool lds = true;
+  int vec = 1;  // columns per thread (16-byte accesses when > 1)
+};
+
+// Launch shape of the fused product for a p x n operand of `elem` bytes.
+// Default: one row per workgroup staged in LDS (the fastest shape measured
+// for banded and K-NN graphs); two rows through the L1 when a row does not
+// fit in 64 KiB of LDS.
+ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem) {
+  ApplyCfg c;
+  const int W = (int)(16 / elem);
+  c.vec = (n % W == 0) ? W : 1;
+  const size_t row_bytes = (size_t)n * elem;
+  c.R = 1;
+  c.lds = row_bytes <= 65536;
+  if (!c.lds && p >= 4096) c.R = 2;
+  if (h->force_R > 0) c.R = h->force_R;
+  if (h->force_lds == 1) c.lds = (size_t)c.R * row_bytes <= 65536;
+  if (h->force_lds == 0) c.lds = false;
+  if (h->force_lds == -1 && h->force_R > 0) c.lds = (size_t)c.R * row_bytes <= 65536;
+  return c;
+}
+
+int slice_height(const ApplyCfg& c) { return kWave * c.vec; }
+
+int vec_grid(size_t N) {
+  const size_t b = (N + kThreads - 1) / kThreads;
+  return (int)std::max<size_t>(1, std::min<size_t>(b, 2048));
+}
+
+int apply_grid(const ApplyCfg& cfg, int p) {
+  const int nrb = (p + cfg.R - 1) / cfg.R;
+  return 8 * ((nrb + 7) / 8);
+}
+
+template <typename T, int R, bool LDS, int VEC, class Epi>
+hipError_t launch_apply_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
+                          const Epi& epi) {
+  const int nrb = (p + R - 1) / R;
+  const int per = (nrb + 7) / 8;
+  const size_t shmem = LDS ? (size_t)R * n * sizeof(T) : 0;
+  k_apply2<T, R, LDS, VEC, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
+      X, p, n, g.Lr, g.Lc, g.mr, g.mc, nrb, per, epi);
+  return hipGetLastError();
+}
+
+template <typename T, int R, class Epi>
+hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
+                          const DevGraph<T>& g, const Epi& epi) {
+  constexpr int W = (int)(16 / sizeof(T));
+  if (cfg.vec == W) {
+    return cfg.lds ? launch_apply_t<T, R, true, W>(h, X, p, n, g, epi)
+                   : launch_apply_t<T, R, false, W>(h, X, p, n, g, epi);
+  }
+  return cfg.lds ? launch_apply_t<T, R, true, 1>(h, X, p, n, g, epi)
+                 : launch_apply_t<T, R, false, 1>(h, X, p, n, g, epi);
+}
+
+template <typename T, class Epi>
+cpca_status launch_apply(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
+                         const DevGraph<T>& g, const Epi& epi, int fam) {
+  STCHK(prof_begin(h, fam));
+  hipError_t e;
+  switch (cfg.R) {
+    case 1: e = launch_apply_r<T, 1>(h, cfg, X, p, n, g, epi); break;
+    case 2: e = launch_apply_r<T, 2>(h, cfg, X, p, n, g, epi); break;
+    case 4: e = launch_apply_r<T, 4>(h, cfg, X, p, n, g, epi); break;
+    case 8: e = launch_apply_r<T, 8>(h, cfg, X, p, n, g, epi); break;
+    default: return fail(CPCA_EINVAL, "unsupported rows per workgroup");
+  }
+  if (e != hipSuccess) return fail(CPCA_EHIP, std::string("apply launch: ") + hipGetErrorString(e));
+  return prof_end(h);
+}
+
+#define LAUNCHCHK()                                                                        \
+  do {                                                                                     \
+    hipError_t _e = hipGetLastError();                                                     \
+    if (_e != hipSuccess) return fail(CPCA_EHIP, std::string("launch: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+
+// ------------------------------------------------------------------ status
+constexpr int kMaxOuter = 40;  // refinement steps per solve
+
+cpca_status done_status(int done) {
+  switch (done) {
+    case 1: return CPCA_OK;
+    case 2: return fail(CPCA_ENOTSPD, "CG breakdown: <p, A p> <= 0");
+    case 3: return fail(CPCA_ENAN, "NaN or Inf in the iteration");
+    default: return fail(CPCA_ENOCONV, "iteration limit reached before the tolerance");
+  }
+}
+
+void fill_info(cpca_info* info, cpca_status st, int iters, int outer, double rel, double obj,
+               std::chrono::steady_clock::time_point t0) {
+  if (!info) return;
+  info->iters = iters;
+  info->outer_iters = outer;
+  info->status = (int32_t)st;
+  info->reserved = 0;
+  info->rel_residual = rel;
+  info->objective = obj;
+  info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+
+// --------------------------------------------------------------- autotuner
+// Launch-shape autotuning of the fused product: each candidate (rows per
+// workgroup, LDS staging) is timed over a few launches on the real operand
+// and the fastest is kept in the handle, keyed by element type and shape.
+// With CPCA_TUNE_CACHE set, choices are also appended to that file and read
+// back when a handle is created.
+inline std::string tune_key(const char* kind, size_t elem, int64_t p, int64_t n, int64_t nnz) {
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s:f%zu:p%lld:n%lld:z%lld", kind, elem * 8, (long long)p,
+                (long long)n, (long long)nnz);
+  return buf;
+}
+
+inline bool tune_lookup(cpca_handle h, const std::string& key, ApplyCfg& c) {
+  for (const auto& kv : h->tuned)
+    if (kv.first == key) {
+      c.R = kv.second.first;
+      c.lds = kv.second.second != 0;
+      return true;
+    }
+  return false;
+}
+
+inline void tune_store(cpca_handle h, const std::string& key, const ApplyCfg& c) {
+  h->tuned.push_back({key, {c.R, c.lds ? 1 : 0}});
+  if (const char* path = std::getenv("CPCA_TUNE_CACHE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %d %d\n", key.c_str(), c.R, c.lds ? 1 : 0);
+      std::fclose(f);
+    }
+  }
+}
+
+inline void tune_load_file(cpca_handle h) {
+  const char* path = std::getenv("CPCA_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[200];
+  int R, lds;
+  while (std::fscanf(f, "%199s %d %d", key, &R, &lds) == 3) {
+    if (R == 1 || R == 2 || R == 4 || R == 8) h->tuned.push_back({key, {R, lds}});
+  }
+  std::fclose(f);
+}
+
+// Times `reps` calls of `launch(cfg)` for every candidate and returns the
+// fastest. `launch` enqueues one kernel and returns a status.
+template <class F>
+cpca_status autotune(cpca_handle h, const std::string& key, size_t row_bytes, ApplyCfg base,
+                     F launch, ApplyCfg* best) {
+  if (tune_lookup(h, key, *best)) {
+    best->vec = base.vec;
+    return CPCA_OK;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  *best = base;
+  const int Rs[] = {1, 2, 4};
+  cpca_status st = CPCA_OK;
+  for (int lds = 1; lds >= 0 && st == CPCA_OK; --lds) {
+    for (int R : Rs) {
+      if (lds && (size_t)R * row_bytes > 65536) continue;
+      ApplyCfg c = base;
+      c.R = R;
+      c.lds = lds != 0;
+      if ((st = launch(c)) != CPCA_OK) break;  // warm-up
+      if (hipEventRecord(e0, h->stream) != hipSuccess) {
+        st = fail(CPCA_EHIP, "autotune: event record failed");
+        break;
+      }
+      for (int k = 0; k < 3 && st == CPCA_OK; ++k) st = launch(c);
+      if (st != CPCA_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(CPCA_EHIP, "autotune: event timing failed");
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        *best = c;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == CPCA_OK) tune_store(h, key, *best);
+  return st;
+}
+
+}  // namespace

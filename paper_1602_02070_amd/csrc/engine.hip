@@ -10,349 +10,9 @@
 // layouts (CSR of L_r in the compute type, sliced ELL of L_c, 0/1 masks),
 // then runs entirely on the handle's stream. Convergence scalars stay on
 // the device; the host polls them at geometrically growing intervals.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <chrono>
-#include <cmath>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "cpca.h"
-#include "kernels.hpp"
-#include "validate.hpp"
-
-using namespace cpca;
+#include "common.hpp"
 
 namespace {
-
-// apply: the CG operator application; other: residual / objective / dot launches
-enum Family { FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_COUNT = 4 };
-
-}  // namespace
-
-struct cpca_handle_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;          // workspace (device)
-  size_t ws_cap = 0;
-  char* fixed = nullptr;       // counters + scalars (device), zeroed at creation
-  void* pinned = nullptr;      // host mirror of the scalars
-  int force_R = 0;             // tuning override (CPCA_APPLY_R)
-  int force_lds = -1;          // tuning override (CPCA_APPLY_LDS)
-  bool prof = false;
-  std::vector<hipEvent_t> ev;  // pairs (start, stop)
-  std::vector<int> ev_fam;
-  size_t ev_used = 0;
-  int64_t prof_n[FAM_COUNT] = {0, 0, 0, 0};
-  double prof_ms[FAM_COUNT] = {0, 0, 0, 0};
-};
-
-namespace {
-
-// Layout of the `fixed` device block.
-constexpr size_t kOffCg = 256;             // CgScal[2]
-constexpr size_t kOffFista = 512;          // FistaScal
-constexpr size_t kOffResults = 768;        // double[32]
-constexpr size_t kFixedBytes = 1024;
-
-#define HIPCHK(expr)                                                              \
-  do {                                                                            \
-    hipError_t _e = (expr);                                                       \
-    if (_e != hipSuccess) {                                                       \
-      return fail(_e == hipErrorOutOfMemory ? CPCA_ENOMEM : CPCA_EHIP,            \
-                  std::string(#expr) + ": " + hipGetErrorString(_e));             \
-    }                                                                             \
-  } while (0)
-
-#define STCHK(expr)                   \
-  do {                                \
-    cpca_status _s = (expr);          \
-    if (_s != CPCA_OK) return _s;     \
-  } while (0)
-
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-// Two-pass bump allocator: the first pass (base == nullptr) only measures.
-struct Arena {
-  char* base = nullptr;
-  size_t off = 0;
-  template <typename T>
-  T* take(size_t count) {
-    off = align_up(off, 256);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += count * sizeof(T);
-    return p;
-  }
-};
-
-cpca_status ensure_ws(cpca_handle h, size_t bytes) {
-  if (bytes <= h->ws_cap) return CPCA_OK;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  if (h->ws) HIPCHK(hipFree(h->ws));
-  h->ws = nullptr;
-  h->ws_cap = 0;
-  const size_t cap = align_up(bytes + bytes / 8, 1 << 20);
-  HIPCHK(hipMalloc(&h->ws, cap));
-  h->ws_cap = cap;
-  return CPCA_OK;
-}
-
-CgScal* cg_ptr(cpca_handle h, int k = 0) { return reinterpret_cast<CgScal*>(h->fixed + kOffCg) + k; }
-FistaScal* fista_ptr(cpca_handle h) { return reinterpret_cast<FistaScal*>(h->fixed + kOffFista); }
-double* results_ptr(cpca_handle h) { return reinterpret_cast<double*>(h->fixed + kOffResults); }
-
-// Copy the fixed scalar block to the pinned mirror and wait.
-cpca_status read_fixed(cpca_handle h) {
-  HIPCHK(hipMemcpyAsync(h->pinned, h->fixed, kFixedBytes, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return CPCA_OK;
-}
-const CgScal& host_cg(cpca_handle h, int k = 0) {
-  return reinterpret_cast<const CgScal*>(static_cast<char*>(h->pinned) + kOffCg)[k];
-}
-const FistaScal& host_fista(cpca_handle h) {
-  return *reinterpret_cast<const FistaScal*>(static_cast<char*>(h->pinned) + kOffFista);
-}
-const double* host_results(cpca_handle h) {
-  return reinterpret_cast<const double*>(static_cast<char*>(h->pinned) + kOffResults);
-}
-
-// ---------------------------------------------------------------- profiling
-cpca_status prof_begin(cpca_handle h, int fam) {
-  if (!h->prof) return CPCA_OK;
-  if (2 * h->ev_used + 2 > h->ev.size()) {
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
-    h->ev.push_back(a);
-    h->ev.push_back(b);
-    h->ev_fam.push_back(fam);
-  }
-  h->ev_fam[h->ev_used] = fam;
-  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used], h->stream));
-  return CPCA_OK;
-}
-cpca_status prof_end(cpca_handle h) {
-  if (!h->prof) return CPCA_OK;
-  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream));
-  ++h->ev_used;
-  return CPCA_OK;
-}
-// Only after the stream has been synchronised.
-cpca_status prof_collect(cpca_handle h) {
-  if (!h->prof) return CPCA_OK;
-  for (size_t k = 0; k < h->ev_used; ++k) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
-    h->prof_n[h->ev_fam[k]] += 1;
-    h->prof_ms[h->ev_fam[k]] += ms;
-  }
-  h->ev_used = 0;
-  return CPCA_OK;
-}
-cpca_status sync_collect(cpca_handle h) {
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return prof_collect(h);
-}
-
-// ------------------------------------------------------------- preparation
-struct HostCsr {
-  int64_t n = 0, nnz = 0;
-  std::vector<int32_t> rp, ci;
-  std::vector<double> v;
-};
-
-cpca_status fetch_csr(const char* name, const cpca_csr* A, HostCsr& out) {
-  out.n = A->n;
-  out.nnz = A->nnz;
-  out.rp.resize((size_t)A->n + 1);
-  out.ci.resize((size_t)std::max<int64_t>(A->nnz, 1));
-  out.v.resize((size_t)std::max<int64_t>(A->nnz, 1));
-  HIPCHK(hipMemcpy(out.rp.data(), A->rowptr, sizeof(int32_t) * (A->n + 1), hipMemcpyDefault));
-  if (A->nnz > 0) {
-    HIPCHK(hipMemcpy(out.ci.data(), A->colind, sizeof(int32_t) * A->nnz, hipMemcpyDefault));
-    HIPCHK(hipMemcpy(out.v.data(), A->vals, sizeof(double) * A->nnz, hipMemcpyDefault));
-  }
-  return check_csr_host(name, out.n, out.nnz, out.rp.data(), out.ci.data(), out.v.data());
-}
-
-cpca_status fetch_index_set(const char* name, const int32_t* idx, int64_t count, int64_t dim,
-                            std::vector<uint8_t>& mask) {
-  std::vector<int32_t> h((size_t)std::max<int64_t>(count, 1));
-  if (count > 0) HIPCHK(hipMemcpy(h.data(), idx, sizeof(int32_t) * count, hipMemcpyDefault));
-  return check_index_set_host(name, count, dim, h.data(), &mask);
-}
-
-// Device image of one operator (L_r CSR, L_c SELL, masks) in type T, packed
-// into a single host staging buffer and copied with one transfer.
-template <typename T>
-struct DevGraph {
-  CsrDev<T> Lr{};
-  SellDev<T> Lc{};
-  const uint8_t* mr = nullptr;
-  const uint8_t* mc = nullptr;
-};
-
-struct Staging {
-  std::vector<char> buf;
-  size_t add(const void* src, size_t bytes) {
-    const size_t off = align_up(buf.size(), 256);
-    buf.resize(off + bytes);
-    if (bytes) std::memcpy(buf.data() + off, src, bytes);
-    return off;
-  }
-};
-
-template <typename T>
-struct GraphImage {
-  size_t o_rp, o_ci, o_v, o_sp, o_sci, o_sv, o_mr, o_mc;
-};
-
-template <typename T>
-GraphImage<T> stage_graph(Staging& st, const HostCsr& Lr, const HostCsr& Lc,
-                          const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int H) {
-  GraphImage<T> g{};
-  std::vector<T> vr(Lr.v.begin(), Lr.v.begin() + Lr.nnz);
-  g.o_rp = st.add(Lr.rp.data(), sizeof(int32_t) * Lr.rp.size());
-  g.o_ci = st.add(Lr.ci.data(), sizeof(int32_t) * std::max<int64_t>(Lr.nnz, 1));
-  g.o_v = st.add(vr.data(), sizeof(T) * vr.size());
-  // sliced ELL of L_c, slice height H
-  const int64_t n = Lc.n;
-  const int64_t ns = (n + H - 1) / H;
-  std::vector<int32_t> sp((size_t)ns + 1, 0);
-  for (int64_t s = 0; s < ns; ++s) {
-    int w = 0;
-    for (int64_t j = s * H; j < std::min<int64_t>(n, (s + 1) * H); ++j)
-      w = std::max(w, Lc.rp[j + 1] - Lc.rp[j]);
-    sp[s + 1] = sp[s] + w * H;
-  }
-  std::vector<int32_t> sci((size_t)std::max(sp[ns], 1), 0);
-  std::vector<T> sv((size_t)std::max(sp[ns], 1), T(0));
-  for (int64_t s = 0; s < ns; ++s) {
-    const int w = (sp[s + 1] - sp[s]) / H;
-    for (int lane = 0; lane < H; ++lane) {
-      const int64_t j = s * H + lane;
-      const int deg = j < n ? Lc.rp[j + 1] - Lc.rp[j] : 0;
-      for (int e = 0; e < w; ++e) {
-        const size_t pos = (size_t)sp[s] + (size_t)e * H + lane;
-        if (e < deg) {
-          sci[pos] = Lc.ci[Lc.rp[j] + e];
-          sv[pos] = (T)Lc.v[Lc.rp[j] + e];
-        } else {
-          sci[pos] = j < n ? (int32_t)j : 0;
-          sv[pos] = T(0);
-        }
-      }
-    }
-  }
-  g.o_sp = st.add(sp.data(), sizeof(int32_t) * sp.size());
-  g.o_sci = st.add(sci.data(), sizeof(int32_t) * sci.size());
-  g.o_sv = st.add(sv.data(), sizeof(T) * sv.size());
-  g.o_mr = st.add(mr.data(), mr.size());
-  g.o_mc = st.add(mc.data(), mc.size());
-  return g;
-}
-
-template <typename T>
-DevGraph<T> bind_graph(const GraphImage<T>& g, const char* dev) {
-  DevGraph<T> d;
-  d.Lr.rp = reinterpret_cast<const int*>(dev + g.o_rp);
-  d.Lr.ci = reinterpret_cast<const int*>(dev + g.o_ci);
-  d.Lr.v = reinterpret_cast<const T*>(dev + g.o_v);
-  d.Lc.sp = reinterpret_cast<const int*>(dev + g.o_sp);
-  d.Lc.ci = reinterpret_cast<const int*>(dev + g.o_sci);
-  d.Lc.v = reinterpret_cast<const T*>(dev + g.o_sv);
-  d.mr = reinterpret_cast<const uint8_t*>(dev + g.o_mr);
-  d.mc = reinterpret_cast<const uint8_t*>(dev + g.o_mc);
-  return d;
-}
-
-// ------------------------------------------------------------------ launch
-struct ApplyCfg {
-  int R = 1;
-  bool lds = true;
-  int vpt = 4;  // columns per thread per pass
-};
-
-// Launch shape of the fused product for a p x n operand of `elem` bytes.
-ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem) {
-  ApplyCfg c;
-  const size_t row_bytes = (size_t)n * elem;
-  c.vpt = n >= 4 * kThreads ? 4 : (n >= 2 * kThreads ? 2 : 1);
-  c.R = 1;
-  if (p >= 4 * 2048 && 2 * row_bytes <= 32768) c.R = 2;
-  c.lds = row_bytes * c.R <= 65536;
-  if (h->force_R > 0) c.R = h->force_R;
-  if (h->force_lds == 1) c.lds = (size_t)c.R * row_bytes <= 65536;
-  if (h->force_lds == 0) c.lds = false;
-  if (h->force_lds == -1) c.lds = (size_t)c.R * row_bytes <= 65536;
-  return c;
-}
-
-int slice_height(const ApplyCfg&) { return kWave; }
-
-int vec_grid(size_t N) {
-  const size_t b = (N + kThreads - 1) / kThreads;
-  return (int)std::max<size_t>(1, std::min<size_t>(b, 2048));
-}
-
-int apply_grid(const ApplyCfg& cfg, int p) {
-  const int nrb = (p + cfg.R - 1) / cfg.R;
-  return 8 * ((nrb + 7) / 8);
-}
-
-template <typename T, int R, bool LDS, int VPT, class Epi>
-hipError_t launch_apply_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
-                          const Epi& epi) {
-  const int nrb = (p + R - 1) / R;
-  const int per = (nrb + 7) / 8;
-  const size_t shmem = LDS ? (size_t)R * n * sizeof(T) : 0;
-  k_apply2<T, R, LDS, VPT, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
-      X, p, n, g.Lr, g.Lc, g.mr, g.mc, nrb, per, epi);
-  return hipGetLastError();
-}
-
-template <typename T, int R, class Epi>
-hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
-                          const DevGraph<T>& g, const Epi& epi) {
-  switch (cfg.vpt) {
-    case 4:
-      return cfg.lds ? launch_apply_t<T, R, true, 4>(h, X, p, n, g, epi)
-                     : launch_apply_t<T, R, false, 4>(h, X, p, n, g, epi);
-    case 2:
-      return cfg.lds ? launch_apply_t<T, R, true, 2>(h, X, p, n, g, epi)
-                     : launch_apply_t<T, R, false, 2>(h, X, p, n, g, epi);
-    default:
-      return cfg.lds ? launch_apply_t<T, R, true, 1>(h, X, p, n, g, epi)
-                     : launch_apply_t<T, R, false, 1>(h, X, p, n, g, epi);
-  }
-}
-
-template <typename T, class Epi>
-cpca_status launch_apply(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
-                         const DevGraph<T>& g, const Epi& epi, int fam) {
-  STCHK(prof_begin(h, fam));
-  hipError_t e;
-  switch (cfg.R) {
-    case 1: e = launch_apply_r<T, 1>(h, cfg, X, p, n, g, epi); break;
-    case 2: e = launch_apply_r<T, 2>(h, cfg, X, p, n, g, epi); break;
-    case 4: e = launch_apply_r<T, 4>(h, cfg, X, p, n, g, epi); break;
-    case 8: e = launch_apply_r<T, 8>(h, cfg, X, p, n, g, epi); break;
-    default: return fail(CPCA_EINVAL, "unsupported rows per workgroup");
-  }
-  if (e != hipSuccess) return fail(CPCA_EHIP, std::string("apply launch: ") + hipGetErrorString(e));
-  return prof_end(h);
-}
-
-#define LAUNCHCHK()                                                                        \
-  do {                                                                                     \
-    hipError_t _e = hipGetLastError();                                                     \
-    if (_e != hipSuccess) return fail(CPCA_EHIP, std::string("launch: ") + hipGetErrorString(_e)); \
-  } while (0)
 
 // ---------------------------------------------------------------- CG core
 template <typename T>
@@ -408,27 +68,6 @@ cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, 
   return CPCA_OK;
 }
 
-cpca_status done_status(int done) {
-  switch (done) {
-    case 1: return CPCA_OK;
-    case 2: return fail(CPCA_ENOTSPD, "CG breakdown: <p, A p> <= 0");
-    case 3: return fail(CPCA_ENAN, "NaN or Inf in the iteration");
-    default: return fail(CPCA_ENOCONV, "iteration limit reached before the tolerance");
-  }
-}
-
-void fill_info(cpca_info* info, cpca_status st, int iters, int outer, double rel, double obj,
-               std::chrono::steady_clock::time_point t0) {
-  if (!info) return;
-  info->iters = iters;
-  info->outer_iters = outer;
-  info->status = (int32_t)st;
-  info->reserved = 0;
-  info->rel_residual = rel;
-  info->objective = obj;
-  info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-}
-
 // ------------------------------------------------------------- decode core
 // Problem preparation shared by decode, backward and apply.
 struct Prepared {
@@ -469,7 +108,22 @@ struct SolveOut {
   Partials part;
 };
 
-constexpr int kMaxOuter = 40;
+
+// With autotuning enabled (rows_per_block = -1), times the launch shapes of
+// the CG product on the current direction p and returns the fastest.
+template <typename T>
+cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, const Prepared& P, const T* pv, T* q,
+                      double* part, ApplyCfg* out) {
+  *out = op.cfg;
+  if (h->force_R != -1) return CPCA_OK;
+  const std::string key = tune_key("cg", sizeof(T), op.p, op.n, P.Lr.nnz + P.Lc.nnz);
+  return autotune(h, key, (size_t)op.n * sizeof(T), op.cfg,
+                  [&](const ApplyCfg& c) -> cpca_status {
+                    EpiApply<T> epi{q, op.gr, op.gc, part};
+                    return launch_apply<T>(h, c, pv, op.p, op.n, op.g, epi, FAM_OTHER);
+                  },
+                  out);
+}
 
 // Solves A(X) = B for the given mode. On return (OK or ENOCONV) the FP64
 // solution sits at so.x64 and, if `out` is given, the result is written to
@@ -590,6 +244,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
       k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
     LAUNCHCHK();
+    STCHK(tuned_cfg<double>(h, op, P, p64, q64, pa, &op.cfg));
     STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, part));
     so.iters = host_cg(h).iter;
     done = host_cg(h).done;
@@ -609,6 +264,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
       k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
     LAUNCHCHK();
+    STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
     STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
     so.iters = host_cg(h).iter;
     done = host_cg(h).done;
@@ -647,6 +303,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
         done = 0;
         break;
       }
+      if (outer == 0) STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
       STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
       const CgScal ci = host_cg(h);
       total += ci.iter;
@@ -806,6 +463,7 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
                 std::string("cpca_create: ") + hipGetErrorString(e));
   }
   h->stream = static_cast<hipStream_t>(stream);
+  tune_load_file(h);
   if (const char* s = std::getenv("CPCA_APPLY_R")) h->force_R = std::atoi(s);
   if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
   *out = h;
@@ -965,6 +623,8 @@ template <typename T>
 cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_t p, int64_t n,
                       double gr, double gc, double* pq) {
   ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T));
+  // user buffers: fall back to scalar columns if they are not 16-byte aligned
+  if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Q)) % 16 != 0) cfg.vec = 1;
   Staging stg;
   const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg));
   const int ag = apply_grid(cfg, (int)p);
@@ -1024,9 +684,9 @@ extern "C" cpca_status cpca_apply(cpca_handle h, cpca_mode mode, const void* P, 
 extern "C" cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_block, int32_t use_lds) {
   clear_error();
   if (!h) return fail(CPCA_EINVAL, "null handle");
-  if (!(rows_per_block == 0 || rows_per_block == 1 || rows_per_block == 2 || rows_per_block == 4 ||
-        rows_per_block == 8))
-    return fail(CPCA_EINVAL, "rows_per_block must be 0, 1, 2, 4 or 8");
+  if (!(rows_per_block == -1 || rows_per_block == 0 || rows_per_block == 1 ||
+        rows_per_block == 2 || rows_per_block == 4 || rows_per_block == 8))
+    return fail(CPCA_EINVAL, "rows_per_block must be -1, 0, 1, 2, 4 or 8");
   if (use_lds < -1 || use_lds > 1) return fail(CPCA_EINVAL, "use_lds must be -1, 0 or 1");
   h->force_R = rows_per_block;
   h->force_lds = use_lds;

@@ -4,14 +4,14 @@
 //     out(i, j) = mask(i, j) X(i, j) + a_r (L_r X)(i, j) + a_c (X L_c)(i, j)
 // which is the gradient of the graph term of FRPCAG (Section IV.B) and the
 // operator of the alternate decoder's normal equations (Section V.B). One
-// workgroup owns R consecutive rows of X and sweeps all n columns, VPT
-// columns per thread per pass, lane-consecutive:
-//   * L_r X streams the neighbour rows of X with coalesced loads; the CSR
-//     entries of row i are uniform across the workgroup;
+// workgroup owns R consecutive rows of X and sweeps all n columns, VEC
+// consecutive columns per thread (16-byte accesses):
+//   * L_r X streams the neighbour rows of X with coalesced vector loads; the
+//     CSR entries of row i are uniform across the workgroup;
 //   * X L_c gathers from the R rows of X (staged in LDS, or read through the
 //     L1 when LDS staging is off); L_c is held as sliced ELL with one slice
-//     per wavefront (64 columns), so its index/value loads are coalesced and
-//     every lane of a wave runs the same trip count;
+//     per wavefront (64 * VEC columns), so its index/value loads are 16-byte
+//     vector loads and every lane of a wave runs the same trip count;
 //   * the row-block index is remapped so that each XCD owns a contiguous
 //     range of rows and neighbour rows are shared through its L2.
 // What happens to out(i, j) is decided by an epilogue functor (CG apply,
@@ -40,11 +40,10 @@ struct CsrDev {
   const T* v;
 };
 
-// Sliced ELL with one slice per wavefront (64 consecutive columns): slice s
-// covers columns [64 s, 64 s + 64); its entries start at sp[s], width
-// w_s = (sp[s+1] - sp[s]) / 64, entry e of column j sits at
-// sp[s] + 64 e + (j - 64 s). Padding entries carry value 0 and a valid
-// column index.
+// Sliced ELL with slice height H = 64 * VEC: slice s covers columns
+// [H s, H s + H); its entries start at sp[s], width w_s = (sp[s+1]-sp[s]) / H,
+// entry e of column j sits at sp[s] + H e + (j - H s). Padding entries carry
+// value 0 and a valid column index.
 template <typename T>
 struct SellDev {
   const int* sp;
@@ -174,11 +173,10 @@ __device__ __forceinline__ void vst(T* __restrict__ p, const T (&v)[VEC]) {
 //   prologue()            called by the whole workgroup first; returns true to
 //                         skip the launch (converged solve); may sum partials
 //                         of the previous kernel
-//   apply<VPT>(i, idx, ok, x, mx, accr, accc, acc)
-//                         VPT outputs of row i at flat indices
-//                         idx + kThreads * v (valid where ok[v]): x = X,
-//                         mx = mask o X, accr = (L_r X), accc = (X L_c);
-//                         acc receives the partial sums
+//   apply<VEC>(i, idx, x, mx, accr, accc, acc)
+//                         VEC consecutive outputs of row i starting at flat
+//                         index idx: x = X, mx = mask o X, accr = (L_r X),
+//                         accc = (X L_c); acc receives the partial sums
 //   partials              where the workgroup partials go (may be null)
 // ---------------------------------------------------------------------------
 
@@ -190,17 +188,16 @@ struct EpiApply {
   T gr, gc;
   double* partials;
   __device__ bool prologue() const { return false; }
-  template <int VPT>
-  __device__ void apply(int, size_t idx, const bool (&ok)[VPT], const T (&x)[VPT],
-                        const T (&mx)[VPT], const T (&accr)[VPT], const T (&accc)[VPT],
-                        double* acc) const {
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&x)[VEC], const T (&mx)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T out[VEC];
 #pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-      if (!ok[v]) continue;
-      const T out = mx[v] + gr * accr[v] + gc * accc[v];
-      Q[idx + kThreads * v] = out;
-      acc[0] += (double)x[v] * (double)out;
+    for (int v = 0; v < VEC; ++v) {
+      out[v] = mx[v] + gr * accr[v] + gc * accc[v];
+      acc[0] += (double)x[v] * (double)out[v];
     }
+    vst<T, VEC>(Q + idx, out);
   }
 };
 
@@ -224,19 +221,18 @@ struct EpiResidual {
   T gr, gc;
   double* partials;
   __device__ bool prologue() const { return false; }
-  template <int VPT>
-  __device__ void apply(int, size_t idx, const bool (&ok)[VPT], const T (&)[VPT],
-                        const T (&mx)[VPT], const T (&accr)[VPT], const T (&accc)[VPT],
-                        double* acc) const {
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&)[VEC], const T (&mx)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T b[VEC];
+    vld<T, VEC>(B + idx, b);
 #pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-      if (!ok[v]) continue;
-      const size_t e = idx + kThreads * v;
-      const T R = B[e] - (mx[v] + gr * accr[v] + gc * accc[v]);
+    for (int v = 0; v < VEC; ++v) {
+      const T R = b[v] - (mx[v] + gr * accr[v] + gc * accc[v]);
       const TO Rt = (TO)R;
-      r_out[e] = Rt;
-      p_out[e] = Rt;
-      if (x_out) x_out[e] = TO(0);
+      r_out[idx + v] = Rt;
+      p_out[idx + v] = Rt;
+      if (x_out) x_out[idx + v] = TO(0);
       acc[0] += (double)R * (double)R;
       acc[1] += (double)Rt * (double)Rt;
     }
@@ -251,14 +247,14 @@ struct EpiResNorm {
   T gr, gc;
   double* partials;
   __device__ bool prologue() const { return false; }
-  template <int VPT>
-  __device__ void apply(int, size_t idx, const bool (&ok)[VPT], const T (&)[VPT],
-                        const T (&mx)[VPT], const T (&accr)[VPT], const T (&accc)[VPT],
-                        double* acc) const {
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&)[VEC], const T (&mx)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T b[VEC];
+    vld<T, VEC>(B + idx, b);
 #pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-      if (!ok[v]) continue;
-      const double R = (double)B[idx + kThreads * v] - (double)(mx[v] + gr * accr[v] + gc * accc[v]);
+    for (int v = 0; v < VEC; ++v) {
+      const double R = (double)b[v] - (double)(mx[v] + gr * accr[v] + gc * accc[v]);
       acc[0] += R * R;
     }
   }
@@ -299,28 +295,28 @@ struct EpiFista {
     }
     return stop;
   }
-  template <int VPT>
-  __device__ void apply(int, size_t idx, const bool (&ok)[VPT], const double (&z)[VPT],
-                        const double (&)[VPT], const double (&accr)[VPT],
-                        const double (&accc)[VPT], double* acc) const {
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const double (&z)[VEC], const double (&)[VEC],
+                        const double (&accr)[VEC], const double (&accc)[VEC],
+                        double* acc) const {
+    double y[VEC], sp[VEC], s[VEC], zn[VEC];
+    vld<double, VEC>(Y + idx, y);
+    vld<double, VEC>(S + idx, sp);
 #pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-      if (!ok[v]) continue;
-      const size_t e = idx + kThreads * v;
-      const double y = Y[e];
+    for (int v = 0; v < VEC; ++v) {
       const double g = z[v] - lam * (two_gr * accr[v] + two_gc * accc[v]);
-      const double d = g - y;
+      const double d = g - y[v];
       const double mag = fabs(d) - lam;
-      const double s = mag > 0.0 ? y + copysign(mag, d) : y;
-      const double zn = s + c * (s - S[e]);
-      S[e] = s;
-      Zn[e] = zn;
+      s[v] = mag > 0.0 ? y[v] + copysign(mag, d) : y[v];
+      zn[v] = s[v] + c * (s[v] - sp[v]);
       if (REDUCE) {
-        const double dz = zn - z[v];
+        const double dz = zn[v] - z[v];
         acc[0] += dz * dz;
         acc[1] += z[v] * z[v];
       }
     }
+    vst<double, VEC>(S + idx, s);
+    vst<double, VEC>(Zn + idx, zn);
   }
 };
 
@@ -331,14 +327,15 @@ struct EpiObjective {
   double gr, gc;
   double* partials;
   __device__ bool prologue() const { return false; }
-  template <int VPT>
-  __device__ void apply(int, size_t idx, const bool (&ok)[VPT], const double (&x)[VPT],
-                        const double (&)[VPT], const double (&accr)[VPT],
-                        const double (&accc)[VPT], double* acc) const {
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const double (&x)[VEC], const double (&)[VEC],
+                        const double (&accr)[VEC], const double (&accc)[VEC],
+                        double* acc) const {
+    double y[VEC];
+    vld<double, VEC>(Y + idx, y);
 #pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-      if (!ok[v]) continue;
-      acc[0] += fabs(Y[idx + kThreads * v] - x[v]);
+    for (int v = 0; v < VEC; ++v) {
+      acc[0] += fabs(y[v] - x[v]);
       acc[1] += x[v] * (gr * accr[v] + gc * accc[v]);
     }
   }
@@ -351,126 +348,136 @@ struct EpiDot2 {
   const T* Lam;
   double* partials;
   __device__ bool prologue() const { return false; }
-  template <int VPT>
-  __device__ void apply(int, size_t idx, const bool (&ok)[VPT], const T (&)[VPT],
-                        const T (&)[VPT], const T (&accr)[VPT], const T (&accc)[VPT],
-                        double* acc) const {
+  template <int VEC>
+  __device__ void apply(int, size_t idx, const T (&)[VEC], const T (&)[VEC],
+                        const T (&accr)[VEC], const T (&accc)[VEC], double* acc) const {
+    T l[VEC];
+    vld<T, VEC>(Lam + idx, l);
 #pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-      if (!ok[v]) continue;
-      const double l = (double)Lam[idx + kThreads * v];
-      acc[0] += l * (double)accr[v];
-      acc[1] += l * (double)accc[v];
+    for (int v = 0; v < VEC; ++v) {
+      acc[0] += (double)l[v] * (double)accr[v];
+      acc[1] += (double)l[v] * (double)accc[v];
     }
   }
 };
 
 // ---------------------------------------------------------------------------
-// The fused two-sided product. R rows per workgroup, all n columns. Each
-// pass covers kThreads * VPT columns: thread t owns columns
-// cb + t + kThreads * v (v < VPT), so the lanes of a wave always touch
-// consecutive columns (coalesced global accesses, and LDS gathers of a
-// banded L_c hit consecutive banks).
-//   LDS = true : the R rows live in LDS (R * n * sizeof(T) bytes).
+// The fused two-sided product on rows [i0, i0 + rows) of a p x n operand
+// stored with row stride ld (ld >= n rounded up to VEC; padding columns hold
+// zeros and the masks are padded with zeros, so padding outputs are zero).
+// VEC consecutive columns per thread, kThreads * VEC columns per pass.
+//   LDS = true : the R rows live in LDS (R * ld * sizeof(T) bytes).
 //   LDS = false: X L_c gathers from global memory (through the L1).
+// Shared by the single-problem kernel and the batched (task-table) kernel.
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool LDS, int VEC, class Epi>
+__device__ __forceinline__ void apply_rows(const T* __restrict__ X, int ld, int n,
+                                           const CsrDev<T>& Lr, const SellDev<T>& Lc,
+                                           const uint8_t* __restrict__ mr,
+                                           const uint8_t* __restrict__ mc, int i0, int rows,
+                                           const Epi& epi, double* acc, T* panel) {
+  constexpr int H = kWave * VEC;         // SELL slice height
+  constexpr int CPB = kThreads * VEC;    // columns per pass
+  if (LDS) {
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      if (rr < rows) {
+        const T* src = X + (size_t)(i0 + rr) * ld;
+        for (int c = threadIdx.x * VEC; c < n; c += CPB) {
+          T t[VEC];
+          vld<T, VEC>(src + c, t);
+          vst<T, VEC>(panel + rr * ld + c, t);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int c0 = threadIdx.x * VEC; c0 < n; c0 += CPB) {
+    // X L_c: columns c0 .. c0 + VEC - 1 of L_c (= rows, L_c symmetric),
+    // shared by the R rows of the block
+    T accc[R][VEC];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) accc[rr][v] = T(0);
+    {
+      const int s = c0 / H;
+      const int beg = Lc.sp[s];
+      const int w = (Lc.sp[s + 1] - beg) / H;
+      const int off = beg + (c0 - s * H);
+#pragma unroll 2
+      for (int e = 0; e < w; ++e) {
+        int kk[VEC];
+        T vv[VEC];
+        vld<int, VEC>(Lc.ci + off + e * H, kk);
+        vld<T, VEC>(Lc.v + off + e * H, vv);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          if (rr < rows) {
+            const T* rowp = LDS ? panel + rr * ld : X + (size_t)(i0 + rr) * ld;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) accc[rr][v] += vv[v] * rowp[kk[v]];
+          }
+        }
+      }
+    }
+    uint8_t mcv[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) mcv[v] = mc[c0 + v];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      if (rr < rows) {
+        const int i = i0 + rr;
+        // L_r X: row i of L_r, neighbour rows of X, coalesced over columns
+        T accr[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) accr[v] = T(0);
+        const int e0 = Lr.rp[i];
+        const int e1 = Lr.rp[i + 1];
+#pragma unroll 4
+        for (int e = e0; e < e1; ++e) {
+          const T w = Lr.v[e];
+          T xv[VEC];
+          vld<T, VEC>(X + (size_t)Lr.ci[e] * ld + c0, xv);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) accr[v] += w * xv[v];
+        }
+        const size_t idx = (size_t)i * ld + c0;
+        T x[VEC], mx[VEC];
+        if (LDS)
+          vld<T, VEC>(panel + rr * ld + c0, x);
+        else
+          vld<T, VEC>(X + idx, x);
+        const uint8_t mri = mr[i];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) mx[v] = (mri & mcv[v]) ? x[v] : T(0);
+        epi.template apply<VEC>(i, idx, x, mx, accr, accc[rr], acc);
+      }
+    }
+  }
+}
+
+// Single problem: R rows per workgroup, all n columns (row stride n).
 // Grid: 8 * per workgroups; workgroup b handles row block (b % 8) * per + b / 8
 // so that each XCD (workgroups are dealt to XCDs round-robin) owns `per`
 // consecutive row blocks. Workgroups past the last row block only write
 // zero partials.
-// ---------------------------------------------------------------------------
-template <typename T, int R, bool LDS, int VPT, class Epi>
+template <typename T, int R, bool LDS, int VEC, class Epi>
 __global__ void __launch_bounds__(kThreads)
 k_apply2(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc,
          const uint8_t* __restrict__ mr, const uint8_t* __restrict__ mc, int nrb, int per,
          Epi epi) {
   if (epi.prologue()) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* panel = reinterpret_cast<T*>(smem_raw);
   double acc[Epi::NV];
 #pragma unroll
   for (int k = 0; k < Epi::NV; ++k) acc[k] = 0.0;
-
   const int b = blockIdx.x;
   const int rb = (b & 7) * per + (b >> 3);
-  constexpr int CPB = kThreads * VPT;  // columns per pass
   if (rb < nrb) {
     const int i0 = rb * R;
-    const int rows = min(R, p - i0);
-    if (LDS) {
-      for (int rr = 0; rr < rows; ++rr) {
-        const T* src = X + (size_t)(i0 + rr) * n;
-        for (int c = threadIdx.x; c < n; c += kThreads) panel[rr * n + c] = src[c];
-      }
-      __syncthreads();
-    }
-    for (int cb = 0; cb < n; cb += CPB) {
-      bool ok[VPT];
-      int col[VPT];
-#pragma unroll
-      for (int v = 0; v < VPT; ++v) {
-        col[v] = cb + threadIdx.x + kThreads * v;
-        ok[v] = col[v] < n;
-      }
-      // X L_c: column col[v] of L_c (= row, L_c symmetric), shared by the R rows
-      T accc[R][VPT];
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) accc[rr][v] = T(0);
-#pragma unroll
-      for (int v = 0; v < VPT; ++v) {
-        if (!ok[v]) continue;
-        const int s = col[v] >> 6;
-        const int beg = Lc.sp[s];
-        const int w = (Lc.sp[s + 1] - beg) >> 6;
-        const int* ci = Lc.ci + beg + (col[v] & 63);
-        const T* cv = Lc.v + beg + (col[v] & 63);
-#pragma unroll 4
-        for (int e = 0; e < w; ++e) {
-          const int k = ci[e * kWave];
-          const T val = cv[e * kWave];
-#pragma unroll
-          for (int rr = 0; rr < R; ++rr) {
-            if (rr < rows) {
-              const T xv = LDS ? panel[rr * n + k] : X[(size_t)(i0 + rr) * n + k];
-              accc[rr][v] += val * xv;
-            }
-          }
-        }
-      }
-      uint8_t mcv[VPT];
-#pragma unroll
-      for (int v = 0; v < VPT; ++v) mcv[v] = ok[v] ? mc[col[v]] : 0;
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        if (rr < rows) {
-          const int i = i0 + rr;
-          // L_r X: row i of L_r, neighbour rows of X, coalesced over columns
-          T accr[VPT];
-#pragma unroll
-          for (int v = 0; v < VPT; ++v) accr[v] = T(0);
-          const int e0 = Lr.rp[i];
-          const int e1 = Lr.rp[i + 1];
-#pragma unroll 2
-          for (int e = e0; e < e1; ++e) {
-            const T w = Lr.v[e];
-            const T* xr = X + (size_t)Lr.ci[e] * n;
-#pragma unroll
-            for (int v = 0; v < VPT; ++v)
-              if (ok[v]) accr[v] += w * xr[col[v]];
-          }
-          const size_t idx = (size_t)i * n + cb + threadIdx.x;
-          T x[VPT], mx[VPT];
-          const uint8_t mri = mr[i];
-#pragma unroll
-          for (int v = 0; v < VPT; ++v) {
-            x[v] = ok[v] ? (LDS ? panel[rr * n + col[v]] : X[idx + kThreads * v]) : T(0);
-            mx[v] = (mri & mcv[v]) ? x[v] : T(0);
-          }
-          epi.template apply<VPT>(i, idx, ok, x, mx, accr, accc[rr], acc);
-        }
-      }
-    }
+    apply_rows<T, R, LDS, VEC, Epi>(X, n, n, Lr, Lc, mr, mc, i0, min(R, p - i0), epi, acc,
+                                    reinterpret_cast<T*>(smem_raw));
   }
   if (epi.partials) block_partials<Epi::NV>(acc, epi.partials);
 }

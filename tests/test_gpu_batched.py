@@ -1,0 +1,95 @@
+"""Batched solves (many instances of uneven sizes, gamma grids) against the
+single-problem calls and against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1602_02070_amd as cp
+import synth
+from oracle import decoder as OD
+from oracle import frpcag as OF
+from tests.gpu_util import dev_problem, host, rel
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [((6, 7), 45), ((9, 13), 130), ((5, 11), 77), ((12, 10), 201), ((4, 9), 38)]
+GRID = [(0.5, 0.3), (0.5, 3.0), (5.0, 0.3), (5.0, 3.0)]
+J = 60
+
+
+@pytest.fixture(scope="module")
+def batch():
+    probs = [synth.small_problem(40 + k, p_shape=s, n=n, frac=0.4, rank=3)
+             for k, (s, n) in enumerate(SHAPES)]
+    return probs
+
+
+def _instances(probs, dtype):
+    out = []
+    for P in probs:
+        d = dev_problem(P, dtype)
+        out.append(cp.Instance(P.p, P.n, d["om_r"], d["om_c"], d["Lr"], d["Lc"], d["Lr_til"],
+                               d["Lc_til"], P.lmax_r_til, P.lmax_c_til, d["Ytil"]))
+    return out
+
+
+def _tasks(probs):
+    return [(k, gr, gc) for k in range(len(probs)) for gr, gc in GRID]
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+def test_batched_matches_single_calls_and_oracle(batch, mode):
+    print(f"[case] batched {mode}", flush=True)
+    dt = torch.float64 if mode == "fp64" else torch.float32
+    inst = _instances(batch, dt)
+    tasks = _tasks(batch)
+    tol = 1e-12 if mode == "fp64" else 1e-10
+    Xs, Xts, infos = cp.solve_batched(inst, tasks, fista_iters=J, tol=tol, mode=mode,
+                                      want_xtil=True)
+    assert all(i["status"] == 0 for i in infos)
+    for t, (k, gr, gc) in enumerate(tasks):
+        P, I = batch[k], inst[k]
+        Xt1, _ = cp.frpcag(I.Ytil, I.Lr_til, I.Lc_til, gr, gc, P.lmax_r_til, P.lmax_c_til,
+                           max_iter=J)
+        X1, _ = cp.decode(Xt1, I.omega_r, I.omega_c, P.p, P.n, I.Lr, I.Lc, gr, gc, tol=tol,
+                          mode=mode)
+        assert rel(host(Xts[t]), host(Xt1)) <= 1e-12
+        assert rel(host(Xs[t]), host(X1)) <= (1e-9 if mode == "fp64" else 1e-6)
+        # oracle: FISTA then the exact decoder on the (rounded) estimate
+        Y = P.Ytil if mode == "fp64" else P.Ytil.astype(np.float32).astype(np.float64)
+        Xt_ref, _ = OF.fista(Y, P.Lr_til, P.Lc_til, gr, gc, P.lmax_r_til, P.lmax_c_til, J)
+        if mode != "fp64":
+            Xt_ref = Xt_ref.astype(np.float32).astype(np.float64)
+        X_ref = OD.decode(Xt_ref, P.p, P.n, P.omega_r, P.omega_c, P.Lr, P.Lc, gr, gc)
+        assert rel(host(Xs[t]), X_ref) <= (1e-8 if mode == "fp64" else 1e-5), (t, k, gr, gc)
+
+
+def test_batched_deterministic_and_autotuned(batch):
+    print("[case] batched determinism + autotune", flush=True)
+    inst = _instances(batch, torch.float32)
+    tasks = _tasks(batch)
+    a, _, _ = cp.solve_batched(inst, tasks, fista_iters=J, tol=1e-10)
+    b, _, _ = cp.solve_batched(inst, tasks, fista_iters=J, tol=1e-10)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    cp.set_apply_config(-1, -1)
+    try:
+        c, _, infos = cp.solve_batched(inst, tasks, fista_iters=J, tol=1e-10)
+        assert all(i["status"] == 0 for i in infos)
+        for x, y in zip(a, c):
+            assert rel(host(x), host(y)) <= 1e-6
+        # single-problem autotune path as well
+        P = batch[3]
+        I = inst[3]
+        X1, _ = cp.decode(I.Ytil, I.omega_r, I.omega_c, P.p, P.n, I.Lr, I.Lc, 1.0, 1.0, tol=1e-10)
+    finally:
+        cp.set_apply_config(0, -1)
+    X2, _ = cp.decode(I.Ytil, I.omega_r, I.omega_c, P.p, P.n, I.Lr, I.Lc, 1.0, 1.0, tol=1e-10)
+    assert rel(host(X1), host(X2)) <= 1e-6
+
+
+def test_batched_iteration_cap_reports_noconv(batch):
+    inst = _instances(batch[:2], torch.float64)
+    with pytest.warns(RuntimeWarning):
+        Xs, _, infos = cp.solve_batched(inst, [(0, 1.0, 1.0), (1, 10.0, 10.0)], fista_iters=5,
+                                        tol=1e-14, max_iter=3, mode="fp64")
+    assert all(i["status"] == 2 and i["iters"] == 3 for i in infos)
