@@ -396,13 +396,26 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
     const std::string key = tune_key(cg32 ? "batch32" : "batch64", elem_cg, ntasks, ld_max, sum_p);
     ApplyCfg best;
     if (!tune_lookup(h, key, best)) {
-      // prepare p = B so that the candidates run on meaningful data
-      if (mode == CPCA_FP32) k_pass_batched<P_B32><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
-      if (cg32) k_init_zero_batched<float><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab, pb);
-      else k_init_zero_batched<double><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab, pb);
-      LAUNCHCHK();
-      k_arm_batched<false><<<ntasks, kThreads, 0, s>>>(d_tasks, pb, 1e-300);
-      LAUNCHCHK();
+      // prepare p = B (rounded to the CG type) so that the candidates run
+      // on meaningful data, and arm every task so none is skipped
+      if (mode == CPCA_FP32_IR) {
+        // FP32_IR keeps no FP32 copy of B: take the refinement residual at X = 0
+        k_pass_batched<P_ZERO_X64><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
+        LAUNCHCHK();
+        k_pass_batched<P_ZERO_32><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
+        LAUNCHCHK();
+        HIPCHK((launch_bapply<double, B_RES>(h, s, bc, g.a, (size_t)ld_max, d_tasks, d_atab, pa,
+                                             0.0, 0)));
+        k_arm_batched<true><<<ntasks, kThreads, 0, s>>>(d_tasks, pa, 0.0);
+        LAUNCHCHK();
+      } else {
+        if (mode == CPCA_FP32) k_pass_batched<P_B32><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
+        if (cg32) k_init_zero_batched<float><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab, pb);
+        else k_init_zero_batched<double><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab, pb);
+        LAUNCHCHK();
+        k_arm_batched<false><<<ntasks, kThreads, 0, s>>>(d_tasks, pb, 1e-300);
+        LAUNCHCHK();
+      }
       ApplyCfg base;
       base.vec = (int)(16 / elem_cg);
       STCHK(autotune(h, key, (size_t)ld_max * sizeof(double), base,
@@ -511,6 +524,8 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
     }
   } else {
     k_pass_batched<P_ZERO_X64><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
+    LAUNCHCHK();
+    k_pass_batched<P_ZERO_32><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
     LAUNCHCHK();
     std::vector<double> rel_prev((size_t)ntasks, 1.0);
     for (int o = 0;; ++o) {

@@ -343,7 +343,12 @@ k_apply_sum_batched(const BTask* __restrict__ tasks, const double* part, double*
 }
 
 // Element-wise per-task passes over p x ld (grid: vector blocks).
-enum BPass { P_ACCUM = 0, P_B32 = 1, P_X64_FROM_32 = 2, P_ZERO_X64 = 3, P_ZERO_B64 = 4 };
+// P_ZERO_32 clears the FP32 CG vectors over the whole padded extent: the
+// FP64 residual epilogue (2 columns per thread) only writes up to n rounded
+// to 2, while the FP32 kernels (4 columns per thread) read up to n rounded
+// to 4.
+enum BPass { P_ACCUM = 0, P_B32 = 1, P_X64_FROM_32 = 2, P_ZERO_X64 = 3, P_ZERO_B64 = 4,
+             P_ZERO_32 = 5 };
 template <int PASS>
 __global__ void __launch_bounds__(kThreads)
 k_pass_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_task) {
@@ -358,6 +363,7 @@ k_pass_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_tas
     if (PASS == P_X64_FROM_32) tk.X64[e] = (double)tk.x32[e];
     if (PASS == P_ZERO_X64) tk.X64[e] = 0.0;
     if (PASS == P_ZERO_B64) tk.B64[e] = 0.0;
+    if (PASS == P_ZERO_32) tk.x32[e] = tk.r32[e] = tk.p32[e] = tk.q32[e] = 0.f;
   }
 }
 
@@ -376,7 +382,7 @@ k_scatter_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_
   }
 }
 
-// FISTA set-up per task: S = Za = Y (grid: vector blocks).
+// FISTA set-up per task: S = Za = Y, Zb = 0 (grid: vector blocks).
 __global__ void __launch_bounds__(kThreads)
 k_fista_init_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_task) {
   const BTask& tk = tasks[vblk_task[blockIdx.x]];
@@ -385,6 +391,7 @@ k_fista_init_batched(const BTask* __restrict__ tasks, const int* __restrict__ vb
   for (size_t e = (size_t)(blockIdx.x - tk.vblk0) * blockDim.x + threadIdx.x; e < N; e += stride) {
     tk.S[e] = tk.Y[e];
     tk.Za[e] = tk.Y[e];
+    tk.Zb[e] = 0.0;
   }
 }
 
