@@ -418,7 +418,7 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
       }
       ApplyCfg base;
       base.vec = (int)(16 / elem_cg);
-      STCHK(autotune(h, key, (size_t)ld_max * sizeof(double), base,
+      STCHK(autotune(h, key, ld_max, sizeof(double), base,
                      [&](const ApplyCfg& c) -> cpca_status {
                        BatchCfg b2{c.R, c.lds};
                        std::vector<BTask> btc = bt;

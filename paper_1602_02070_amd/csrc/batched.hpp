@@ -93,7 +93,7 @@ k_apply_batched(const BTask* __restrict__ tasks, const int* __restrict__ blk_tas
     epi.sc = tk.sc;
     if (epi.prologue()) return;
     if (rows > 0)
-      apply_rows<float, R, LDS, VEC>(tk.p32, ld, ncols, tk.Lr32, tk.Lc32, tk.mr, tk.mc, i0, rows,
+      apply_rows<float, R, LDS, VEC, 0>(tk.p32, ld, ncols, tk.Lr32, tk.Lc32, BandDev<float>{}, tk.mr, tk.mc, i0, rows,
                                      epi, acc, reinterpret_cast<float*>(panel));
     double a1[1] = {acc[0]};
     block_partials<1>(a1, partials);
@@ -106,7 +106,7 @@ k_apply_batched(const BTask* __restrict__ tasks, const int* __restrict__ blk_tas
     epi.sc = tk.sc;
     if (epi.prologue()) return;
     if (rows > 0)
-      apply_rows<double, R, LDS, VEC>(tk.p64, ld, ncols, tk.Lr64, tk.Lc64, tk.mr, tk.mc, i0, rows,
+      apply_rows<double, R, LDS, VEC, 0>(tk.p64, ld, ncols, tk.Lr64, tk.Lc64, BandDev<double>{}, tk.mr, tk.mc, i0, rows,
                                       epi, acc, reinterpret_cast<double*>(panel));
     double a1[1] = {acc[0]};
     block_partials<1>(a1, partials);
@@ -115,13 +115,13 @@ k_apply_batched(const BTask* __restrict__ tasks, const int* __restrict__ blk_tas
     if (!tk.active) return;
     EpiResidual<double, float> epi{tk.B64, tk.r32, tk.p32, tk.x32, tk.gr, tk.gc, partials};
     if (rows > 0)
-      apply_rows<double, R, LDS, VEC>(tk.X64, ld, ncols, tk.Lr64, tk.Lc64, tk.mr, tk.mc, i0, rows,
+      apply_rows<double, R, LDS, VEC, 0>(tk.X64, ld, ncols, tk.Lr64, tk.Lc64, BandDev<double>{}, tk.mr, tk.mc, i0, rows,
                                       epi, acc, reinterpret_cast<double*>(panel));
     block_partials<2>(acc, partials);
   } else if constexpr (KIND == B_RESNORM) {
     EpiResNorm<double> epi{tk.B64, tk.gr, tk.gc, partials};
     if (rows > 0)
-      apply_rows<double, R, LDS, VEC>(tk.X64, ld, ncols, tk.Lr64, tk.Lc64, tk.mr, tk.mc, i0, rows,
+      apply_rows<double, R, LDS, VEC, 0>(tk.X64, ld, ncols, tk.Lr64, tk.Lc64, BandDev<double>{}, tk.mr, tk.mc, i0, rows,
                                       epi, acc, reinterpret_cast<double*>(panel));
     double a1[1] = {acc[0]};
     block_partials<1>(a1, partials);
@@ -132,7 +132,7 @@ k_apply_batched(const BTask* __restrict__ tasks, const int* __restrict__ blk_tas
     double* Zout = par ? tk.Za : tk.Zb;
     EpiFista<false> epi{tk.Y, tk.S, Zout, 2.0 * tk.gr, 2.0 * tk.gc, tk.lam, fista_c, 0.0,
                         nullptr, 0, nullptr, 0, nullptr};
-    apply_rows<double, R, LDS, VEC>(Zin, ld, ncols, tk.Lrt, tk.Lct, tk.zmr, tk.zmc, i0, rows,
+    apply_rows<double, R, LDS, VEC, 0>(Zin, ld, ncols, tk.Lrt, tk.Lct, BandDev<double>{}, tk.zmr, tk.zmc, i0, rows,
                                     epi, acc, reinterpret_cast<double*>(panel));
   }
 }

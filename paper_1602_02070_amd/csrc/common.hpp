@@ -35,6 +35,7 @@ struct cpca_handle_s {
   void* pinned = nullptr;      // host mirror of the scalars
   int force_R = 0;             // launch-shape override (0: default, -1: autotune)
   int force_lds = -1;          // LDS override (-1: default)
+  int force_band = -1;         // band path override (0: off, -1: automatic)
   std::vector<std::pair<std::string, std::pair<int, int>>> tuned;  // autotuner cache
   bool prof = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
@@ -186,6 +187,7 @@ template <typename T>
 struct DevGraph {
   CsrDev<T> Lr{};
   SellDev<T> Lc{};
+  BandDev<T> Lb{};
   const uint8_t* mr = nullptr;
   const uint8_t* mc = nullptr;
 };
@@ -202,25 +204,66 @@ struct Staging {
 
 template <typename T>
 struct GraphImage {
-  size_t o_rp, o_ci, o_v, o_sp, o_sci, o_sv, o_mr, o_mc;
+  size_t o_rp, o_ci, o_v, o_sp, o_sci, o_sv, o_mr, o_mc, o_bv;
+  int ldb;                      // band row stride (0: no band)
+  unsigned long long nonempty;  // band diagonals holding an entry
 };
 
+// Half-bandwidth of the diagonal (band) part of L_c: the smallest of 8 and
+// 16 that holds at least 90% of the entries, else 0 (sliced ELL only).
+inline int choose_band(const HostCsr& Lc) {
+  if (Lc.nnz == 0) return 0;
+  int64_t in8 = 0, in16 = 0;
+  for (int64_t j = 0; j < Lc.n; ++j)
+    for (int32_t e = Lc.rp[j]; e < Lc.rp[j + 1]; ++e) {
+      const int64_t d = std::llabs((int64_t)Lc.ci[e] - j);
+      in8 += d <= 8;
+      in16 += d <= 16;
+    }
+  if (in8 * 10 >= Lc.nnz * 9) return 8;
+  if (in16 * 10 >= Lc.nnz * 9) return 16;
+  return 0;
+}
+
+// Stages the device image of one operator: CSR of L_r in T, L_c as band
+// diagonals (|k - j| <= BW, when BW > 0) plus a sliced ELL of the remaining
+// entries with slice height H, and the 0/1 masks.
 template <typename T>
 GraphImage<T> stage_graph(Staging& st, const HostCsr& Lr, const HostCsr& Lc,
-                          const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int H) {
+                          const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int H,
+                          int BW = 0) {
   GraphImage<T> g{};
   std::vector<T> vr(Lr.v.begin(), Lr.v.begin() + Lr.nnz);
   g.o_rp = st.add(Lr.rp.data(), sizeof(int32_t) * Lr.rp.size());
   g.o_ci = st.add(Lr.ci.data(), sizeof(int32_t) * std::max<int64_t>(Lr.nnz, 1));
   g.o_v = st.add(vr.data(), sizeof(T) * vr.size());
-  // sliced ELL of L_c, slice height H
   const int64_t n = Lc.n;
+  auto in_band = [&](int64_t j, int32_t k) { return BW > 0 && std::llabs((int64_t)k - j) <= BW; };
+  // band diagonals
+  g.ldb = 0;
+  g.nonempty = 0;
+  if (BW > 0) {
+    const int vec = H / kWave;
+    g.ldb = (int)((n + vec - 1) / vec * vec);
+    std::vector<T> bv((size_t)(2 * BW + 1) * g.ldb, T(0));
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t e = Lc.rp[j]; e < Lc.rp[j + 1]; ++e)
+        if (in_band(j, Lc.ci[e])) {
+          const int d = (int)((int64_t)Lc.ci[e] - j);
+          bv[(size_t)(d + BW) * g.ldb + j] += (T)Lc.v[e];
+          g.nonempty |= 1ull << (d + BW);
+        }
+    g.o_bv = st.add(bv.data(), sizeof(T) * bv.size());
+  }
+  // sliced ELL of the remaining entries, slice height H
   const int64_t ns = (n + H - 1) / H;
   std::vector<int32_t> sp((size_t)ns + 1, 0);
+  std::vector<int32_t> deg((size_t)n, 0);
+  for (int64_t j = 0; j < n; ++j)
+    for (int32_t e = Lc.rp[j]; e < Lc.rp[j + 1]; ++e) deg[(size_t)j] += !in_band(j, Lc.ci[e]);
   for (int64_t s = 0; s < ns; ++s) {
     int w = 0;
-    for (int64_t j = s * H; j < std::min<int64_t>(n, (s + 1) * H); ++j)
-      w = std::max(w, Lc.rp[j + 1] - Lc.rp[j]);
+    for (int64_t j = s * H; j < std::min<int64_t>(n, (s + 1) * H); ++j) w = std::max(w, deg[(size_t)j]);
     sp[s + 1] = sp[s] + w * H;
   }
   std::vector<int32_t> sci((size_t)std::max(sp[ns], 1), 0);
@@ -229,16 +272,20 @@ GraphImage<T> stage_graph(Staging& st, const HostCsr& Lr, const HostCsr& Lc,
     const int w = (sp[s + 1] - sp[s]) / H;
     for (int lane = 0; lane < H; ++lane) {
       const int64_t j = s * H + lane;
-      const int deg = j < n ? Lc.rp[j + 1] - Lc.rp[j] : 0;
-      for (int e = 0; e < w; ++e) {
-        const size_t pos = (size_t)sp[s] + (size_t)e * H + lane;
-        if (e < deg) {
-          sci[pos] = Lc.ci[Lc.rp[j] + e];
-          sv[pos] = (T)Lc.v[Lc.rp[j] + e];
-        } else {
-          sci[pos] = j < n ? (int32_t)j : 0;
-          sv[pos] = T(0);
+      int e_out = 0;
+      if (j < n) {
+        for (int32_t e = Lc.rp[j]; e < Lc.rp[j + 1]; ++e) {
+          if (in_band(j, Lc.ci[e])) continue;
+          const size_t pos = (size_t)sp[s] + (size_t)e_out * H + lane;
+          sci[pos] = Lc.ci[e];
+          sv[pos] = (T)Lc.v[e];
+          ++e_out;
         }
+      }
+      for (; e_out < w; ++e_out) {
+        const size_t pos = (size_t)sp[s] + (size_t)e_out * H + lane;
+        sci[pos] = j < n ? (int32_t)j : 0;
+        sv[pos] = T(0);
       }
     }
   }
@@ -261,6 +308,9 @@ DevGraph<T> bind_graph(const GraphImage<T>& g, const char* dev) {
   d.Lc.v = reinterpret_cast<const T*>(dev + g.o_sv);
   d.mr = reinterpret_cast<const uint8_t*>(dev + g.o_mr);
   d.mc = reinterpret_cast<const uint8_t*>(dev + g.o_mc);
+  d.Lb.v = g.ldb ? reinterpret_cast<const T*>(dev + g.o_bv) : nullptr;
+  d.Lb.ldb = g.ldb;
+  d.Lb.nonempty = g.nonempty;
   return d;
 }
 
@@ -269,13 +319,24 @@ struct ApplyCfg {
   int R = 1;
   bool lds = true;
   int vec = 1;  // columns per thread (16-byte accesses when > 1)
+  int bw = 0;   // band half-width of L_c (0: sliced ELL only)
+  bool strip = false;  // column-strip kernel (needs bw > 0 and full vectors)
 };
+
+constexpr int kStripRows = 16;  // rows per workgroup of the column-strip kernel
+
+inline size_t lds_bytes(const ApplyCfg& c, int64_t ld, size_t elem) {
+  const int pad = c.bw == 0 ? 0 : (c.bw + c.vec - 1) / c.vec * c.vec;
+  return (size_t)c.R * (size_t)(ld + 2 * pad) * elem;
+}
 
 // Launch shape of the fused product for a p x n operand of `elem` bytes.
 // Default: one row per workgroup staged in LDS (the fastest shape measured
 // for banded and K-NN graphs); two rows through the L1 when a row does not
-// fit in 64 KiB of LDS.
-ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem) {
+// fit in 64 KiB of LDS. `band` is the candidate band half-width of L_c
+// (choose_band); it is used when the rows are staged in LDS with full
+// 16-byte vectors.
+ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem, int band = 0) {
   ApplyCfg c;
   const int W = (int)(16 / elem);
   c.vec = (n % W == 0) ? W : 1;
@@ -287,6 +348,20 @@ ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem) {
   if (h->force_lds == 1) c.lds = (size_t)c.R * row_bytes <= 65536;
   if (h->force_lds == 0) c.lds = false;
   if (h->force_lds == -1 && h->force_R > 0) c.lds = (size_t)c.R * row_bytes <= 65536;
+  c.bw = 0;
+  c.strip = false;
+  if (band > 0 && c.vec == W && h->force_band != 0) {
+    if (h->force_R <= 0 && h->force_lds != 0) {
+      // banded L_c: column strips with the diagonals held in registers
+      c.bw = band;
+      c.strip = h->force_band != 2;
+    }
+    if (!c.strip && c.lds && c.R <= 4) {
+      ApplyCfg t = c;
+      t.bw = band;
+      c.bw = lds_bytes(t, n, elem) <= 65536 ? band : 0;
+    }
+  }
   return c;
 }
 
@@ -297,19 +372,49 @@ int vec_grid(size_t N) {
   return (int)std::max<size_t>(1, std::min<size_t>(b, 2048));
 }
 
-int apply_grid(const ApplyCfg& cfg, int p) {
+// Largest workgroup count any launch shape can use for a p x n operand
+// (sizes the partial-sum buffers before the shape is known).
+int max_apply_grid(int p, int n) {
+  const int nchunks = (p + kStripRows - 1) / kStripRows;
+  const int nstrips = (n + kStripThreads - 1) / kStripThreads;
+  return std::max(8 * ((p + 7) / 8), 8 * ((nchunks + 7) / 8) * nstrips);
+}
+
+// Workgroups of one fused-product launch (= partial sums written).
+int apply_grid(const ApplyCfg& cfg, int p, int n = 0) {
+  if (cfg.strip) {
+    const int cw = kStripThreads * cfg.vec;
+    const int nstrips = (n + cw - 1) / cw;
+    const int nchunks = (p + kStripRows - 1) / kStripRows;
+    return 8 * ((nchunks + 7) / 8) * nstrips;
+  }
   const int nrb = (p + cfg.R - 1) / cfg.R;
   return 8 * ((nrb + 7) / 8);
 }
 
-template <typename T, int R, bool LDS, int VEC, class Epi>
+template <typename T, int R, bool LDS, int VEC, int BW, class Epi>
 hipError_t launch_apply_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
                           const Epi& epi) {
   const int nrb = (p + R - 1) / R;
   const int per = (nrb + 7) / 8;
-  const size_t shmem = LDS ? (size_t)R * n * sizeof(T) : 0;
-  k_apply2<T, R, LDS, VEC, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
-      X, p, n, g.Lr, g.Lc, g.mr, g.mc, nrb, per, epi);
+  constexpr int PAD = band_pad<BW, VEC>();
+  const size_t shmem = LDS ? (size_t)R * (n + 2 * PAD) * sizeof(T) : 0;
+  k_apply2<T, R, LDS, VEC, BW, Epi><<<dim3(8 * per), dim3(kThreads), shmem, h->stream>>>(
+      X, p, n, g.Lr, g.Lc, g.Lb, g.mr, g.mc, nrb, per, epi);
+  return hipGetLastError();
+}
+
+template <typename T, int BW, class Epi>
+hipError_t launch_strip_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
+                          const Epi& epi) {
+  constexpr int W = (int)(16 / sizeof(T));
+  const int cw = kStripThreads * W;
+  const int nstrips = (n + cw - 1) / cw;
+  const int nchunks = (p + kStripRows - 1) / kStripRows;
+  const int cpx = (nchunks + 7) / 8;
+  k_apply_strip<T, W, BW, kStripRows, Epi><<<dim3(8 * cpx * nstrips), dim3(kStripThreads), 0,
+                                              h->stream>>>(X, p, n, g.Lr, g.Lc, g.Lb, g.mr, g.mc,
+                                                           nchunks, cpx, epi);
   return hipGetLastError();
 }
 
@@ -317,12 +422,23 @@ template <typename T, int R, class Epi>
 hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
                           const DevGraph<T>& g, const Epi& epi) {
   constexpr int W = (int)(16 / sizeof(T));
-  if (cfg.vec == W) {
-    return cfg.lds ? launch_apply_t<T, R, true, W>(h, X, p, n, g, epi)
-                   : launch_apply_t<T, R, false, W>(h, X, p, n, g, epi);
+  if (cfg.strip) {
+    if (cfg.vec != W) return hipErrorInvalidValue;
+    if (cfg.bw == 8) return launch_strip_t<T, 8>(h, X, p, n, g, epi);
+    if (cfg.bw == 16) return launch_strip_t<T, 16>(h, X, p, n, g, epi);
+    return hipErrorInvalidValue;
   }
-  return cfg.lds ? launch_apply_t<T, R, true, 1>(h, X, p, n, g, epi)
-                 : launch_apply_t<T, R, false, 1>(h, X, p, n, g, epi);
+  if constexpr (R <= 4) {
+    if (cfg.bw == 8 && cfg.lds && cfg.vec == W) return launch_apply_t<T, R, true, W, 8>(h, X, p, n, g, epi);
+    if (cfg.bw == 16 && cfg.lds && cfg.vec == W) return launch_apply_t<T, R, true, W, 16>(h, X, p, n, g, epi);
+  }
+  if (cfg.bw != 0) return hipErrorInvalidValue;
+  if (cfg.vec == W) {
+    return cfg.lds ? launch_apply_t<T, R, true, W, 0>(h, X, p, n, g, epi)
+                   : launch_apply_t<T, R, false, W, 0>(h, X, p, n, g, epi);
+  }
+  return cfg.lds ? launch_apply_t<T, R, true, 1, 0>(h, X, p, n, g, epi)
+                 : launch_apply_t<T, R, false, 1, 0>(h, X, p, n, g, epi);
 }
 
 template <typename T, class Epi>
@@ -386,21 +502,25 @@ inline std::string tune_key(const char* kind, size_t elem, int64_t p, int64_t n,
   return buf;
 }
 
+// Cached shape: rows per workgroup and a mode (0: no LDS, 1: LDS rows,
+// 2: column strips).
 inline bool tune_lookup(cpca_handle h, const std::string& key, ApplyCfg& c) {
   for (const auto& kv : h->tuned)
     if (kv.first == key) {
       c.R = kv.second.first;
       c.lds = kv.second.second != 0;
+      c.strip = kv.second.second == 2;
       return true;
     }
   return false;
 }
 
 inline void tune_store(cpca_handle h, const std::string& key, const ApplyCfg& c) {
-  h->tuned.push_back({key, {c.R, c.lds ? 1 : 0}});
+  const int mode = c.strip ? 2 : (c.lds ? 1 : 0);
+  h->tuned.push_back({key, {c.R, mode}});
   if (const char* path = std::getenv("CPCA_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "%s %d %d\n", key.c_str(), c.R, c.lds ? 1 : 0);
+      std::fprintf(f, "%s %d %d\n", key.c_str(), c.R, mode);
       std::fclose(f);
     }
   }
@@ -422,10 +542,12 @@ inline void tune_load_file(cpca_handle h) {
 // Times `reps` calls of `launch(cfg)` for every candidate and returns the
 // fastest. `launch` enqueues one kernel and returns a status.
 template <class F>
-cpca_status autotune(cpca_handle h, const std::string& key, size_t row_bytes, ApplyCfg base,
+cpca_status autotune(cpca_handle h, const std::string& key, int64_t ld, size_t elem, ApplyCfg base,
                      F launch, ApplyCfg* best) {
   if (tune_lookup(h, key, *best)) {
     best->vec = base.vec;
+    best->bw = base.bw;
+    if (best->bw == 0) best->strip = false;
     return CPCA_OK;
   }
   hipEvent_t e0, e1;
@@ -433,31 +555,48 @@ cpca_status autotune(cpca_handle h, const std::string& key, size_t row_bytes, Ap
   HIPCHK(hipEventCreate(&e1));
   float best_ms = 1e30f;
   *best = base;
-  const int Rs[] = {1, 2, 4};
-  cpca_status st = CPCA_OK;
-  for (int lds = 1; lds >= 0 && st == CPCA_OK; --lds) {
-    for (int R : Rs) {
-      if (lds && (size_t)R * row_bytes > 65536) continue;
-      ApplyCfg c = base;
+  // candidates: with a band image, the column-strip kernel and the row-panel
+  // band kernel; otherwise rows per workgroup x LDS staging
+  std::vector<ApplyCfg> cands;
+  if (base.bw > 0) {
+    ApplyCfg c = base;
+    c.strip = true;
+    c.R = 1;
+    c.lds = true;
+    cands.push_back(c);
+    for (int R : {1, 2, 4}) {
+      c.strip = false;
       c.R = R;
-      c.lds = lds != 0;
-      if ((st = launch(c)) != CPCA_OK) break;  // warm-up
-      if (hipEventRecord(e0, h->stream) != hipSuccess) {
-        st = fail(CPCA_EHIP, "autotune: event record failed");
-        break;
+      if (lds_bytes(c, ld, elem) <= 65536) cands.push_back(c);
+    }
+  } else {
+    for (int lds = 1; lds >= 0; --lds)
+      for (int R : {1, 2, 4}) {
+        ApplyCfg c = base;
+        c.R = R;
+        c.lds = lds != 0;
+        c.strip = false;
+        if (!lds || lds_bytes(c, ld, elem) <= 65536) cands.push_back(c);
       }
-      for (int k = 0; k < 3 && st == CPCA_OK; ++k) st = launch(c);
-      if (st != CPCA_OK) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = fail(CPCA_EHIP, "autotune: event timing failed");
-        break;
-      }
-      if (ms < best_ms) {
-        best_ms = ms;
-        *best = c;
-      }
+  }
+  cpca_status st = CPCA_OK;
+  for (const ApplyCfg& c : cands) {
+    if ((st = launch(c)) != CPCA_OK) break;  // warm-up
+    if (hipEventRecord(e0, h->stream) != hipSuccess) {
+      st = fail(CPCA_EHIP, "autotune: event record failed");
+      break;
+    }
+    for (int k = 0; k < 3 && st == CPCA_OK; ++k) st = launch(c);
+    if (st != CPCA_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(CPCA_EHIP, "autotune: event timing failed");
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = c;
     }
   }
   (void)hipEventDestroy(e0);

@@ -41,7 +41,7 @@ cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, 
   if (host_cg(h).done) return CPCA_OK;
   int it = 0;
   int chunk = 4;
-  const int ag = apply_grid(op.cfg, op.p);
+  const int ag = apply_grid(op.cfg, op.p, op.n);
   const int vg = vec_grid(N / V16<T>::W + 1);
   while (it < max_iter) {
     const int m = std::min(chunk, max_iter - it);
@@ -117,7 +117,7 @@ cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, const Prepared& P, c
   *out = op.cfg;
   if (h->force_R != -1) return CPCA_OK;
   const std::string key = tune_key("cg", sizeof(T), op.p, op.n, P.Lr.nnz + P.Lc.nnz);
-  return autotune(h, key, (size_t)op.n * sizeof(T), op.cfg,
+  return autotune(h, key, op.n, sizeof(T), op.cfg,
                   [&](const ApplyCfg& c) -> cpca_status {
                     EpiApply<T> epi{q, op.gr, op.gc, part};
                     return launch_apply<T>(h, c, pv, op.p, op.n, op.g, epi, FAM_OTHER);
@@ -133,13 +133,15 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
                          const void* X0, void* out, bool want_spare, SolveOut& so) {
   const size_t N = (size_t)p * n;
   const bool f32 = mode != CPCA_FP64;
-  const ApplyCfg cfg64 = choose_cfg(h, p, n, sizeof(double));
-  const ApplyCfg cfg32 = choose_cfg(h, p, n, sizeof(float));
+  const int band = choose_band(P.Lc);
+  const ApplyCfg cfg64 = choose_cfg(h, p, n, sizeof(double), band);
+  const ApplyCfg cfg32 = choose_cfg(h, p, n, sizeof(float), band);
   Staging stg;
-  const GraphImage<double> gi64 = stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg64));
+  const GraphImage<double> gi64 =
+      stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg64), cfg64.bw);
   GraphImage<float> gi32{};
-  if (f32) gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg32));
-  const int maxgrid = std::max({apply_grid(cfg64, (int)p), apply_grid(cfg32, (int)p), 2048});
+  if (f32) gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg32), cfg32.bw);
+  const int maxgrid = std::max({max_apply_grid((int)p, (int)n), 2048});
 
   char* img = nullptr;
   double *pa = nullptr, *pb = nullptr, *B64 = nullptr, *X64 = nullptr, *r64 = nullptr,
@@ -179,8 +181,8 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
   const Partials part{pa, pb};
   CgScal* sc = cg_ptr(h);
   const int vg = vec_grid(N);
-  const int ag64 = apply_grid(cfg64, (int)p);
-  const int ag32 = apply_grid(cfg32, (int)p);
+  const int ag64 = apply_grid(cfg64, (int)p, (int)n);
+  const int ag32 = apply_grid(cfg32, (int)p, (int)n);
   so.x64 = X64;
   so.spare64 = spare;
   so.g64 = g64;
@@ -348,10 +350,10 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   STCHK(fetch_csr("Lc_til", Lc_t, Lc));
   const size_t N = (size_t)rho_r * rho_c;
   std::vector<uint8_t> mr((size_t)rho_r, 0), mc((size_t)rho_c, 0);
-  const ApplyCfg cfg = choose_cfg(h, rho_r, rho_c, sizeof(double));
+  const ApplyCfg cfg = choose_cfg(h, rho_r, rho_c, sizeof(double), choose_band(Lc));
   Staging stg;
-  const GraphImage<double> gi = stage_graph<double>(stg, Lr, Lc, mr, mc, slice_height(cfg));
-  const int ag = apply_grid(cfg, (int)rho_r);
+  const GraphImage<double> gi = stage_graph<double>(stg, Lr, Lc, mr, mc, slice_height(cfg), cfg.bw);
+  const int ag = apply_grid(cfg, (int)rho_r, (int)rho_c);
   const int maxgrid = std::max(ag, 2048);
   char* img = nullptr;
   double *pa = nullptr, *pb = nullptr, *Y = nullptr, *S = nullptr, *Za = nullptr, *Zb = nullptr;
@@ -466,6 +468,7 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
   tune_load_file(h);
   if (const char* s = std::getenv("CPCA_APPLY_R")) h->force_R = std::atoi(s);
   if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
+  if (const char* s = std::getenv("CPCA_BAND")) h->force_band = std::atoi(s);
   *out = h;
   return CPCA_OK;
 }
@@ -607,7 +610,7 @@ extern "C" cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode, const
   LAUNCHCHK();
   EpiDot2<double> epi{so.x64, so.part.a};
   STCHK(launch_apply<double>(h, so.cfg64, so.spare64, (int)p, (int)n, so.g64, epi, FAM_OTHER));
-  k_sum_partials<2><<<1, kThreads, 0, h->stream>>>(so.part.a, apply_grid(so.cfg64, (int)p),
+  k_sum_partials<2><<<1, kThreads, 0, h->stream>>>(so.part.a, apply_grid(so.cfg64, (int)p, (int)n),
                                                     results_ptr(h) + 2);
   LAUNCHCHK();
   STCHK(read_fixed(h));
@@ -622,12 +625,15 @@ namespace {
 template <typename T>
 cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_t p, int64_t n,
                       double gr, double gc, double* pq) {
-  ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T));
+  ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T), choose_band(P.Lc));
   // user buffers: fall back to scalar columns if they are not 16-byte aligned
-  if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Q)) % 16 != 0) cfg.vec = 1;
+  if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Q)) % 16 != 0) {
+    cfg.vec = 1;
+    cfg.bw = 0;
+  }
   Staging stg;
-  const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg));
-  const int ag = apply_grid(cfg, (int)p);
+  const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg), cfg.bw);
+  const int ag = apply_grid(cfg, (int)p, (int)n);
   char* img = nullptr;
   double* part = nullptr;
   auto layout = [&](Arena& a) {

@@ -361,32 +361,71 @@ struct EpiDot2 {
   }
 };
 
+// Diagonals of L_c within half-bandwidth BW, stored diagonal-major:
+// v[(d + BW) * ldb + j] = L_c[j, j + d] (zero where there is no edge), for
+// d in [-BW, BW]; bit d + BW of `nonempty` is set when diagonal d holds an
+// entry. Entries farther from the diagonal stay in the sliced-ELL remainder.
+template <typename T>
+struct BandDev {
+  const T* v;
+  int ldb;
+  unsigned long long nonempty;
+};
+
 // ---------------------------------------------------------------------------
 // The fused two-sided product on rows [i0, i0 + rows) of a p x n operand
 // stored with row stride ld (ld >= n rounded up to VEC; padding columns hold
 // zeros and the masks are padded with zeros, so padding outputs are zero).
 // VEC consecutive columns per thread, kThreads * VEC columns per pass.
-//   LDS = true : the R rows live in LDS (R * ld * sizeof(T) bytes).
+//   LDS = true : the R rows live in LDS (R * pitch * sizeof(T) bytes, with
+//                pitch = ld + 2 * band_pad<BW, VEC>).
 //   LDS = false: X L_c gathers from global memory (through the L1).
+//   BW > 0     : L_c entries within BW of the diagonal come from BandDev; each
+//                thread loads its window of 2 BW + VEC consecutive row values
+//                with aligned 16-byte LDS reads (conflict-free) and applies
+//                the diagonals from registers. Requires LDS and VEC = 16 / T.
 // Shared by the single-problem kernel and the batched (task-table) kernel.
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool LDS, int VEC, class Epi>
+template <int BW, int VEC>
+constexpr int band_pad() {
+  return BW == 0 ? 0 : (BW + VEC - 1) / VEC * VEC;
+}
+
+template <int BW, int VEC>
+constexpr int band_pitch_pad() {
+  return 2 * band_pad<BW, VEC>();
+}
+
+template <typename T, int R, bool LDS, int VEC, int BW, class Epi>
 __device__ __forceinline__ void apply_rows(const T* __restrict__ X, int ld, int n,
                                            const CsrDev<T>& Lr, const SellDev<T>& Lc,
+                                           const BandDev<T>& Lb,
                                            const uint8_t* __restrict__ mr,
                                            const uint8_t* __restrict__ mc, int i0, int rows,
                                            const Epi& epi, double* acc, T* panel) {
+  static_assert(BW == 0 || LDS, "the band path reads its windows from LDS");
   constexpr int H = kWave * VEC;         // SELL slice height
   constexpr int CPB = kThreads * VEC;    // columns per pass
+  constexpr int PAD = band_pad<BW, VEC>();
+  const int pitch = ld + 2 * PAD;        // LDS row pitch
   if (LDS) {
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       if (rr < rows) {
         const T* src = X + (size_t)(i0 + rr) * ld;
+        T* dst = panel + rr * pitch + PAD;
         for (int c = threadIdx.x * VEC; c < n; c += CPB) {
           T t[VEC];
           vld<T, VEC>(src + c, t);
-          vst<T, VEC>(panel + rr * ld + c, t);
+          vst<T, VEC>(dst + c, t);
+        }
+        if (PAD > 0) {
+          // zero the band padding on both sides and the columns past n
+          for (int c = threadIdx.x; c < PAD; c += kThreads) {
+            dst[c - PAD] = T(0);
+            dst[ld + c] = T(0);
+          }
+          for (int c = n + threadIdx.x; c < ld; c += kThreads) dst[c] = T(0);
         }
       }
     }
@@ -400,7 +439,38 @@ __device__ __forceinline__ void apply_rows(const T* __restrict__ X, int ld, int 
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) accc[rr][v] = T(0);
+    T xw[R][VEC];  // own values (filled from the band windows when BW > 0)
+    if constexpr (BW > 0) {
+      constexpr int WIN = 2 * PAD + VEC;
+      T win[R][WIN];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        if (rr < rows) {
+          const T* base = panel + rr * pitch + c0;  // = row column c0 - PAD
+#pragma unroll
+          for (int q = 0; q < WIN; q += VEC) {
+            T t[VEC];
+            vld<T, VEC>(base + q, t);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) win[rr][q + v] = t[v];
+          }
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) xw[rr][v] = win[rr][PAD + v];
+        }
+      }
+#pragma unroll
+      for (int d = -BW; d <= BW; ++d) {
+        if (!((Lb.nonempty >> (d + BW)) & 1ull)) continue;
+        T vv[VEC];
+        vld<T, VEC>(Lb.v + (size_t)(d + BW) * Lb.ldb + c0, vv);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) accc[rr][v] += vv[v] * win[rr][PAD + v + d];
+      }
+    }
     {
+      // sliced-ELL part (all of L_c when BW = 0, the far entries otherwise)
       const int s = c0 / H;
       const int beg = Lc.sp[s];
       const int w = (Lc.sp[s + 1] - beg) / H;
@@ -414,7 +484,7 @@ __device__ __forceinline__ void apply_rows(const T* __restrict__ X, int ld, int 
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
           if (rr < rows) {
-            const T* rowp = LDS ? panel + rr * ld : X + (size_t)(i0 + rr) * ld;
+            const T* rowp = LDS ? panel + rr * pitch + PAD : X + (size_t)(i0 + rr) * ld;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) accc[rr][v] += vv[v] * rowp[kk[v]];
           }
@@ -444,10 +514,14 @@ __device__ __forceinline__ void apply_rows(const T* __restrict__ X, int ld, int 
         }
         const size_t idx = (size_t)i * ld + c0;
         T x[VEC], mx[VEC];
-        if (LDS)
-          vld<T, VEC>(panel + rr * ld + c0, x);
-        else
+        if constexpr (BW > 0) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) x[v] = xw[rr][v];
+        } else if (LDS) {
+          vld<T, VEC>(panel + rr * pitch + c0, x);
+        } else {
           vld<T, VEC>(X + idx, x);
+        }
         const uint8_t mri = mr[i];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) mx[v] = (mri & mcv[v]) ? x[v] : T(0);
@@ -462,9 +536,9 @@ __device__ __forceinline__ void apply_rows(const T* __restrict__ X, int ld, int 
 // so that each XCD (workgroups are dealt to XCDs round-robin) owns `per`
 // consecutive row blocks. Workgroups past the last row block only write
 // zero partials.
-template <typename T, int R, bool LDS, int VEC, class Epi>
+template <typename T, int R, bool LDS, int VEC, int BW, class Epi>
 __global__ void __launch_bounds__(kThreads)
-k_apply2(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc,
+k_apply2(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc, BandDev<T> Lb,
          const uint8_t* __restrict__ mr, const uint8_t* __restrict__ mc, int nrb, int per,
          Epi epi) {
   if (epi.prologue()) return;
@@ -476,8 +550,147 @@ k_apply2(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc,
   const int rb = (b & 7) * per + (b >> 3);
   if (rb < nrb) {
     const int i0 = rb * R;
-    apply_rows<T, R, LDS, VEC, Epi>(X, n, n, Lr, Lc, mr, mc, i0, min(R, p - i0), epi, acc,
-                                    reinterpret_cast<T*>(smem_raw));
+    apply_rows<T, R, LDS, VEC, BW, Epi>(X, n, n, Lr, Lc, Lb, mr, mc, i0, min(R, p - i0), epi,
+                                        acc, reinterpret_cast<T*>(smem_raw));
+  }
+  if (epi.partials) block_partials<Epi::NV>(acc, epi.partials);
+}
+
+// ---------------------------------------------------------------------------
+// Column-strip variant for a banded L_c (BW > 0). A workgroup of kStripThreads
+// threads owns the strip of columns [s * CW, s * CW + CW), CW = kStripThreads *
+// VEC, and walks RB consecutive rows. The band diagonals of its columns stay
+// in registers for all RB rows; each row's strip segment plus a halo of PAD
+// columns on both sides is staged in LDS (double-buffered, one barrier per
+// row) and every thread reads its window of 2 PAD + VEC values with aligned
+// 16-byte LDS loads. Entries of L_c farther than BW from the diagonal (the
+// sliced-ELL remainder) are gathered from global memory.
+// Grid: 8 * cpx * nstrips workgroups. XCD x (workgroups are dealt to XCDs
+// round-robin) owns row chunks [x * cpx, (x + 1) * cpx) and sweeps them strip
+// by strip, so the neighbour rows of L_r X are reused from its L2.
+// Requires n % VEC == 0 (row stride n).
+// ---------------------------------------------------------------------------
+constexpr int kStripThreads = 128;
+
+template <typename T, int VEC, int BW, int RB, class Epi>
+__global__ void __launch_bounds__(kStripThreads)
+k_apply_strip(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc, BandDev<T> Lb,
+              const uint8_t* __restrict__ mr, const uint8_t* __restrict__ mc, int nchunks,
+              int cpx, Epi epi) {
+  if (epi.prologue()) return;
+  constexpr int PAD = band_pad<BW, VEC>();
+  constexpr int CW = kStripThreads * VEC;
+  constexpr int SEG = CW + 2 * PAD;   // staged values per row
+  constexpr int WIN = 2 * PAD + VEC;  // window per thread
+  constexpr int H = kWave * VEC;      // SELL slice height
+  __shared__ __align__(16) T seg[2][SEG];
+  double acc[Epi::NV];
+#pragma unroll
+  for (int k = 0; k < Epi::NV; ++k) acc[k] = 0.0;
+
+  const int b = blockIdx.x;
+  const int x = b & 7;
+  const int l = b >> 3;
+  const int strip = l / cpx;
+  const int chunk = x * cpx + (l - strip * cpx);
+  const int cs = strip * CW;
+  if (chunk < nchunks && cs < n) {
+    const int i0 = chunk * RB;
+    const int i1 = min(p, i0 + RB);
+    const int c0 = cs + threadIdx.x * VEC;
+    const bool ok = c0 < n;
+    // band diagonals of this thread's columns (zero for empty diagonals)
+    T vb[2 * BW + 1][VEC];
+#pragma unroll
+    for (int d = 0; d <= 2 * BW; ++d) {
+      if (ok && ((Lb.nonempty >> d) & 1ull)) {
+        vld<T, VEC>(Lb.v + (size_t)d * Lb.ldb + c0, vb[d]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) vb[d][v] = T(0);
+      }
+    }
+    uint8_t mcv[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) mcv[v] = ok ? mc[c0 + v] : 0;
+    // sliced-ELL remainder of these columns
+    int sbeg = 0, sw = 0;
+    if (ok) {
+      const int s = c0 / H;
+      sbeg = Lc.sp[s] + (c0 - s * H);
+      sw = (Lc.sp[s + 1] - Lc.sp[s]) / H;
+    }
+    // stage the first row
+    auto stage = [&](int i, T* dst) {
+      const T* src = X + (size_t)i * n;
+      if (ok) {
+        T t[VEC];
+        vld<T, VEC>(src + c0, t);
+        vst<T, VEC>(dst + PAD + threadIdx.x * VEC, t);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) dst[PAD + threadIdx.x * VEC + v] = T(0);
+      }
+      if (threadIdx.x < PAD) {
+        const int cl = cs - PAD + (int)threadIdx.x;  // left halo
+        dst[threadIdx.x] = cl >= 0 ? src[cl] : T(0);
+        const int cr = cs + CW + (int)threadIdx.x;   // right halo
+        dst[PAD + CW + threadIdx.x] = cr < n ? src[cr] : T(0);
+      }
+    };
+    stage(i0, seg[0]);
+    __syncthreads();
+    for (int i = i0; i < i1; ++i) {
+      const int buf = (i - i0) & 1;
+      if (i + 1 < i1) stage(i + 1, seg[buf ^ 1]);
+      // window of this thread: columns c0 - PAD .. c0 + VEC + PAD - 1
+      T win[WIN];
+#pragma unroll
+      for (int q = 0; q < WIN; q += VEC) {
+        T t[VEC];
+        vld<T, VEC>(&seg[buf][threadIdx.x * VEC + q], t);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) win[q + v] = t[v];
+      }
+      if (ok) {
+        T accc[VEC], accr[VEC], xv[VEC], mx[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) accc[v] = T(0);
+#pragma unroll
+        for (int d = -BW; d <= BW; ++d)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) accc[v] += vb[d + BW][v] * win[PAD + v + d];
+        const T* rowp = X + (size_t)i * n;
+        for (int e = 0; e < sw; ++e) {
+          int kk[VEC];
+          T vv[VEC];
+          vld<int, VEC>(Lc.ci + sbeg + e * H, kk);
+          vld<T, VEC>(Lc.v + sbeg + e * H, vv);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) accc[v] += vv[v] * rowp[kk[v]];
+        }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) accr[v] = T(0);
+        const int e0 = Lr.rp[i];
+        const int e1 = Lr.rp[i + 1];
+#pragma unroll 4
+        for (int e = e0; e < e1; ++e) {
+          const T w = Lr.v[e];
+          T t[VEC];
+          vld<T, VEC>(X + (size_t)Lr.ci[e] * n + c0, t);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) accr[v] += w * t[v];
+        }
+        const uint8_t mri = mr[i];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          xv[v] = win[PAD + v];
+          mx[v] = (mri & mcv[v]) ? xv[v] : T(0);
+        }
+        epi.template apply<VEC>(i, (size_t)i * n + c0, xv, mx, accr, accc, acc);
+      }
+      __syncthreads();
+    }
   }
   if (epi.partials) block_partials<Epi::NV>(acc, epi.partials);
 }

@@ -73,9 +73,13 @@ def test_apply_matches_oracle_random_graphs(shape, dtype):
 
 
 @pytest.mark.parametrize("n", [333, 600, 1100])
-@pytest.mark.parametrize("R,lds", [(1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (4, 0)])
+@pytest.mark.parametrize("R,lds", [(0, -1), (1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (4, 0)])
 def test_apply_every_launch_shape(R, lds, n):
-    # n = 333 / 600 / 1100 selects 1 / 2 / 4 columns per thread, all ragged
+    # n = 333: scalar columns; 600 / 1100: 16-byte vectors, ragged; the circle
+    # column graph is banded (plus wrap-around entries), so the default shape
+    # (R = 0) takes the column-strip kernel with a partial last strip and a
+    # partial last row chunk, and R = 1, 2, 4 with LDS take the row-panel band
+    # kernel
     _announce(f"apply launch shape R={R} lds={lds} n={n}")
     P_ = synth.small_problem(3, p_shape=(11, 13), n=n, rank=3, frac=0.3)
     rng = np.random.default_rng(5)
