@@ -58,8 +58,10 @@ typedef enum {
 typedef enum {
   CPCA_FP64 = 0,     /* everything in FP64                                   */
   CPCA_FP32 = 1,     /* FP32 vectors and sparse products, FP64 CG scalars    */
-  CPCA_FP32_IR = 2   /* FP32 inner CG inside FP64 iterative refinement: the
-                        residual B - A(X) and the solution accumulate in FP64 */
+  CPCA_FP32_IR = 2   /* FP32 CG with FP64 residual replacement: the solution
+                        accumulates in FP64 and the FP32 residual is replaced
+                        by the FP64 residual B - A(X) whenever it has dropped
+                        by 100x (the search direction is kept)             */
 } cpca_mode;
 
 typedef struct {
@@ -72,7 +74,7 @@ typedef struct {
 
 typedef struct {
   int32_t iters;           /* FISTA iterations run / total CG iterations     */
-  int32_t outer_iters;     /* refinement steps (CPCA_FP32_IR), else 0        */
+  int32_t outer_iters;     /* FP64 residual replacements (CPCA_FP32_IR)      */
   int32_t status;          /* same value as the call's return code           */
   int32_t reserved;
   double rel_residual;     /* decode: FP64 ||B - A(X)||_F / ||B||_F of the
@@ -140,10 +142,11 @@ cpca_status cpca_frpcag(cpca_handle h, cpca_mode mode,
  * Lr, Lc      p x p and n x n Laplacians; gamma_r/_c >= 0 and finite.
  * tol         > 0: stop when ||B - A(X)||_F <= tol ||B||_F, measured on the CG
  *             recursive residual (FP64 and FP32 modes) or on the true FP64
- *             residual of each refinement step (FP32_IR). info.rel_residual
- *             always reports the true FP64 residual of the returned X.
- * max_iter    > 0: cap on CG iterations (in FP32_IR: per inner solve; at
- *             most 40 refinement steps).
+ *             residual computed at each replacement (FP32_IR).
+ *             info.rel_residual always reports the true FP64 residual of the
+ *             returned X.
+ * max_iter    > 0: cap on CG iterations (FP32_IR: in total, with at most 40
+ *             residual replacements).
  * X0          optional p x n warm start (NULL: zero).
  * X_out       p x n solution.
  * Returns OK, EINVAL, ENOCONV, ENOTSPD (gamma = 0 with partial sampling can

@@ -273,21 +273,31 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
     k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
     LAUNCHCHK();
   } else {
-    // FP32 inner CG inside FP64 iterative refinement
+    // FP32 CG with residual replacement ("reliable updates"): the FP32
+    // recursion runs until its residual has dropped by kReplace against the
+    // last true residual; then the FP32 iterate is folded into X64, the true
+    // residual B - A(X64) is recomputed in FP64 and replaces the FP32 one, and
+    // CG continues with the same search direction (no restart, so the
+    // iteration count stays close to that of FP64 CG).
+    constexpr double kReplace = 1e-2;
     Operator<float> op{(int)p, (int)n, g32, (float)gr, (float)gc, cfg32};
     if (X0)
       k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, static_cast<const float*>(X0), N);
     else
       k_fill<double><<<vg, kThreads, 0, h->stream>>>(X64, 0.0, N);
     LAUNCHCHK();
-    double rel_prev = 1.0;
-    int total = 0;
-    done = 0;
-    for (int outer = 0;; ++outer) {
-      const double inner_tol = std::min(0.25, std::max(1e-5, 0.5 * tol / rel_prev));
+    const double floor2 = 0.09 * tol * tol * bb;  // segments need not go below (0.3 tol)^2 bb
+    {
+      // first residual: r = p = round(B - A X), x32 = 0
       EpiResidual<double, float> epi{B64, r32, p32, x32, gr, gc, pa};
       STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, FAM_OTHER));
-      k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag64, -1.0, inner_tol * inner_tol);
+    }
+    int total = 0;
+    done = 0;
+    for (int seg = 0;; ++seg) {
+      // arm from the residual partials: the segment stops at
+      // max(kReplace^2 ||r||^2, floor2)
+      k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag64, -1.0, kReplace * kReplace);
       LAUNCHCHK();
       STCHK(read_fixed(h));
       const CgScal cs = host_cg(h);
@@ -296,26 +306,32 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
         break;
       }
       const double rel = std::sqrt(cs.res2 / bb);
-      so.outer = outer;
+      so.outer = seg;
       if (rel <= tol) {
         done = 1;
         break;
       }
-      if (outer >= kMaxOuter) {
+      if (seg >= kMaxOuter || total >= max_iter) {
         done = 0;
         break;
       }
-      if (outer == 0) STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
-      STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
+      if (cs.thr < floor2) {
+        k_cg_set_thr<<<1, 1, 0, h->stream>>>(sc, floor2);
+        LAUNCHCHK();
+      }
+      if (seg == 0) STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
+      STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part));
       const CgScal ci = host_cg(h);
       total += ci.iter;
       if (ci.done == 2 || ci.done == 3) {
         done = ci.done;
         break;
       }
+      // replacement: X64 += x32; r = round(B - A X64); x32 = 0; p kept
       k_accumulate<float><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
       LAUNCHCHK();
-      rel_prev = rel;
+      EpiResidual<double, float> epi{B64, r32, nullptr, x32, gr, gc, pa};
+      STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, FAM_OTHER));
     }
     so.iters = total;
   }

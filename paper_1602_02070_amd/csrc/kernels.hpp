@@ -208,9 +208,10 @@ struct EpiCg : EpiApply<T> {
   __device__ bool prologue() const { return sc->done != 0; }
 };
 
-// Residual R = B - A(X) computed in T, stored rounded to TO into r_out and
-// p_out (initial residual and direction of a CG solve); x_out (the CG
-// iterate), if given, is cleared. Partials: ||R||^2 and ||round(R)||^2.
+// Residual R = B - A(X) computed in T, stored rounded to TO into r_out and,
+// if given, p_out (initial residual and direction of a CG solve; a residual
+// replacement keeps the direction and passes null); x_out (the CG iterate),
+// if given, is cleared. Partials: ||R||^2 and ||round(R)||^2.
 template <typename T, typename TO>
 struct EpiResidual {
   static constexpr int NV = 2;
@@ -231,7 +232,7 @@ struct EpiResidual {
       const T R = b[v] - (mx[v] + gr * accr[v] + gc * accc[v]);
       const TO Rt = (TO)R;
       r_out[idx + v] = Rt;
-      p_out[idx + v] = Rt;
+      if (p_out) p_out[idx + v] = Rt;
       if (x_out) x_out[idx + v] = TO(0);
       acc[0] += (double)R * (double)R;
       acc[1] += (double)Rt * (double)Rt;
@@ -842,6 +843,14 @@ k_cg_arm(CgScal* sc, const double* part, int nb, double thr_abs, double rel_tol2
   sc->alpha = 0.0;
   sc->beta = 0.0;
   sc->done = (bad(t[0]) || bad(rr)) ? 3 : (rr <= thr ? 1 : 0);
+}
+
+// Raises the stop threshold of an armed CG solve to at least thr.
+static __global__ void k_cg_set_thr(CgScal* sc, double thr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (sc->thr < thr) sc->thr = thr;
+    if (sc->done == 0 && sc->rr[0] <= sc->thr) sc->done = 1;
+  }
 }
 
 // out[k] = sum of the partials (one workgroup).
