@@ -289,7 +289,10 @@ k_arm_batched(const BTask* __restrict__ tasks, const double* part, double thr_re
   CgScal* sc = tk.sc;
   if (FROM_APPLY) {
     if (!tk.active) {
-      if (threadIdx.x == 0) sc->done = 1;
+      if (threadIdx.x == 0) {
+        sc->conv_it = 0;
+        sc->done = 1;
+      }
       return;
     }
     double t[2];
@@ -300,6 +303,7 @@ k_arm_batched(const BTask* __restrict__ tasks, const double* part, double thr_re
       sc->rr[0] = sc->rr[1] = t[1];
       sc->thr = tk.inner_rel2 * t[1];
       sc->iter = 0;
+      sc->conv_it = 0;
       sc->done = (bad(t[0]) || bad(t[1])) ? 3 : (t[1] <= sc->thr ? 1 : 0);
     }
   } else {
@@ -309,6 +313,7 @@ k_arm_batched(const BTask* __restrict__ tasks, const double* part, double thr_re
       sc->rr[0] = sc->rr[1] = t[0];
       sc->thr = thr_rel2 * sc->bb;
       sc->iter = 0;
+      sc->conv_it = 0;
       sc->done = bad(t[0]) ? 3 : (t[0] <= sc->thr ? 1 : 0);
     }
   }

@@ -36,6 +36,7 @@ struct cpca_handle_s {
   int force_R = 0;             // launch-shape override (0: default, -1: autotune)
   int force_lds = -1;          // LDS override (-1: default)
   int force_band = -1;         // band path override (0: off, -1: automatic)
+  bool debug = false;          // per-segment trace on stderr (CPCA_DEBUG=1)
   std::vector<std::pair<std::string, std::pair<int, int>>> tuned;  // autotuner cache
   bool prof = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)

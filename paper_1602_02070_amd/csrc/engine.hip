@@ -38,7 +38,7 @@ cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, 
   const size_t N = (size_t)op.p * op.n;
   CgScal* sc = cg_ptr(h);
   STCHK(read_fixed(h));
-  if (host_cg(h).done) return CPCA_OK;
+  if (host_cg(h).done || host_cg(h).conv_it) return CPCA_OK;
   int it = 0;
   int chunk = 4;
   const int ag = apply_grid(op.cfg, op.p, op.n);
@@ -62,7 +62,7 @@ cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, 
     }
     STCHK(read_fixed(h));
     STCHK(prof_collect(h));
-    if (host_cg(h).done) break;
+    if (host_cg(h).done || host_cg(h).conv_it) break;
     chunk = std::min(chunk * 2, 64);
   }
   return CPCA_OK;
@@ -249,7 +249,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
     STCHK(tuned_cfg<double>(h, op, P, p64, q64, pa, &op.cfg));
     STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, part));
     so.iters = host_cg(h).iter;
-    done = host_cg(h).done;
+    done = host_cg(h).done ? host_cg(h).done : (host_cg(h).conv_it ? 1 : 0);
   } else if (mode == CPCA_FP32) {
     Operator<float> op{(int)p, (int)n, g32, (float)gr, (float)gc, cfg32};
     k_convert<double, float><<<vg, kThreads, 0, h->stream>>>(B32, B64, N);
@@ -269,7 +269,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
     STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
     STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
     so.iters = host_cg(h).iter;
-    done = host_cg(h).done;
+    done = host_cg(h).done ? host_cg(h).done : (host_cg(h).conv_it ? 1 : 0);
     k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
     LAUNCHCHK();
   } else {
@@ -322,6 +322,9 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
       if (seg == 0) STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
       STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part));
       const CgScal ci = host_cg(h);
+      if (h->debug)
+        std::fprintf(stderr, "[cpca] segment %d: rel %.3e aux %.3e thr %.3e -> iters %d done %d rr %.3e pq %.3e alpha %.3e beta %.3e\n",
+                     seg, rel, cs.aux, cs.thr, ci.iter, ci.done, ci.rr[ci.iter & 1], ci.pq, ci.alpha, ci.beta);
       total += ci.iter;
       if (ci.done == 2 || ci.done == 3) {
         done = ci.done;
@@ -485,6 +488,7 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
   if (const char* s = std::getenv("CPCA_APPLY_R")) h->force_R = std::atoi(s);
   if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
   if (const char* s = std::getenv("CPCA_BAND")) h->force_band = std::atoi(s);
+  if (const char* s = std::getenv("CPCA_DEBUG")) h->debug = std::atoi(s) != 0;
   *out = h;
   return CPCA_OK;
 }

@@ -66,6 +66,12 @@ struct CgScal {
   double bb;      // ||rhs||^2
   int iter;       // iterations completed
   int done;       // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
+  // Convergence detected by the p-update of iteration `it` is recorded as
+  // conv_it = it + 1 (-1: converged when armed). The p-update of the
+  // converging iteration still runs in full, so the direction stays valid
+  // for a residual replacement; later iterations see conv_it and skip.
+  int conv_it;
+  int pad0;
 };
 
 // Device-resident scalars of one FISTA run.
@@ -205,7 +211,7 @@ struct EpiApply {
 template <typename T>
 struct EpiCg : EpiApply<T> {
   const CgScal* sc;
-  __device__ bool prologue() const { return sc->done != 0; }
+  __device__ bool prologue() const { return sc->done != 0 || sc->conv_it != 0; }
 };
 
 // Residual R = B - A(X) computed in T, stored rounded to TO into r_out and,
@@ -708,7 +714,7 @@ __global__ void __launch_bounds__(kThreads)
 k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
             const T* __restrict__ q, size_t N, CgScal* sc, int it,
             const double* __restrict__ part_pq, int nb_pq, double* __restrict__ part_rr) {
-  if (sc->done != 0) return;
+  if (sc->done != 0 || sc->conv_it != 0) return;
   double t[1];
   sum_partials<1>(part_pq, nb_pq, t);
   const double pq = t[0];
@@ -756,11 +762,13 @@ k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
 }
 
 // beta = rr_new / rr; p = r + beta p; convergence test rr_new <= thr.
+// The converging iteration updates p as well (see CgScal::conv_it).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_cg_pupdate(T* __restrict__ p, const T* __restrict__ r, size_t N, CgScal* sc, int it,
              const double* __restrict__ part_rr, int nb_rr) {
   if (sc->done != 0) return;
+  if (sc->conv_it != 0 && sc->conv_it <= it) return;
   double t[1];
   sum_partials<1>(part_rr, nb_rr, t);
   const double rr_new = t[0];
@@ -773,19 +781,12 @@ k_cg_pupdate(T* __restrict__ p, const T* __restrict__ r, size_t N, CgScal* sc, i
     }
     return;
   }
-  if (rr_new <= sc->thr) {
-    if (lead) {
-      sc->rr[(it + 1) & 1] = rr_new;
-      sc->iter = it + 1;
-      sc->done = 1;
-    }
-    return;
-  }
   const double beta_d = rr_new / rr;
   if (lead) {
     sc->rr[(it + 1) & 1] = rr_new;
     sc->beta = beta_d;
     sc->iter = it + 1;
+    if (rr_new <= sc->thr) sc->conv_it = it + 1;
   }
   const T beta = (T)beta_d;
   constexpr int W = V16<T>::W;
@@ -842,14 +843,15 @@ k_cg_arm(CgScal* sc, const double* part, int nb, double thr_abs, double rel_tol2
   sc->iter = 0;
   sc->alpha = 0.0;
   sc->beta = 0.0;
-  sc->done = (bad(t[0]) || bad(rr)) ? 3 : (rr <= thr ? 1 : 0);
+  sc->done = (bad(t[0]) || bad(rr)) ? 3 : 0;
+  sc->conv_it = (sc->done == 0 && rr <= thr) ? -1 : 0;
 }
 
 // Raises the stop threshold of an armed CG solve to at least thr.
 static __global__ void k_cg_set_thr(CgScal* sc, double thr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     if (sc->thr < thr) sc->thr = thr;
-    if (sc->done == 0 && sc->rr[0] <= sc->thr) sc->done = 1;
+    if (sc->done == 0 && sc->conv_it == 0 && sc->rr[0] <= sc->thr) sc->conv_it = -1;
   }
 }
 
