@@ -73,7 +73,7 @@ def _declare(lib):
         "cpca_check_index_set_host": (st, [c_int64, c_int64, P]),
         "cpca_set_profiling": (st, [P, c_int32]),
         "cpca_get_profile": (st, [P, c_char_p, POINTER(c_int64), POINTER(c_double)]),
-        "cpca_set_apply_config": (st, [P, c_int32, c_int32]),
+        "cpca_set_apply_config": (st, [P, c_int32, c_int32, c_int32]),
         "cpca_solve_batched": (st, [P, c_int32, POINTER(CpcaInstance), c_int32, POINTER(CpcaTask),
                                     c_int32, c_int32, c_double, c_int32, POINTER(CpcaInfo)]),
     }

@@ -64,10 +64,18 @@ def profiling(enable: bool, h=None) -> None:
     _check(lib.cpca_set_profiling(h or handle(), int(bool(enable))), "cpca_set_profiling")
 
 
-def set_apply_config(rows_per_block: int = 0, use_lds: int = -1, h=None) -> None:
-    """Launch shape of the fused two-sided product (0 / -1 = automatic)."""
+KERNELS = {"auto": -1, "rows": 0, "strip": 1, "panel": 2}
+
+
+def set_apply_config(rows_per_block: int = 0, use_lds: int = -1, kernel: str = "auto",
+                     h=None) -> None:
+    """Launch shape of the fused two-sided product (0 / -1 = automatic).
+
+    kernel: preference for a banded L_c, one of "auto", "rows", "strip",
+    "panel" (see cpca_set_apply_config)."""
     lib = _lib.load()
-    _check(lib.cpca_set_apply_config(h or handle(), int(rows_per_block), int(use_lds)),
+    _check(lib.cpca_set_apply_config(h or handle(), int(rows_per_block), int(use_lds),
+                                     KERNELS[kernel]),
            "cpca_set_apply_config", allow_noconv=False)
 
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -36,6 +37,7 @@ struct cpca_handle_s {
   int force_R = 0;             // launch-shape override (0: default, -1: autotune)
   int force_lds = -1;          // LDS override (-1: default)
   int force_band = -1;         // band path override (0: off, -1: automatic)
+  int force_kernel = -1;       // banded-L_c kernel preference (-1 auto, 0 rows, 1 strip, 2 panel)
   bool debug = false;          // per-segment trace on stderr (CPCA_DEBUG=1)
   std::vector<std::pair<std::string, std::pair<int, int>>> tuned;  // autotuner cache
   bool prof = false;
@@ -189,6 +191,7 @@ struct DevGraph {
   CsrDev<T> Lr{};
   SellDev<T> Lc{};
   BandDev<T> Lb{};
+  PanelDev<T> Lp{};
   const uint8_t* mr = nullptr;
   const uint8_t* mc = nullptr;
 };
@@ -208,7 +211,111 @@ struct GraphImage {
   size_t o_rp, o_ci, o_v, o_sp, o_sci, o_sv, o_mr, o_mc, o_bv;
   int ldb;                      // band row stride (0: no band)
   unsigned long long nonempty;  // band diagonals holding an entry
+  int npan;                     // panels of L_r rows (0: no panel tables)
+  size_t o_pu_off, o_pu, o_pr_off, o_prows, o_peidx, o_pew, o_pmeta, o_pdiag;
 };
+
+// ------------------------------------------------------------------ panels
+// Row panels of L_r for the row-panel gather kernel (k_apply_panel).
+struct HostPanels {
+  int npan = 0;
+  std::vector<int32_t> u_off, u, r_off, rows, meta;  // meta: 4 ints per row
+  std::vector<uint16_t> eidx;
+  std::vector<double> ew, diag;
+};
+
+// Greedy grouping of the rows of L_r: a panel starts at the lowest row not
+// yet assigned and repeatedly takes, among the unassigned rows already in its
+// union U (the rows its L_r entries reference, itself included), the one
+// whose entries add the fewest new rows to U (ties: lowest index), while the
+// panel holds at most rmax rows and U at most umax. Rows of a panel and their
+// neighbourhoods therefore overlap, which is what makes staging U once per
+// panel cheaper than one read per entry. Returns false when a row has more
+// than kPanelK off-diagonal entries (the kernel's table width).
+inline bool build_panels(const HostCsr& Lr, const std::vector<uint8_t>& mr, int rmax, int umax,
+                         HostPanels& P) {
+  P = HostPanels{};
+  const int64_t p64 = Lr.n;
+  if (p64 <= 0 || p64 >= INT_MAX) return false;
+  const int p = (int)p64;
+  for (int i = 0; i < p; ++i) {
+    int c = 0;
+    for (int32_t e = Lr.rp[i]; e < Lr.rp[i + 1]; ++e) c += Lr.ci[e] != i;
+    if (c > kPanelK) return false;
+  }
+  std::vector<char> assigned((size_t)p, 0);
+  std::vector<int> stamp((size_t)p, -1), loc((size_t)p, -1);
+  std::vector<int> U, R, cand;
+  P.u_off.push_back(0);
+  P.r_off.push_back(0);
+  int seed = 0, k = 0;
+  for (;;) {
+    while (seed < p && assigned[(size_t)seed]) ++seed;
+    if (seed == p) break;
+    U.clear();
+    R.clear();
+    cand.clear();
+    auto added_by = [&](int v) {  // rows v would add to U
+      int c = stamp[(size_t)v] != k;
+      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e) c += stamp[(size_t)Lr.ci[e]] != k;
+      return c;
+    };
+    auto take = [&](int v) {
+      R.push_back(v);
+      assigned[(size_t)v] = 1;
+      auto ins = [&](int w) {
+        if (stamp[(size_t)w] == k) return;
+        stamp[(size_t)w] = k;
+        U.push_back(w);
+        if (!assigned[(size_t)w]) cand.push_back(w);
+      };
+      ins(v);
+      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e) ins(Lr.ci[e]);
+    };
+    take(seed);
+    while ((int)R.size() < rmax) {
+      int best = -1, bc = INT_MAX;
+      for (int c : cand) {
+        if (assigned[(size_t)c]) continue;
+        const int nc = added_by(c);
+        if (nc < bc || (nc == bc && c < best)) {
+          bc = nc;
+          best = c;
+        }
+      }
+      if (best < 0 || (int)U.size() + bc > umax) break;
+      take(best);
+    }
+    std::sort(U.begin(), U.end());
+    for (size_t i = 0; i < U.size(); ++i) loc[(size_t)U[i]] = (int)i;
+    P.u.insert(P.u.end(), U.begin(), U.end());
+    for (int v : R) {
+      const size_t base = P.eidx.size();
+      P.eidx.resize(base + kPanelK, 0);
+      P.ew.resize(base + kPanelK, 0.0);
+      int c = 0;
+      double dg = 0.0;
+      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e) {
+        if (Lr.ci[e] == v) {
+          dg += Lr.v[e];
+          continue;
+        }
+        P.eidx[base + c] = (uint16_t)loc[(size_t)Lr.ci[e]];
+        P.ew[base + c] = Lr.v[e];
+        ++c;
+      }
+      P.rows.push_back(v);
+      P.diag.push_back(dg);
+      const int m4[4] = {v, loc[(size_t)v] | (c << 16), (int)mr[(size_t)v], 0};
+      P.meta.insert(P.meta.end(), m4, m4 + 4);
+    }
+    ++k;
+    P.u_off.push_back((int)P.u.size());
+    P.r_off.push_back((int)P.rows.size());
+  }
+  P.npan = k;
+  return true;
+}
 
 // Half-bandwidth of the diagonal (band) part of L_c: the smallest of 8 and
 // 16 that holds at least 90% of the entries, else 0 (sliced ELL only).
@@ -232,8 +339,24 @@ inline int choose_band(const HostCsr& Lc) {
 template <typename T>
 GraphImage<T> stage_graph(Staging& st, const HostCsr& Lr, const HostCsr& Lc,
                           const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int H,
-                          int BW = 0) {
+                          int BW = 0, bool panels = false) {
   GraphImage<T> g{};
+  g.npan = 0;
+  if (BW > 0 && panels) {
+    HostPanels hp;
+    if (build_panels(Lr, mr, kPanelRows, PanelUnion<T>::value, hp) && hp.npan > 0) {
+      g.npan = hp.npan;
+      g.o_pu_off = st.add(hp.u_off.data(), sizeof(int32_t) * hp.u_off.size());
+      g.o_pu = st.add(hp.u.data(), sizeof(int32_t) * hp.u.size());
+      g.o_pr_off = st.add(hp.r_off.data(), sizeof(int32_t) * hp.r_off.size());
+      g.o_prows = st.add(hp.rows.data(), sizeof(int32_t) * hp.rows.size());
+      g.o_peidx = st.add(hp.eidx.data(), sizeof(uint16_t) * hp.eidx.size());
+      std::vector<T> ew(hp.ew.begin(), hp.ew.end()), dg(hp.diag.begin(), hp.diag.end());
+      g.o_pew = st.add(ew.data(), sizeof(T) * ew.size());
+      g.o_pmeta = st.add(hp.meta.data(), sizeof(int32_t) * hp.meta.size());
+      g.o_pdiag = st.add(dg.data(), sizeof(T) * dg.size());
+    }
+  }
   std::vector<T> vr(Lr.v.begin(), Lr.v.begin() + Lr.nnz);
   g.o_rp = st.add(Lr.rp.data(), sizeof(int32_t) * Lr.rp.size());
   g.o_ci = st.add(Lr.ci.data(), sizeof(int32_t) * std::max<int64_t>(Lr.nnz, 1));
@@ -312,6 +435,17 @@ DevGraph<T> bind_graph(const GraphImage<T>& g, const char* dev) {
   d.Lb.v = g.ldb ? reinterpret_cast<const T*>(dev + g.o_bv) : nullptr;
   d.Lb.ldb = g.ldb;
   d.Lb.nonempty = g.nonempty;
+  d.Lp.npan = g.npan;
+  if (g.npan > 0) {
+    d.Lp.u_off = reinterpret_cast<const int*>(dev + g.o_pu_off);
+    d.Lp.u = reinterpret_cast<const int*>(dev + g.o_pu);
+    d.Lp.r_off = reinterpret_cast<const int*>(dev + g.o_pr_off);
+    d.Lp.rows = reinterpret_cast<const int*>(dev + g.o_prows);
+    d.Lp.eidx = reinterpret_cast<const uint16_t*>(dev + g.o_peidx);
+    d.Lp.ew = reinterpret_cast<const T*>(dev + g.o_pew);
+    d.Lp.meta = reinterpret_cast<const int4*>(dev + g.o_pmeta);
+    d.Lp.diag = reinterpret_cast<const T*>(dev + g.o_pdiag);
+  }
   return d;
 }
 
@@ -322,7 +456,11 @@ struct ApplyCfg {
   int vec = 1;  // columns per thread (16-byte accesses when > 1)
   int bw = 0;   // band half-width of L_c (0: sliced ELL only)
   bool strip = false;  // column-strip kernel (needs bw > 0 and full vectors)
+  bool panel = false;  // row-panel gather kernel (needs bw > 0, full vectors, panel tables)
+  int npan = 0;        // panels in the staged image
 };
+
+constexpr int kPanelGroup = 2;  // consecutive panels per workgroup of the panel kernel
 
 constexpr int kStripRows = 16;  // rows per workgroup of the column-strip kernel
 
@@ -337,7 +475,8 @@ inline size_t lds_bytes(const ApplyCfg& c, int64_t ld, size_t elem) {
 // fit in 64 KiB of LDS. `band` is the candidate band half-width of L_c
 // (choose_band); it is used when the rows are staged in LDS with full
 // 16-byte vectors.
-ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem, int band = 0) {
+ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem, int band = 0,
+                    bool allow_panel = false) {
   ApplyCfg c;
   const int W = (int)(16 / elem);
   c.vec = (n % W == 0) ? W : 1;
@@ -352,12 +491,18 @@ ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem, int band =
   c.bw = 0;
   c.strip = false;
   if (band > 0 && c.vec == W && h->force_band != 0) {
-    if (h->force_R <= 0 && h->force_lds != 0) {
-      // banded L_c: column strips with the diagonals held in registers
+    if (h->force_R <= 0 && h->force_lds != 0 && h->force_kernel != 0) {
+      // banded L_c: column strips with the diagonals held in registers, or
+      // (preferred where panel tables exist) the row-panel gather kernel
       c.bw = band;
       c.strip = h->force_band != 2;
+      // (FP64 rows need twice the registers; there the strip kernel measured faster)
+      if (c.strip && allow_panel && h->force_kernel != 1 && (elem == 4 || h->force_kernel == 2)) {
+        c.panel = true;
+        c.strip = false;
+      }
     }
-    if (!c.strip && c.lds && c.R <= 4) {
+    if (!c.strip && !c.panel && c.lds && c.R <= 4) {
       ApplyCfg t = c;
       t.bw = band;
       c.bw = lds_bytes(t, n, elem) <= 65536 ? band : 0;
@@ -367,6 +512,25 @@ ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem, int band =
 }
 
 int slice_height(const ApplyCfg& c) { return kWave * c.vec; }
+
+// Records the staged panel count; a panel shape without panel tables (a row
+// of L_r too long for the table) falls back to the column-strip kernel.
+inline void set_panels(ApplyCfg& c, int npan) {
+  c.npan = npan;
+  if (c.panel && npan == 0) {
+    c.panel = false;
+    c.strip = true;
+  }
+}
+
+// Workgroups of the panel kernel for npan panels of a p x n operand with
+// `vec` elements per 16 bytes.
+inline int panel_grid(int npan, int n, int vec) {
+  const int w = kPanelLanes * vec;
+  const int nstrips = (n + w - 1) / w;
+  const int ngroups = (npan + kPanelGroup - 1) / kPanelGroup;
+  return 8 * ((ngroups + 7) / 8) * nstrips;
+}
 
 int vec_grid(size_t N) {
   const size_t b = (N + kThreads - 1) / kThreads;
@@ -383,6 +547,7 @@ int max_apply_grid(int p, int n) {
 
 // Workgroups of one fused-product launch (= partial sums written).
 int apply_grid(const ApplyCfg& cfg, int p, int n = 0) {
+  if (cfg.panel) return panel_grid(cfg.npan, n, cfg.vec);
   if (cfg.strip) {
     const int cw = kStripThreads * cfg.vec;
     const int nstrips = (n + cw - 1) / cw;
@@ -419,10 +584,30 @@ hipError_t launch_strip_t(cpca_handle h, const T* X, int p, int n, const DevGrap
   return hipGetLastError();
 }
 
+template <typename T, int BW, class Epi>
+hipError_t launch_panel_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
+                          const Epi& epi) {
+  if (g.Lp.npan <= 0) return hipErrorInvalidValue;
+  constexpr int W = kPanelLanes * (int)(16 / sizeof(T));
+  const int nstrips = (n + W - 1) / W;
+  const int ngroups = (g.Lp.npan + kPanelGroup - 1) / kPanelGroup;
+  const int gpx = (ngroups + 7) / 8;
+  static_assert(kPanelGroup <= kPanelGroupMax, "panel group");
+  k_apply_panel<T, BW, Epi><<<dim3(8 * gpx * nstrips), dim3(kThreads), 0, h->stream>>>(
+      X, p, n, g.Lp, g.Lc, g.Lb, g.mc, kPanelGroup, ngroups, gpx, epi);
+  return hipGetLastError();
+}
+
 template <typename T, int R, class Epi>
 hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p, int n,
                           const DevGraph<T>& g, const Epi& epi) {
   constexpr int W = (int)(16 / sizeof(T));
+  if (cfg.panel) {
+    if (cfg.vec != W || g.Lp.npan != cfg.npan) return hipErrorInvalidValue;
+    if (cfg.bw == 8) return launch_panel_t<T, 8>(h, X, p, n, g, epi);
+    if (cfg.bw == 16) return launch_panel_t<T, 16>(h, X, p, n, g, epi);
+    return hipErrorInvalidValue;
+  }
   if (cfg.strip) {
     if (cfg.vec != W) return hipErrorInvalidValue;
     if (cfg.bw == 8) return launch_strip_t<T, 8>(h, X, p, n, g, epi);
@@ -504,20 +689,21 @@ inline std::string tune_key(const char* kind, size_t elem, int64_t p, int64_t n,
 }
 
 // Cached shape: rows per workgroup and a mode (0: no LDS, 1: LDS rows,
-// 2: column strips).
+// 2: column strips, 3: row panels).
 inline bool tune_lookup(cpca_handle h, const std::string& key, ApplyCfg& c) {
   for (const auto& kv : h->tuned)
     if (kv.first == key) {
       c.R = kv.second.first;
       c.lds = kv.second.second != 0;
       c.strip = kv.second.second == 2;
+      c.panel = kv.second.second == 3;
       return true;
     }
   return false;
 }
 
 inline void tune_store(cpca_handle h, const std::string& key, const ApplyCfg& c) {
-  const int mode = c.strip ? 2 : (c.lds ? 1 : 0);
+  const int mode = c.panel ? 3 : (c.strip ? 2 : (c.lds ? 1 : 0));
   h->tuned.push_back({key, {c.R, mode}});
   if (const char* path = std::getenv("CPCA_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
@@ -535,7 +721,8 @@ inline void tune_load_file(cpca_handle h) {
   char key[200];
   int R, lds;
   while (std::fscanf(f, "%199s %d %d", key, &R, &lds) == 3) {
-    if (R == 1 || R == 2 || R == 4 || R == 8) h->tuned.push_back({key, {R, lds}});
+    if ((R == 1 || R == 2 || R == 4 || R == 8) && lds >= 0 && lds <= 3)
+      h->tuned.push_back({key, {R, lds}});
   }
   std::fclose(f);
 }
@@ -548,7 +735,10 @@ cpca_status autotune(cpca_handle h, const std::string& key, int64_t ld, size_t e
   if (tune_lookup(h, key, *best)) {
     best->vec = base.vec;
     best->bw = base.bw;
+    best->npan = base.npan;
     if (best->bw == 0) best->strip = false;
+    if (best->bw == 0 || best->npan == 0) best->panel = false;
+    if (best->panel || best->strip) best->R = 1;
     return CPCA_OK;
   }
   hipEvent_t e0, e1;
@@ -561,10 +751,17 @@ cpca_status autotune(cpca_handle h, const std::string& key, int64_t ld, size_t e
   std::vector<ApplyCfg> cands;
   if (base.bw > 0) {
     ApplyCfg c = base;
+    c.panel = false;
     c.strip = true;
     c.R = 1;
     c.lds = true;
     cands.push_back(c);
+    if (base.npan > 0) {
+      c.strip = false;
+      c.panel = true;
+      cands.push_back(c);
+      c.panel = false;
+    }
     for (int R : {1, 2, 4}) {
       c.strip = false;
       c.R = R;
@@ -577,6 +774,7 @@ cpca_status autotune(cpca_handle h, const std::string& key, int64_t ld, size_t e
         c.R = R;
         c.lds = lds != 0;
         c.strip = false;
+        c.panel = false;
         if (!lds || lds_bytes(c, ld, elem) <= 65536) cands.push_back(c);
       }
   }

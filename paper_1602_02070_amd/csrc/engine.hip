@@ -134,14 +134,22 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
   const size_t N = (size_t)p * n;
   const bool f32 = mode != CPCA_FP64;
   const int band = choose_band(P.Lc);
-  const ApplyCfg cfg64 = choose_cfg(h, p, n, sizeof(double), band);
-  const ApplyCfg cfg32 = choose_cfg(h, p, n, sizeof(float), band);
+  ApplyCfg cfg64 = choose_cfg(h, p, n, sizeof(double), band, true);
+  ApplyCfg cfg32 = choose_cfg(h, p, n, sizeof(float), band, true);
   Staging stg;
-  const GraphImage<double> gi64 =
-      stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg64), cfg64.bw);
+  // panel tables when the panel kernel is chosen or may be tried by the tuner
+  const bool tables = h->force_R == -1;
+  const GraphImage<double> gi64 = stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc,
+                                                      slice_height(cfg64), cfg64.bw,
+                                                      cfg64.panel || tables);
   GraphImage<float> gi32{};
-  if (f32) gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg32), cfg32.bw);
-  const int maxgrid = std::max({max_apply_grid((int)p, (int)n), 2048});
+  if (f32)
+    gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg32), cfg32.bw,
+                              cfg32.panel || tables);
+  set_panels(cfg64, gi64.npan);
+  set_panels(cfg32, gi32.npan);
+  const int maxgrid = std::max({max_apply_grid((int)p, (int)n), 2048,
+                                panel_grid(gi64.npan, (int)n, 2), panel_grid(gi32.npan, (int)n, 4)});
 
   char* img = nullptr;
   double *pa = nullptr, *pb = nullptr, *B64 = nullptr, *X64 = nullptr, *r64 = nullptr,
@@ -488,6 +496,10 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
   if (const char* s = std::getenv("CPCA_APPLY_R")) h->force_R = std::atoi(s);
   if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
   if (const char* s = std::getenv("CPCA_BAND")) h->force_band = std::atoi(s);
+  if (const char* s = std::getenv("CPCA_KERNEL")) {
+    const std::string k = s;
+    h->force_kernel = k == "rows" ? 0 : k == "strip" ? 1 : k == "panel" ? 2 : -1;
+  }
   if (const char* s = std::getenv("CPCA_DEBUG")) h->debug = std::atoi(s) != 0;
   *out = h;
   return CPCA_OK;
@@ -645,14 +657,18 @@ namespace {
 template <typename T>
 cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_t p, int64_t n,
                       double gr, double gc, double* pq) {
-  ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T), choose_band(P.Lc));
+  ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T), choose_band(P.Lc), true);
   // user buffers: fall back to scalar columns if they are not 16-byte aligned
   if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Q)) % 16 != 0) {
     cfg.vec = 1;
     cfg.bw = 0;
+    cfg.strip = false;
+    cfg.panel = false;
   }
   Staging stg;
-  const GraphImage<T> gi = stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg), cfg.bw);
+  const GraphImage<T> gi =
+      stage_graph<T>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg), cfg.bw, cfg.panel);
+  set_panels(cfg, gi.npan);
   const int ag = apply_grid(cfg, (int)p, (int)n);
   char* img = nullptr;
   double* part = nullptr;
@@ -707,14 +723,17 @@ extern "C" cpca_status cpca_apply(cpca_handle h, cpca_mode mode, const void* P, 
                           gamma_r, gamma_c, pq);
 }
 
-extern "C" cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_block, int32_t use_lds) {
+extern "C" cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_block, int32_t use_lds,
+                                              int32_t kernel) {
   clear_error();
   if (!h) return fail(CPCA_EINVAL, "null handle");
   if (!(rows_per_block == -1 || rows_per_block == 0 || rows_per_block == 1 ||
         rows_per_block == 2 || rows_per_block == 4 || rows_per_block == 8))
     return fail(CPCA_EINVAL, "rows_per_block must be -1, 0, 1, 2, 4 or 8");
   if (use_lds < -1 || use_lds > 1) return fail(CPCA_EINVAL, "use_lds must be -1, 0 or 1");
+  if (kernel < -1 || kernel > 2) return fail(CPCA_EINVAL, "kernel must be -1, 0, 1 or 2");
   h->force_R = rows_per_block;
   h->force_lds = use_lds;
+  h->force_kernel = kernel;
   return CPCA_OK;
 }

@@ -703,6 +703,276 @@ k_apply_strip(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc
 }
 
 // ---------------------------------------------------------------------------
+// Row-panel gather variant for a banded L_c (BW > 0) and any L_r whose rows
+// hold at most kPanelK off-diagonal entries.
+//
+// The rows of L_r are grouped on the host into panels of at most kPanelRows
+// rows whose L_r neighbourhoods overlap (greedy growth on the graph of L_r);
+// the union U of a panel's neighbour rows (itself included) has at most
+// PanelUnion<T> rows. A workgroup owns one column strip of W = 16 * VEC
+// columns and G consecutive panels. Per panel it copies the strip segment of
+// every row of U into LDS once (plus a halo of PAD columns on both sides of
+// the panel's own rows), so each row of X is read about |U| / |panel| times
+// instead of once per L_r entry, and computes the panel's rows entirely from
+// LDS: L_r X from the staged union rows (local indices precomputed on the
+// host), X L_c from the band diagonals held in registers and the row's
+// window. The next panel's global loads are issued into registers before the
+// current panel is computed, so HBM traffic overlaps the LDS work.
+// Thread t serves row slot t / 16 (16 rows in flight) and columns
+// c0 = s * W + (t % 16) * VEC of strip s.
+// Grid: 8 * gpx * nstrips workgroups, gpx = ceil(ceil(npan / G) / 8); XCD x
+// takes panel groups [x * gpx, (x + 1) * gpx) of every strip, so panels that
+// share union rows run on the same XCD (one L2).
+// ---------------------------------------------------------------------------
+constexpr int kPanelLanes = 16;   // lanes per row slot
+constexpr int kPanelRows = 64;    // rows per panel (max)
+constexpr int kPanelK = 16;       // off-diagonal L_r entries per row (max)
+constexpr int kPanelGroupMax = 16;
+template <typename T> struct PanelUnion { static constexpr int value = sizeof(T) == 4 ? 160 : 128; };
+
+template <typename T>
+struct PanelDev {
+  const int* u_off;        // npan + 1 offsets into u
+  const int* u;            // union rows of each panel
+  const int* r_off;        // npan + 1 offsets into the per-row arrays
+  const int* rows;         // output rows, panel by panel
+  const uint16_t* eidx;    // [row][kPanelK] union-local index of each off-diagonal entry
+  const T* ew;             // [row][kPanelK] its value (0 beyond the row's count)
+  const int4* meta;        // [row] {row, local index | count << 16, row mask, 0}
+  const T* diag;           // [row] diagonal entry of L_r
+  int npan;
+};
+
+template <typename T, int BW, class Epi>
+__global__ void __launch_bounds__(kThreads)
+k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> Lc, BandDev<T> Lb,
+              const uint8_t* __restrict__ mc, int G, int ngroups, int gpx, Epi epi) {
+  if (epi.prologue()) return;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int LN = kPanelLanes;
+  constexpr int NS = kThreads / LN;              // row slots
+  constexpr int W = LN * VEC;                    // strip width
+  constexpr int PAD = band_pad<BW, VEC>();
+  constexpr int RM = kPanelRows;
+  constexpr int UM = PanelUnion<T>::value;
+  constexpr int KR = kPanelK;
+  constexpr int SM = UM / NS;                    // union rows staged per thread
+  constexpr int HV = 2 * PAD / VEC;              // halo vectors per panel row
+  constexpr int HM = (RM * HV + kThreads - 1) / kThreads;
+  constexpr int EV = RM * KR / VEC;              // weight vectors per panel
+  constexpr int EM = (EV + kThreads - 1) / kThreads;
+  constexpr int H = kWave * VEC;                 // SELL slice height
+  static_assert(BW > 0 && UM % NS == 0 && KR % 8 == 0 && RM * KR == 4 * kThreads, "panel shape");
+  __shared__ __align__(16) T su[UM * W];
+  __shared__ __align__(16) T shl[RM * PAD];
+  __shared__ __align__(16) T shr[RM * PAD];
+  __shared__ __align__(16) uint16_t sidx[RM * KR];
+  __shared__ __align__(16) T swt[RM * KR];
+  __shared__ __align__(16) T sdg[RM];
+  __shared__ __align__(16) int4 smeta[RM];
+  __shared__ int soff[2][kPanelGroupMax + 1];
+  double acc[Epi::NV];
+#pragma unroll
+  for (int k = 0; k < Epi::NV; ++k) acc[k] = 0.0;
+  const int t = threadIdx.x;
+  const int b = blockIdx.x, x = b & 7, l = b >> 3;
+  const int s = l / gpx, g = x * gpx + (l - s * gpx);
+  const int nstrips = (n + W - 1) / W;
+  if (g < ngroups && s < nstrips) {
+    const int cs = s * W, ls = t % LN, rs = t / LN;
+    const int c0 = cs + ls * VEC;
+    const bool ok = c0 < n;
+    const int k0 = g * G, np = min(pd.npan, k0 + G) - k0;
+    if (t <= np) {
+      soff[0][t] = pd.u_off[k0 + t];
+      soff[1][t] = pd.r_off[k0 + t];
+    }
+    T vb[2 * BW + 1][VEC];
+#pragma unroll
+    for (int d = 0; d <= 2 * BW; ++d) {
+      if (ok && ((Lb.nonempty >> d) & 1ull)) {
+        vld<T, VEC>(Lb.v + (size_t)d * Lb.ldb + c0, vb[d]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) vb[d][v] = T(0);
+      }
+    }
+    uint8_t mcv[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) mcv[v] = ok ? mc[c0 + v] : 0;
+    int sbeg = 0, sw = 0;  // sliced-ELL remainder of these columns
+    if (ok) {
+      const int sl = c0 / H;
+      sbeg = Lc.sp[sl] + (c0 - sl * H);
+      sw = (Lc.sp[sl + 1] - Lc.sp[sl]) / H;
+    }
+    __syncthreads();
+    // Prefetch state: union row indices (next panel but one), staged values
+    // and panel tables (next panel).
+    int ridx[SM], hrow[HM];
+    auto load_idx = [&](int kk) {
+      const int u0 = soff[0][kk], nu = soff[0][kk + 1] - u0;
+      const int r0 = soff[1][kk], nr = soff[1][kk + 1] - r0;
+#pragma unroll
+      for (int m = 0; m < SM; ++m) {
+        const int u = rs + NS * m;
+        ridx[m] = u < nu ? pd.u[u0 + u] : -1;
+      }
+#pragma unroll
+      for (int m = 0; m < HM; ++m) {
+        const int r = (t + m * kThreads) / HV;
+        hrow[m] = r < nr ? pd.rows[r0 + r] : -1;
+      }
+    };
+    T px[SM][VEC], ph[HM][VEC], pw[EM][VEC], pdg = T(0);
+    uint2 pi;
+    int4 pm;
+    auto load_data = [&](int kk) {
+      const int r0 = soff[1][kk], nr = soff[1][kk + 1] - r0;
+#pragma unroll
+      for (int m = 0; m < SM; ++m) {
+        if (ridx[m] >= 0 && ok) {
+          vld<T, VEC>(X + (size_t)ridx[m] * n + c0, px[m]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) px[m][v] = T(0);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < HM; ++m) {
+        const int hq = (t + m * kThreads) % HV;
+        const int c = hq < HV / 2 ? cs - PAD + hq * VEC : cs + W + (hq - HV / 2) * VEC;
+        if (hrow[m] >= 0 && c >= 0 && c + VEC <= n) {
+          vld<T, VEC>(X + (size_t)hrow[m] * n + c, ph[m]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) ph[m][v] = T(0);
+        }
+      }
+      pi = make_uint2(0u, 0u);
+      if (t / 4 < nr) pi = *reinterpret_cast<const uint2*>(pd.eidx + (size_t)r0 * KR + t * 4);
+#pragma unroll
+      for (int m = 0; m < EM; ++m) {
+        const int it = t + m * kThreads;
+        if (it < EV && (it * VEC) / KR < nr) {
+          vld<T, VEC>(pd.ew + (size_t)r0 * KR + (size_t)it * VEC, pw[m]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) pw[m][v] = T(0);
+        }
+      }
+      pm = make_int4(0, 0, 0, 0);
+      pdg = T(0);
+      if (t < nr) {
+        pm = pd.meta[r0 + t];
+        pdg = pd.diag[r0 + t];
+      }
+    };
+    load_idx(0);
+    load_data(0);
+    if (np > 1) load_idx(1);
+    for (int kk = 0; kk < np; ++kk) {
+      const int nr = soff[1][kk + 1] - soff[1][kk];
+      __syncthreads();  // the previous panel's LDS reads are done
+#pragma unroll
+      for (int m = 0; m < SM; ++m) vst<T, VEC>(&su[(rs + NS * m) * W + ls * VEC], px[m]);
+#pragma unroll
+      for (int m = 0; m < HM; ++m) {
+        const int it = t + m * kThreads;
+        const int r = it / HV, hq = it % HV;
+        if (r < RM) {
+          T* dst = hq < HV / 2 ? &shl[r * PAD + hq * VEC] : &shr[r * PAD + (hq - HV / 2) * VEC];
+          vst<T, VEC>(dst, ph[m]);
+        }
+      }
+      *reinterpret_cast<uint2*>(&sidx[t * 4]) = pi;
+#pragma unroll
+      for (int m = 0; m < EM; ++m) {
+        const int it = t + m * kThreads;
+        if (it < EV) vst<T, VEC>(&swt[it * VEC], pw[m]);
+      }
+      if (t < RM) {
+        smeta[t] = pm;
+        sdg[t] = pdg;
+      }
+      __syncthreads();
+      if (kk + 1 < np) {
+        load_data(kk + 1);
+        if (kk + 2 < np) load_idx(kk + 2);
+      }
+      if (ok) {
+        for (int j = rs; j < nr; j += NS) {
+          const int4 mt = smeta[j];
+          const int row = mt.x, ctr = mt.y & 0xffff, cnt = mt.y >> 16;
+          const uint8_t mri = (uint8_t)mt.z;
+          uint16_t id[KR];
+#pragma unroll
+          for (int q = 0; q < KR; q += 8) {
+            const uint4 v = *reinterpret_cast<const uint4*>(&sidx[j * KR + q]);
+            id[q + 0] = v.x & 0xffff; id[q + 1] = v.x >> 16;
+            id[q + 2] = v.y & 0xffff; id[q + 3] = v.y >> 16;
+            id[q + 4] = v.z & 0xffff; id[q + 5] = v.z >> 16;
+            id[q + 6] = v.w & 0xffff; id[q + 7] = v.w >> 16;
+          }
+          T wv[KR];
+#pragma unroll
+          for (int q = 0; q < KR; q += VEC) {
+            T w4[VEC];
+            vld<T, VEC>(&swt[j * KR + q], w4);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) wv[q + v] = w4[v];
+          }
+          T win[2 * PAD + VEC];
+#pragma unroll
+          for (int q = 0; q < 2 * PAD + VEC; q += VEC) {
+            const int c = ls * VEC - PAD + q;
+            const T* ptr = c < 0 ? &shl[j * PAD + c + PAD]
+                                 : (c >= W ? &shr[j * PAD + c - W] : &su[ctr * W + c]);
+            T w4[VEC];
+            vld<T, VEC>(ptr, w4);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) win[q + v] = w4[v];
+          }
+          T xv[VEC], mx[VEC], accr[VEC], accc[VEC];
+          const T dg = sdg[j];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            xv[v] = win[PAD + v];
+            accr[v] = dg * xv[v];
+            accc[v] = T(0);
+            mx[v] = (mri & mcv[v]) ? xv[v] : T(0);
+          }
+#pragma unroll
+          for (int e = 0; e < KR; ++e) {
+            if (e < cnt) {
+              T u4[VEC];
+              vld<T, VEC>(&su[id[e] * W + ls * VEC], u4);
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) accr[v] += wv[e] * u4[v];
+            }
+          }
+#pragma unroll
+          for (int d = 0; d <= 2 * BW; ++d)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) accc[v] += vb[d][v] * win[PAD + v + d - BW];
+          const T* rowp = X + (size_t)row * n;
+          for (int e = 0; e < sw; ++e) {
+            int kk2[VEC];
+            T vv[VEC];
+            vld<int, VEC>(Lc.ci + sbeg + e * H, kk2);
+            vld<T, VEC>(Lc.v + sbeg + e * H, vv);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) accc[v] += vv[v] * rowp[kk2[v]];
+          }
+          epi.template apply<VEC>(row, (size_t)row * n + c0, xv, mx, accr, accc, acc);
+        }
+      }
+    }
+  }
+  if (epi.partials) block_partials<Epi::NV>(acc, epi.partials);
+}
+
+// ---------------------------------------------------------------------------
 // CG vector kernels (grid-stride over 16-byte vectors; N % VEC tail scalar).
 // ---------------------------------------------------------------------------
 template <typename T> struct V16 { static constexpr int W = 16 / sizeof(T); };

@@ -73,26 +73,66 @@ def test_apply_matches_oracle_random_graphs(shape, dtype):
 
 
 @pytest.mark.parametrize("n", [333, 600, 1100])
-@pytest.mark.parametrize("R,lds", [(0, -1), (1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (4, 0)])
-def test_apply_every_launch_shape(R, lds, n):
+@pytest.mark.parametrize("R,lds,kernel", [(0, -1, "auto"), (0, -1, "strip"), (0, -1, "panel"),
+                                          (0, -1, "rows"), (1, 1, "auto"), (2, 1, "auto"),
+                                          (4, 1, "auto"), (8, 1, "auto"), (1, 0, "auto"),
+                                          (4, 0, "auto")])
+def test_apply_every_launch_shape(R, lds, kernel, n):
     # n = 333: scalar columns; 600 / 1100: 16-byte vectors, ragged; the circle
-    # column graph is banded (plus wrap-around entries), so the default shape
-    # (R = 0) takes the column-strip kernel with a partial last strip and a
-    # partial last row chunk, and R = 1, 2, 4 with LDS take the row-panel band
-    # kernel
-    _announce(f"apply launch shape R={R} lds={lds} n={n}")
+    # column graph is banded (plus wrap-around entries in the sliced-ELL
+    # remainder). With the default shape (R = 0) the band goes to the kernel
+    # named by `kernel` (auto: row panels) with a partial last strip and a
+    # partial last panel group / row chunk; R = 1, 2, 4 with LDS take the
+    # row kernel with the band in LDS
+    _announce(f"apply launch shape R={R} lds={lds} kernel={kernel} n={n}")
     P_ = synth.small_problem(3, p_shape=(11, 13), n=n, rank=3, frac=0.3)
     rng = np.random.default_rng(5)
     X = rng.standard_normal((P_.p, P_.n))
     m_r, m_c = OD.masks(P_.p, P_.n, P_.omega_r, P_.omega_c)
     ref = OD.apply_A(X, m_r, m_c, P_.Lr, P_.Lc, 1.3, 0.4)
     d = dev_problem(P_)
-    cp.set_apply_config(R, lds)
+    cp.set_apply_config(R, lds, kernel)
     try:
         for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
             Q, _ = cp.apply_operator(torch.from_numpy(X).to(dtype).cuda(), d["Lr"], d["Lc"], 1.3,
                                      0.4, d["om_r"], d["om_c"])
             assert np.abs(host(Q) - ref).max() <= tol * np.abs(ref).max() * 10
+    finally:
+        cp.set_apply_config(0, -1)
+
+
+@pytest.mark.parametrize("kernel", ["panel", "strip", "rows"])
+@pytest.mark.parametrize("shape,n,K", [((48, 61), 1024, 10), ((30, 37), 1000, 10),
+                                       ((20, 25), 512, 20)])
+def test_apply_banded_many_panels(kernel, shape, n, K):
+    # A pixel-grid L_r (many panels: 48 x 61 = 2928 rows, panels of up to 64
+    # rows) and a banded time-line L_c; the last case has about 25 entries per
+    # L_r row, beyond the panel table, so "panel" falls back to column strips.
+    # Both element types; FP64 against the oracle at rounding level.
+    _announce(f"apply banded kernel={kernel} grid={shape} n={n} K={K}")
+    import scipy.sparse as sps
+    Lr, _ = synth.knn_laplacian(synth.grid_coords(*shape), K)
+    Lc, _ = synth.knn_laplacian(np.arange(float(n))[:, None], 10)
+    p = Lr.shape[0]
+    rng = np.random.default_rng(11)
+    om_r = np.sort(rng.choice(p, p // 7, replace=False)).astype(np.int32)
+    om_c = np.sort(rng.choice(n, n // 9, replace=False)).astype(np.int32)
+    X = rng.standard_normal((p, n))
+    m_r, m_c = OD.masks(p, n, om_r, om_c)
+    gr, gc = 0.8, 2.5
+    ref = OD.apply_A(X, m_r, m_c, Lr, Lc, gr, gc)
+    cp.set_apply_config(0, -1, kernel)
+    try:
+        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+            Xt = torch.from_numpy(X).to(dtype).cuda()
+            Q, pq = cp.apply_operator(Xt, cp.Graph.from_scipy(Lr), cp.Graph.from_scipy(Lc), gr,
+                                      gc, torch.from_numpy(om_r).cuda(),
+                                      torch.from_numpy(om_c).cuda())
+            Xh = host(Xt)
+            refd = OD.apply_A(Xh, m_r, m_c, Lr, Lc, gr, gc)
+            assert np.abs(host(Q) - refd).max() <= tol * np.abs(refd).max() * 10
+            assert np.isclose(pq, np.sum(Xh * refd), rtol=1e-12 if dtype == torch.float64 else 1e-5)
+        assert sps.issparse(Lr)
     finally:
         cp.set_apply_config(0, -1)
 
