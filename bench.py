@@ -1,20 +1,25 @@
 """Throughput of the CPCA hot path on one MI355X.
 
 One step = FRPCAG by FISTA on the sampled matrix Y~ (Algorithm 1, FP64
-state) followed by the alternate decoder of the full p x n matrix (CG,
-default FP32 inner solves inside FP64 iterative refinement), with every
-input already resident in HBM. The metric is recovered entries per second
-(p * n per step time). The line also carries the roofline of the fused
-two-sided sparse product (the dominant kernel), timed with HIP events on the
-library's stream, and the FP64 CPU oracle timed on a bounded sample.
+state) followed by the alternate decoder of the full p x n matrix (CG in
+FP32 with FP64 residual replacement by default), with every input already
+resident in HBM. The metric is recovered entries per second (p * n per step
+time). The line also carries the roofline of the fused two-sided sparse
+product (the dominant kernel), timed with HIP events on the library's stream,
+the HBM traffic of that kernel from the committed counter summary (null when
+the kernel sources changed since the counters were taken), and the FP64 CPU
+oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--workload video|face|tiny]
+                    [--copy-probe]   (device copies of known size, for counter calibration)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,6 +28,32 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_apply_panel_video_fp32.md")
+KERNEL_SOURCES = ("paper_1602_02070_amd/csrc/kernels.hpp", "paper_1602_02070_amd/csrc/common.hpp")
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of the sources that define the fused
+    product and its launch shape."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, mode: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken for this workload and mode on the current kernel
+    sources; else None."""
+    if workload != "video" or mode != "fp32_ir" or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    m_hash = re.search(r"kernel source hash: `([0-9a-f]+)`", text)
+    m_bytes = re.search(r"HBM bytes per launch \(fetch \+ write, calibrated\): `([0-9]+)`", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return int(m_bytes.group(1))
 
 WORKLOADS = {
     # name: (builder, description, decoder tolerance)
@@ -41,17 +72,11 @@ def log(msg):
 
 def algorithmic_apply_bytes(P, elem: int) -> int:
     """Bytes one fused-product launch must move at minimum: read the operand
-    once, write the result once, read both sparse operators (CSR of L_r,
-    sliced ELL of L_c with its padding) and the two masks."""
-    import numpy as np
+    once, write the result once, read both sparse operators once in CSR form
+    (int32 indices, values of the element type) and the two byte masks."""
     pn = P.p * P.n
     lr = P.Lr.nnz * (4 + elem) + (P.p + 1) * 4
-    deg = np.diff(P.Lc.indptr)
-    ns = (P.n + 63) // 64
-    pad = np.zeros(ns * 64, dtype=np.int64)
-    pad[:P.n] = deg
-    width = pad.reshape(ns, 64).max(axis=1)
-    lc = int(width.sum()) * 64 * (4 + elem) + (ns + 1) * 4
+    lc = P.Lc.nnz * (4 + elem) + (P.n + 1) * 4
     return 2 * elem * pn + lr + lc + P.p + P.n
 
 
@@ -59,10 +84,12 @@ def cpu_baseline(P, J, tol, gpu_fp64_iters, max_seconds=25.0):
     """Time the oracle on a bounded sample: the whole FISTA on Y~ plus a few
     CG iterations of the full-size decoder, extrapolated to the number of CG
     iterations the plain-FP64 solve needs."""
-    import numpy as np
+    from threadpoolctl import threadpool_limits
+
     from oracle import decoder as OD
     from oracle import frpcag as OF
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    limiter = threadpool_limits(limits=1)  # one core, as the paper's timings
+    threads = 1
     t0 = time.perf_counter()
     Xt, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, P.gamma_r, P.gamma_c, P.lmax_r_til,
                      P.lmax_c_til, J)
@@ -78,6 +105,7 @@ def cpu_baseline(P, J, tol, gpu_fp64_iters, max_seconds=25.0):
     OD.solve_cg(B, m_r, m_c, P.Lr, P.Lc, P.gamma_r, P.gamma_c, tol=tol, max_iter=k)
     t_it = (time.perf_counter() - t0) / k
     total = t_fista + t_it * gpu_fp64_iters
+    limiter.unregister()
     return {"value": P.p * P.n / total, "unit": "entries/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle: FISTA {J} it on Y~ {P.rho_r}x{P.rho_c} timed whole "
                        f"({t_fista:.2f} s); decoder CG timed for {k} iterations at full size "
@@ -88,7 +116,7 @@ def cpu_baseline(P, J, tol, gpu_fp64_iters, max_seconds=25.0):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="video", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="fp32_ir", choices=["fp32_ir", "fp64", "fp32"])
@@ -96,6 +124,8 @@ def main(argv=None):
     ap.add_argument("--fista-iters", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="before the steps, copy a p x n operand on the device three times")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -132,6 +162,14 @@ def main(argv=None):
         infos["fista"], infos["decode"], infos["Xt"] = fi, di, Xt
         return X
 
+    if args.copy_probe:
+        src = torch.empty((P.p, P.n), dtype=dt, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 device copies of {src.numel() * src.element_size()} bytes")
+        del src, dst
     for w in range(args.warmup):
         step()
         log(f"[bench] warmup {w + 1}/{args.warmup}: decode {infos['decode']['iters']} CG it, "
@@ -153,8 +191,13 @@ def main(argv=None):
     value = P.p * P.n * args.steps / elapsed
     elem = 8 if args.mode == "fp64" else 4
     bytes_apply = algorithmic_apply_bytes(P, elem)
-    avg_apply = ms_apply / max(n_apply, 1)
-    achieved = bytes_apply / (avg_apply * 1e-3) / 1e9 if n_apply else None
+    # The CG loop launches iterations in chunks and polls between chunks, so a
+    # few launches after convergence return at once. The average is taken over
+    # the launches that did work (one per CG iteration), with the time of the
+    # early-exit launches included (a slight underestimate of the rate).
+    n_work = infos["decode"]["iters"] * args.steps
+    avg_apply = ms_apply / max(n_work, 1)
+    achieved = bytes_apply / (avg_apply * 1e-3) / 1e9 if n_work else None
 
     extra = {"decode_iters": infos["decode"]["iters"],
              "refinements": infos["decode"]["outer_iters"],
@@ -162,7 +205,7 @@ def main(argv=None):
              "fista_iters": infos["fista"]["iters"],
              "apply_launches_per_step": n_apply / args.steps,
              "apply_ms_avg": avg_apply,
-             "update_ms_avg": ms_upd / max(n_upd, 1),
+             "update_ms_avg": ms_upd / max(n_work, 1),
              "fista_ms_avg": ms_fista / max(n_fista, 1)}
     fp64_iters = None
     if not args.no_fp64_check:
@@ -190,7 +233,9 @@ def main(argv=None):
                    "gamma_c": P.gamma_c, "fista_iters": J, "decoder_tol": tol,
                    "mode": args.mode, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic(args.workload, args.mode),
+                     "traffic_unit": "bytes per launch", "kernel_source_hash": kernel_source_hash(),
                      "kernel": "fused two-sided SpMM with CG epilogue (row-panel gather kernel k_apply_panel for this banded L_c)",
                      "algorithmic_bytes_per_launch": bytes_apply},
         "extra": extra,

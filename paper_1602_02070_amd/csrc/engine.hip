@@ -54,10 +54,10 @@ cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, 
       epi.sc = sc;
       STCHK(launch_apply<T>(h, op.cfg, pv, op.p, op.n, op.g, epi, FAM_APPLY));
       STCHK(prof_begin(h, FAM_UPDATE));
-      k_cg_update<T><<<vg, kThreads, 0, h->stream>>>(x, r, pv, q, N, sc, it, part.a, ag, part.b);
+      k_cg_update<T><<<vg, kThreads, 0, h->stream>>>(r, q, N, sc, it, part.a, ag, part.b);
       LAUNCHCHK();
       STCHK(prof_end(h));
-      k_cg_pupdate<T><<<vg, kThreads, 0, h->stream>>>(pv, r, N, sc, it, part.b, vg);
+      k_cg_pupdate<T><<<vg, kThreads, 0, h->stream>>>(x, pv, r, N, sc, it, part.b, vg);
       LAUNCHCHK();
     }
     STCHK(read_fixed(h));

@@ -977,12 +977,13 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
 // ---------------------------------------------------------------------------
 template <typename T> struct V16 { static constexpr int W = 16 / sizeof(T); };
 
-// x += alpha p; r -= alpha q; partials of <r, r>.
-// alpha = rr / <p, q> is formed here from the apply kernel's partials.
+// r -= alpha q; partials of <r, r>. alpha = rr / <p, q> is formed here from
+// the apply kernel's partials and kept in sc->alpha; the matching x update
+// happens in k_cg_pupdate, which reads p anyway (12 + 20 bytes per entry and
+// element size 4 instead of 24 + 12).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-            const T* __restrict__ q, size_t N, CgScal* sc, int it,
+k_cg_update(T* __restrict__ r, const T* __restrict__ q, size_t N, CgScal* sc, int it,
             const double* __restrict__ part_pq, int nb_pq, double* __restrict__ part_rr) {
   if (sc->done != 0 || sc->conv_it != 0) return;
   double t[1];
@@ -1008,22 +1009,17 @@ k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
   const size_t nv = N / W;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
-    T xv[W], rv[W], pv[W], qv[W];
-    vld<T, W>(x + v * W, xv);
+    T rv[W], qv[W];
     vld<T, W>(r + v * W, rv);
-    vld<T, W>(p + v * W, pv);
     vld<T, W>(q + v * W, qv);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-      xv[k] += alpha * pv[k];
       rv[k] -= alpha * qv[k];
       acc[0] += (double)rv[k] * (double)rv[k];
     }
-    vst<T, W>(x + v * W, xv);
     vst<T, W>(r + v * W, rv);
   }
   for (size_t e = nv * W + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
-    x[e] += alpha * p[e];
     const T rn = r[e] - alpha * q[e];
     r[e] = rn;
     acc[0] += (double)rn * (double)rn;
@@ -1031,12 +1027,13 @@ k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
   block_partials<1>(acc, part_rr);
 }
 
-// beta = rr_new / rr; p = r + beta p; convergence test rr_new <= thr.
-// The converging iteration updates p as well (see CgScal::conv_it).
+// x += alpha p (the step of this iteration, alpha from k_cg_update); then
+// beta = rr_new / rr, p = r + beta p; convergence test rr_new <= thr.
+// The converging iteration updates x and p as well (see CgScal::conv_it).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_cg_pupdate(T* __restrict__ p, const T* __restrict__ r, size_t N, CgScal* sc, int it,
-             const double* __restrict__ part_rr, int nb_rr) {
+k_cg_pupdate(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ r, size_t N, CgScal* sc,
+             int it, const double* __restrict__ part_rr, int nb_rr) {
   if (sc->done != 0) return;
   if (sc->conv_it != 0 && sc->conv_it <= it) return;
   double t[1];
@@ -1052,6 +1049,7 @@ k_cg_pupdate(T* __restrict__ p, const T* __restrict__ r, size_t N, CgScal* sc, i
     return;
   }
   const double beta_d = rr_new / rr;
+  const T alpha = (T)sc->alpha;  // not written in this kernel
   if (lead) {
     sc->rr[(it + 1) & 1] = rr_new;
     sc->beta = beta_d;
@@ -1063,15 +1061,22 @@ k_cg_pupdate(T* __restrict__ p, const T* __restrict__ r, size_t N, CgScal* sc, i
   const size_t nv = N / W;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
-    T pv[W], rv[W];
+    T xv[W], pv[W], rv[W];
+    vld<T, W>(x + v * W, xv);
     vld<T, W>(p + v * W, pv);
     vld<T, W>(r + v * W, rv);
 #pragma unroll
-    for (int k = 0; k < W; ++k) pv[k] = rv[k] + beta * pv[k];
+    for (int k = 0; k < W; ++k) {
+      xv[k] += alpha * pv[k];
+      pv[k] = rv[k] + beta * pv[k];
+    }
+    vst<T, W>(x + v * W, xv);
     vst<T, W>(p + v * W, pv);
   }
-  for (size_t e = nv * W + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride)
+  for (size_t e = nv * W + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+    x[e] += alpha * p[e];
     p[e] = r[e] + beta * p[e];
+  }
 }
 
 // Start of a CG solve from x = 0: x = 0, r = p = B; partials of <B, B>.
