@@ -63,6 +63,10 @@ WORKLOADS = {
     "face": ("cfg2_face", "face-shaped 112x92 pixels x 1000 samples, rank 10, 10% outliers, "
              "10% sampling", 1e-8),
     "tiny": ("cfg1_tiny", "p=100 helix x n=200 circle, rank 5, 50% sampling", 1e-10),
+    "batch": ("cfg5_batch", "64 instances, p log-uniform in [500, 4000] x n log-uniform in "
+              "[200, 2000], rank 3-10, helix rows / circle columns, 5% outliers, 10% sampling, "
+              "each swept over a 4 x 4 (gamma_r, gamma_c) grid in {0.1, 1, 10, 100}: 1024 tasks "
+              "of FISTA 100 it + decoder, FP32 CG with FP64 refinement", 1e-8),
 }
 
 
@@ -113,10 +117,147 @@ def cpu_baseline(P, J, tol, gpu_fp64_iters, max_seconds=25.0):
                        f"of the plain-FP64 GPU solve; est. {total:.1f} s per step")}
 
 
+def batch_cpu_baseline(probs, tasks, iters, J, tol, max_seconds=25.0):
+    """Oracle on one core for a seeded subset of 8 tasks (always including the
+    largest instance at gamma = (100, 100)): FISTA timed whole, the decoder CG
+    timed for a few iterations at full size and extrapolated to each task's
+    GPU iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import decoder as OD
+    from oracle import frpcag as OF
+    limiter = threadpool_limits(limits=1)
+    rng = np.random.default_rng(7)
+    big = max(range(len(probs)), key=lambda k: probs[k].p * probs[k].n)
+    pick = [tasks.index((big, 100.0, 100.0))]
+    pick += [int(t) for t in rng.choice([t for t in range(len(tasks)) if t != pick[0]], 7,
+                                        replace=False)]
+    budget = max_seconds / len(pick)
+    entries, secs = 0, 0.0
+    for t in pick:
+        k, gr, gc = tasks[t]
+        P = probs[k]
+        t0 = time.perf_counter()
+        Xt, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, gr, gc, P.lmax_r_til, P.lmax_c_til, J)
+        t_f = time.perf_counter() - t0
+        m_r, m_c = OD.masks(P.p, P.n, P.omega_r, P.omega_c)
+        B = OD.rhs(Xt, P.p, P.n, P.omega_r, P.omega_c)
+        t0 = time.perf_counter()
+        OD.solve_cg(B, m_r, m_c, P.Lr, P.Lc, gr, gc, tol=tol, max_iter=1)
+        t1 = time.perf_counter() - t0
+        kk = max(1, min(50, int((budget - t_f) / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        OD.solve_cg(B, m_r, m_c, P.Lr, P.Lc, gr, gc, tol=tol, max_iter=kk)
+        t_it = (time.perf_counter() - t0) / kk
+        entries += P.p * P.n
+        secs += t_f + t_it * iters[t]
+    limiter.unregister()
+    return {"value": entries / secs, "unit": "entries/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle on {len(pick)} of {len(tasks)} tasks (largest instance at "
+                       f"gamma (100, 100) plus 7 seeded): FISTA {J} it timed whole, decoder CG "
+                       f"timed for a few iterations at full size and extrapolated to each task's "
+                       f"GPU iteration count; est. {secs:.1f} s for {entries} entries")}
+
+
+def run_batch(args, desc, tol):
+    """The batched workload: every task's FISTA + decode in one cpca_solve_batched
+    call. The roofline line is a whole-solve rate: the algorithmic bytes of all
+    fused products and CG vector passes (per task: iterations x (8 + 32) bytes
+    per entry in FP32 plus the operators) over the step time."""
+    import numpy as np
+    import torch
+
+    import paper_1602_02070_amd as cp
+    import synth
+    log("[bench] building inputs: batch (64 instances)")
+    probs, grid = synth.cfg5_batch(0)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    J = 100
+    inst = []
+    for P in probs:
+        g = {k: cp.Graph.from_scipy(getattr(P, k)) for k in ("Lr", "Lc", "Lr_til", "Lc_til")}
+        inst.append(cp.Instance(P.p, P.n, torch.from_numpy(P.omega_r).to(dev),
+                                torch.from_numpy(P.omega_c).to(dev), g["Lr"], g["Lc"],
+                                g["Lr_til"], g["Lc_til"], P.lmax_r_til, P.lmax_c_til,
+                                torch.from_numpy(P.Ytil).float().to(dev)))
+    tasks = [(k, gr, gc) for k in range(len(probs)) for gr, gc in grid]
+    entries = sum(probs[k].p * probs[k].n for k, _, _ in tasks)
+    out = {}
+
+    def step():
+        Xs, _, infos = cp.solve_batched(inst, tasks, fista_iters=J, tol=tol, max_iter=20000,
+                                        mode="fp32_ir")
+        out["X"], out["infos"] = Xs, infos
+
+    for w in range(args.warmup):
+        step()
+        log(f"[bench] warmup {w + 1}/{args.warmup}: CG iterations max "
+            f"{max(i['iters'] for i in out['infos'])}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    infos = out["infos"]
+    iters = [i["iters"] for i in infos]
+    assert all(i["status"] == 0 for i in infos), "batched solve did not converge"
+    alg = 0
+    for (k, _, _), it in zip(tasks, iters):
+        P = probs[k]
+        ops = P.Lr.nnz * 8 + P.Lc.nnz * 8 + 4 * (P.p + P.n + 2)
+        alg += it * (40 * P.p * P.n + ops)
+        alg += J * 40 * P.rho_r * P.rho_c
+    achieved = alg * args.steps / elapsed / 1e9
+    extra = {"tasks": len(tasks), "cg_iters_min": min(iters), "cg_iters_max": max(iters),
+             "cg_iters_mean": float(np.mean(iters)),
+             "refinements_max": max(i["outer_iters"] for i in infos)}
+    if not args.no_fp64_check:
+        big = max(range(len(probs)), key=lambda k: probs[k].p * probs[k].n)
+        sub = [t for t, (k, _, _) in enumerate(tasks) if k == big]
+        inst64 = [dataclasses_replace(inst[big], Ytil=inst[big].Ytil.double())]
+        X64, _, _ = cp.solve_batched(inst64, [(0, tasks[t][1], tasks[t][2]) for t in sub],
+                                     fista_iters=J, tol=min(tol, 1e-11), max_iter=50000,
+                                     mode="fp64")
+        diffs = [float((out["X"][t].double() - x).norm() / x.norm()) for t, x in zip(sub, X64)]
+        extra["fp64_check"] = f"largest instance ({probs[big].p}x{probs[big].n}), its 16 tasks"
+        extra["rel_diff_vs_gpu_fp64_max"] = max(diffs)
+        log(f"[bench] FP64 GPU check on the largest instance: max rel.diff {max(diffs):.2e}")
+    line = {
+        "metric": "recovered entries/s (FRPCAG FISTA + alternate decoder CG), rel.err<=1e-5 "
+                  "vs FP64 oracle",
+        "value": entries * args.steps / elapsed, "unit": "entries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64-refine", "data": "synthetic",
+        "config": {"workload": f"batch: {desc}", "instances": len(probs), "tasks": len(tasks),
+                   "entries_per_step": entries, "fista_iters": J, "decoder_tol": tol,
+                   "mode": "fp32_ir", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole batched solve (task-table fused products and CG passes)",
+                     "algorithmic_bytes_per_step": alg},
+        "extra": extra,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a task subset")
+        line["cpu_baseline"] = batch_cpu_baseline(probs, tasks, iters, J, tol)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def dataclasses_replace(obj, **kw):
+    import dataclasses
+    return dataclasses.replace(obj, **kw)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 5; 1 for the batch workload)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="video", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="fp32_ir", choices=["fp32_ir", "fp64", "fp32"])
@@ -127,6 +268,8 @@ def main(argv=None):
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the steps, copy a p x n operand on the device three times")
     args = ap.parse_args(argv)
+    if args.steps is None:
+        args.steps = 1 if args.workload == "batch" else 5
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the solver runs on a single MI355X)", file=sys.stderr)
@@ -140,6 +283,8 @@ def main(argv=None):
 
     builder, desc, tol_default = WORKLOADS[args.workload]
     tol = args.tol if args.tol is not None else tol_default
+    if args.workload == "batch":
+        return run_batch(args, desc, tol)
     log(f"[bench] building inputs: {args.workload}")
     P = getattr(synth, builder)(0)
     dt = torch.float64 if args.mode == "fp64" else torch.float32

@@ -112,7 +112,7 @@ def laplacian_lmax(L: sp.spmatrix) -> float:
 def low_eigvecs(L: sp.spmatrix, k: int) -> np.ndarray:
     """First k eigenvectors (smallest eigenvalues) of a Laplacian, N x k."""
     N = L.shape[0]
-    if N <= 2500:
+    if N <= 400:
         _, V = np.linalg.eigh(L.toarray())
         return np.ascontiguousarray(V[:, :k])
     vals, V = spla.eigsh(L.tocsc(), k=k, sigma=-1e-3, which="LM",
