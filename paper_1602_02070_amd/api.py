@@ -304,9 +304,11 @@ class Instance:
 
 
 def solve_batched(instances, tasks, fista_iters: int = 500, tol: float = 1e-9,
-                  max_iter: int = 20000, mode: str | None = None, want_xtil: bool = False):
+                  max_iter: int = 20000, mode: str | None = None, want_xtil: bool = False,
+                  raise_errors: bool = True):
     """FISTA + alternate decoder for every task (instance index, gamma_r,
-    gamma_c) in one batched run. Returns (X list, X~ list or None, infos)."""
+    gamma_c) in one batched run. Returns (X list, X~ list or None, infos).
+    With raise_errors=False a failed task is reported only in its info."""
     if not instances or not tasks:
         raise ValueError("need at least one instance and one task")
     mode = mode_for(instances[0].Ytil.dtype, mode)
@@ -337,5 +339,6 @@ def solve_batched(instances, tasks, fista_iters: int = 500, tol: float = 1e-9,
     st = _lib.load().cpca_solve_batched(handle(instances[0].Ytil.device), _lib.MODES[mode], cin,
                                         len(instances), ctk, len(tasks), int(fista_iters),
                                         float(tol), int(max_iter), infos)
-    _check(st, "cpca_solve_batched")
+    if raise_errors:
+        _check(st, "cpca_solve_batched")
     return outs, (xts if want_xtil else None), [i.as_dict() for i in infos]

@@ -187,6 +187,8 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
     k.om_c = I.omega_c;
     k.active = 1;
     k.inner_rel2 = 1e-10;
+    k.floor2 = 0.0;
+    k.keep_p = 0;
   }
   build_tables(bt, bc.R, atab, ftab, vtab, g);
   // the largest grids any candidate shape can need (R = 1)
@@ -527,13 +529,43 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
     LAUNCHCHK();
     k_pass_batched<P_ZERO_32><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
     LAUNCHCHK();
-    std::vector<double> rel_prev((size_t)ntasks, 1.0);
+    // FP32 CG with FP64 residual replacement (as in the single-problem
+    // solver): each segment runs until its recursive residual has dropped by
+    // kReplace against the last true residual (or to (0.3 tol)^2 ||B||^2);
+    // then X64 += x32 and the true residual replaces the FP32 one, keeping
+    // the direction. A task whose segment fails (breakdown, NaN/Inf,
+    // divergence: X64 is left untouched), does not lower the true residual,
+    // or needs more than kSlow times the iterations per decade of true-
+    // residual reduction of its first segment is too ill-conditioned for the
+    // FP32 recursion to carry a direction across replacements; it switches to
+    // restarted refinement (p = r at every segment, inner tolerance
+    // clamp(0.5 tol / rel, 1e-5, 0.25)). kMaxBad failed segments in a row end
+    // the task.
+    constexpr double kReplace2 = 1e-4;
+    constexpr int kMaxBad = 3;
+    std::vector<int> bad_run((size_t)ntasks, 0), last_bad((size_t)ntasks, 0);
+    std::vector<double> rel_prev((size_t)ntasks, HUGE_VAL);
+    std::vector<char> keep((size_t)ntasks, 0);     // the first residual pass sets p = r
+    std::vector<char> restart((size_t)ntasks, h->ir_restart ? 1 : 0);  // restarted refinement
+    constexpr double kSlow = 2.2;
+    std::vector<double> ipd_first((size_t)ntasks, 0.0);
+    std::vector<int> seg_iters((size_t)ntasks, 0);
     for (int o = 0;; ++o) {
       bool any = false;
       for (int32_t t = 0; t < ntasks; ++t) {
         BTask& k = bt[(size_t)t];
-        const double it_tol = std::min(0.25, std::max(1e-5, 0.5 * tol / rel_prev[(size_t)t]));
-        k.inner_rel2 = it_tol * it_tol;
+        if (restart[(size_t)t]) {
+          const double it_tol =
+              std::min(0.25, std::max(1e-5, 0.5 * tol / std::min(1.0, rel_prev[(size_t)t])));
+          k.inner_rel2 = it_tol * it_tol;
+          k.floor2 = 0.0;
+          k.keep_p = 0;
+        } else {
+          k.inner_rel2 = kReplace2;
+          k.floor2 = 0.09 * tol2 * bb[(size_t)t];
+          k.keep_p = keep[(size_t)t];
+        }
+        k.reset_p = 0;
         any = any || k.active;
       }
       if (!any) break;
@@ -542,7 +574,7 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
       k_arm_batched<true><<<ntasks, kThreads, 0, s>>>(d_tasks, pa, 0.0);
       LAUNCHCHK();
       STCHK(read_sc());
-      bool need = false;
+      bool need = false, reset = false;
       for (int32_t t = 0; t < ntasks; ++t) {
         BTask& k = bt[(size_t)t];
         if (!k.active) continue;
@@ -555,16 +587,37 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
         } else if (rel <= tol) {
           done[(size_t)t] = 1;
           k.active = 0;
+        } else if (bad_run[(size_t)t] >= kMaxBad) {
+          done[(size_t)t] = last_bad[(size_t)t];
+          k.active = 0;
         } else if (o >= kMaxOuter) {
           done[(size_t)t] = 0;
           k.active = 0;
         } else {
+          bool slow = false;
+          if (o > 0 && rel < rel_prev[(size_t)t] && seg_iters[(size_t)t] > 0) {
+            const double ipd = seg_iters[(size_t)t] / std::log10(rel_prev[(size_t)t] / rel);
+            if (ipd_first[(size_t)t] == 0.0) ipd_first[(size_t)t] = ipd;
+            else slow = ipd > kSlow * ipd_first[(size_t)t];
+          }
+          if (k.keep_p && (!(rel < rel_prev[(size_t)t]) || slow)) {  // no or slowing progress
+            k.reset_p = 1;
+            reset = true;
+            restart[(size_t)t] = 1;
+            const double it_tol = std::min(0.25, std::max(1e-5, 0.5 * tol / std::min(1.0, rel)));
+            k.inner_rel2 = it_tol * it_tol;
+            k.floor2 = 0.0;
+          }
           rel_prev[(size_t)t] = rel;
           need = true;
         }
       }
       if (!need) break;
       STCHK(upload_tasks());
+      if (reset) {
+        k_pass_batched<P_P_FROM_R><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
+        LAUNCHCHK();
+      }
       // re-arm from the same residual partials so that the tasks found
       // converged above are marked done before the inner solves
       k_arm_batched<true><<<ntasks, kThreads, 0, s>>>(d_tasks, pa, 0.0);
@@ -575,13 +628,18 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
       for (int32_t t = 0; t < ntasks; ++t) {
         BTask& k = bt[(size_t)t];
         if (!k.active) continue;
-        iters[(size_t)t] += hsc[(size_t)t].iter;
-        if (hsc[(size_t)t].done == 2 || hsc[(size_t)t].done == 3) {
-          done[(size_t)t] = hsc[(size_t)t].done;
-          k.active = 0;
+        const CgScal& c = hsc[(size_t)t];
+        iters[(size_t)t] += c.iter;
+        seg_iters[(size_t)t] = c.iter;
+        const bool failed = c.done == 2 || c.done == 3 || c.done == 4;
+        bad_run[(size_t)t] = failed ? bad_run[(size_t)t] + 1 : 0;
+        if (failed) {
+          last_bad[(size_t)t] = c.done == 4 ? 0 : c.done;
+          restart[(size_t)t] = 1;
         }
+        keep[(size_t)t] = !failed && c.done == 1;
       }
-      STCHK(upload_tasks());
+      // X64 += x32 for the tasks whose segment did not fail (the pass checks)
       k_pass_batched<P_ACCUM><<<g.v, kThreads, 0, s>>>(d_tasks, d_vtab);
       LAUNCHCHK();
     }

@@ -51,8 +51,11 @@ struct BTask {
   float* p32;
   float* q32;
   CgScal* sc;
-  double inner_rel2;      // refinement: inner CG stop, relative to ||R||^2
+  double inner_rel2;      // residual replacement: segment stop, relative to ||round(R)||^2
+  double floor2;          // residual replacement: segments need not go below this ||r||^2
   int active;             // refinement: 0 once the task has converged
+  int keep_p;             // residual pass keeps the search direction (a replacement)
+  int reset_p;            // P_P_FROM_R: restart the direction, p = r
   int pad0;
   // grid slices
   int ablk0, aper, anrb;  // decoder fused product: blocks [ablk0, ablk0 + 8 aper)
@@ -111,9 +114,11 @@ k_apply_batched(const BTask* __restrict__ tasks, const int* __restrict__ blk_tas
     double a1[1] = {acc[0]};
     block_partials<1>(a1, partials);
   } else if constexpr (KIND == B_RES) {
-    // FP64 residual of the refinement, rounded into the FP32 inner solve
+    // FP64 residual, rounded into the FP32 solve: r (and p, unless this is a
+    // replacement that keeps the direction); x32 is cleared
     if (!tk.active) return;
-    EpiResidual<double, float> epi{tk.B64, tk.r32, tk.p32, tk.x32, tk.gr, tk.gc, partials};
+    EpiResidual<double, float> epi{tk.B64, tk.r32, tk.keep_p ? nullptr : tk.p32, tk.x32, tk.gr,
+                                   tk.gc, partials};
     if (rows > 0)
       apply_rows<double, R, LDS, VEC, 0>(tk.X64, ld, ncols, tk.Lr64, tk.Lc64, BandDev<double>{}, tk.mr, tk.mc, i0, rows,
                                       epi, acc, reinterpret_cast<double*>(panel));
@@ -163,11 +168,19 @@ k_update_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_t
   const BTask& tk = tasks[vblk_task[blockIdx.x]];
   CgScal* sc = tk.sc;
   if (sc->done != 0) return;
+  const bool lead = blockIdx.x == tk.vblk0 && threadIdx.x == 0;
+  // Convergence of the previous iteration is decided here, from the <r, r>
+  // that every workgroup reads alike: the p-update of that iteration has run
+  // in full, so p stays a valid direction for a residual replacement (the
+  // product launched in between is wasted, once per segment).
+  const double rr = sc->rr[parity];
+  if (rr <= sc->thr) {
+    if (lead) sc->done = 1;
+    return;
+  }
   double t[1];
   sum_partials<1>(part_pq + tk.ablk0, 8 * tk.aper, t);
   const double pq = t[0];
-  const double rr = sc->rr[parity];
-  const bool lead = blockIdx.x == tk.vblk0 && threadIdx.x == 0;
   if (bad(pq) || !(pq > 0.0)) {
     if (lead) {
       sc->pq = pq;
@@ -225,11 +238,8 @@ k_pupdate_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_
     if (lead) sc->done = 3;
     return;
   }
-  if (rr_new <= sc->thr) {
-    if (lead) {
-      sc->rr[parity ^ 1] = rr_new;
-      sc->done = 1;
-    }
+  if (sc->aux > 0.0 && rr_new > kDiverge * sc->aux) {  // see k_cg_pupdate
+    if (lead) sc->done = 4;
     return;
   }
   const double beta_d = rr_new / rr;
@@ -279,9 +289,9 @@ k_init_zero_batched(const BTask* __restrict__ tasks, const int* __restrict__ vbl
 // One workgroup per task: arm the CG scalars from that task's partials.
 //   FROM_APPLY = false: partials of a vector kernel (NV = 1, rr = total),
 //                threshold thr_rel2 * bb;
-//   FROM_APPLY = true : partials of the refinement residual (NV = 2),
-//                threshold tk.inner_rel2 * ||round(R)||^2. Inactive tasks
-//                are marked done.
+//   FROM_APPLY = true : partials of the FP64 residual (NV = 2), threshold
+//                max(tk.inner_rel2 * ||round(R)||^2, tk.floor2). Inactive
+//                tasks are marked done.
 template <bool FROM_APPLY>
 __global__ void __launch_bounds__(kThreads)
 k_arm_batched(const BTask* __restrict__ tasks, const double* part, double thr_rel2) {
@@ -301,7 +311,7 @@ k_arm_batched(const BTask* __restrict__ tasks, const double* part, double thr_re
       sc->res2 = t[0];
       sc->aux = t[1];
       sc->rr[0] = sc->rr[1] = t[1];
-      sc->thr = tk.inner_rel2 * t[1];
+      sc->thr = fmax(tk.inner_rel2 * t[1], tk.floor2);
       sc->iter = 0;
       sc->conv_it = 0;
       sc->done = (bad(t[0]) || bad(t[1])) ? 3 : (t[1] <= sc->thr ? 1 : 0);
@@ -311,6 +321,7 @@ k_arm_batched(const BTask* __restrict__ tasks, const double* part, double thr_re
     sum_partials<1>(part + tk.vblk0, tk.nvblk, t);
     if (threadIdx.x == 0) {
       sc->rr[0] = sc->rr[1] = t[0];
+      sc->aux = 0.0;
       sc->thr = thr_rel2 * sc->bb;
       sc->iter = 0;
       sc->conv_it = 0;
@@ -353,13 +364,14 @@ k_apply_sum_batched(const BTask* __restrict__ tasks, const double* part, double*
 // to 2, while the FP32 kernels (4 columns per thread) read up to n rounded
 // to 4.
 enum BPass { P_ACCUM = 0, P_B32 = 1, P_X64_FROM_32 = 2, P_ZERO_X64 = 3, P_ZERO_B64 = 4,
-             P_ZERO_32 = 5 };
+             P_ZERO_32 = 5, P_P_FROM_R = 6 };
 template <int PASS>
 __global__ void __launch_bounds__(kThreads)
 k_pass_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_task) {
   const BTask& tk = tasks[vblk_task[blockIdx.x]];
   if (PASS == P_ACCUM && !tk.active) return;
-  if (PASS == P_ACCUM && tk.sc->done == 3) return;
+  if (PASS == P_ACCUM && tk.sc->done >= 2) return;  // failed FP32 segment: X64 kept
+  if (PASS == P_P_FROM_R && !(tk.active && tk.reset_p)) return;
   const size_t N = (size_t)tk.p * tk.ld;
   const size_t stride = (size_t)tk.nvblk * blockDim.x;
   for (size_t e = (size_t)(blockIdx.x - tk.vblk0) * blockDim.x + threadIdx.x; e < N; e += stride) {
@@ -369,6 +381,7 @@ k_pass_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_tas
     if (PASS == P_ZERO_X64) tk.X64[e] = 0.0;
     if (PASS == P_ZERO_B64) tk.B64[e] = 0.0;
     if (PASS == P_ZERO_32) tk.x32[e] = tk.r32[e] = tk.p32[e] = tk.q32[e] = 0.f;
+    if (PASS == P_P_FROM_R) tk.p32[e] = tk.r32[e];
   }
 }
 

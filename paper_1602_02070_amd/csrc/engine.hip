@@ -287,7 +287,17 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
     // residual B - A(X64) is recomputed in FP64 and replaces the FP32 one, and
     // CG continues with the same search direction (no restart, so the
     // iteration count stays close to that of FP64 CG).
+    // Systems too ill-conditioned for the FP32 recursion to carry a direction
+    // across replacements show it as a failed segment (breakdown, NaN/Inf or
+    // divergence; X64 is left untouched), a segment that does not lower the
+    // true residual, or a segment that needs more than kSlow times the
+    // iterations per decade of true-residual reduction of the first segment
+    // (measured: 1.4-2.0 on well-conditioned systems, 2.4-3.0 where
+    // restarting is faster). From then on the solve runs as restarted refinement (p = r
+    // at every segment, inner tolerance clamp(0.5 tol / rel, 1e-5, 0.25)),
+    // which measured faster there; kMaxBad failed segments in a row end it.
     constexpr double kReplace = 1e-2;
+    constexpr int kMaxBad = 3;
     Operator<float> op{(int)p, (int)n, g32, (float)gr, (float)gc, cfg32};
     if (X0)
       k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, static_cast<const float*>(X0), N);
@@ -300,12 +310,19 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
       EpiResidual<double, float> epi{B64, r32, p32, x32, gr, gc, pa};
       STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, FAM_OTHER));
     }
-    int total = 0;
+    int total = 0, bad_run = 0, last_bad = 0;
+    bool keep = true;      // the first segment starts from p = r (set above)
+    bool restart = h->ir_restart;  // restarted-refinement mode
+    constexpr double kSlow = 2.2;
+    double rel_prev = HUGE_VAL, ipd_first = 0.0;  // iterations per decade, first segment
+    int seg_iters = 0;
     done = 0;
     for (int seg = 0;; ++seg) {
       // arm from the residual partials: the segment stops at
-      // max(kReplace^2 ||r||^2, floor2)
-      k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag64, -1.0, kReplace * kReplace);
+      // max(kReplace^2 ||r||^2, floor2), or in restart mode at it_tol^2 ||r||^2
+      const double it_tol =
+          restart ? std::min(0.25, std::max(1e-5, 0.5 * tol / std::min(1.0, rel_prev))) : kReplace;
+      k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag64, -1.0, it_tol * it_tol);
       LAUNCHCHK();
       STCHK(read_fixed(h));
       const CgScal cs = host_cg(h);
@@ -319,11 +336,34 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
         done = 1;
         break;
       }
+      if (bad_run >= kMaxBad) {
+        done = last_bad;
+        break;
+      }
       if (seg >= kMaxOuter || total >= max_iter) {
         done = 0;
         break;
       }
-      if (cs.thr < floor2) {
+      bool slow = false;
+      if (seg > 0 && rel < rel_prev && seg_iters > 0) {
+        const double ipd = seg_iters / std::log10(rel_prev / rel);  // iterations per decade
+        if (ipd_first == 0.0) ipd_first = ipd;
+        else slow = ipd > kSlow * ipd_first;
+      }
+      if ((!(rel < rel_prev) || slow) && !restart) {  // no or slowing progress
+        restart = true;
+        const double t2 = std::min(0.25, std::max(1e-5, 0.5 * tol / std::min(1.0, rel)));
+        k_cg_arm<2><<<1, kThreads, 0, h->stream>>>(sc, pa, ag64, -1.0, t2 * t2);
+        LAUNCHCHK();
+      }
+      rel_prev = rel;
+      if (restart) keep = false;
+      if (!keep) {
+        k_convert<float, float><<<vg, kThreads, 0, h->stream>>>(p32, r32, N);  // p = r
+        LAUNCHCHK();
+      }
+      if (!restart) {
+        // (reads the armed threshold on the device)
         k_cg_set_thr<<<1, 1, 0, h->stream>>>(sc, floor2);
         LAUNCHCHK();
       }
@@ -331,16 +371,22 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
       STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part));
       const CgScal ci = host_cg(h);
       if (h->debug)
-        std::fprintf(stderr, "[cpca] segment %d: rel %.3e aux %.3e thr %.3e -> iters %d done %d rr %.3e pq %.3e alpha %.3e beta %.3e\n",
-                     seg, rel, cs.aux, cs.thr, ci.iter, ci.done, ci.rr[ci.iter & 1], ci.pq, ci.alpha, ci.beta);
+        std::fprintf(stderr, "[cpca] segment %d: rel %.3e aux %.3e thr %.3e keep %d -> iters %d done %d conv %d\n",
+                     seg, rel, cs.aux, cs.thr, (int)keep, ci.iter, ci.done, ci.conv_it);
       total += ci.iter;
-      if (ci.done == 2 || ci.done == 3) {
-        done = ci.done;
-        break;
+      seg_iters = ci.iter;
+      const bool failed = ci.done == 2 || ci.done == 3 || ci.done == 4;
+      bad_run = failed ? bad_run + 1 : 0;
+      if (failed) {
+        last_bad = ci.done == 4 ? 0 : ci.done;
+        restart = true;
       }
-      // replacement: X64 += x32; r = round(B - A X64); x32 = 0; p kept
-      k_accumulate<float><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
-      LAUNCHCHK();
+      keep = !failed && ci.conv_it != 0;
+      // replacement: X64 += x32 (unless the segment failed); r = round(B - A X64); x32 = 0
+      if (!failed) {
+        k_accumulate<float><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
+        LAUNCHCHK();
+      }
       EpiResidual<double, float> epi{B64, r32, nullptr, x32, gr, gc, pa};
       STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, FAM_OTHER));
     }
@@ -496,6 +542,7 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
   if (const char* s = std::getenv("CPCA_APPLY_R")) h->force_R = std::atoi(s);
   if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
   if (const char* s = std::getenv("CPCA_BAND")) h->force_band = std::atoi(s);
+  if (const char* s = std::getenv("CPCA_IR_MODE")) h->ir_restart = std::string(s) == "restart";
   if (const char* s = std::getenv("CPCA_KERNEL")) {
     const std::string k = s;
     h->force_kernel = k == "rows" ? 0 : k == "strip" ? 1 : k == "panel" ? 2 : -1;

@@ -65,7 +65,7 @@ struct CgScal {
   double aux;     // last rounded-residual norm^2 (refinement)
   double bb;      // ||rhs||^2
   int iter;       // iterations completed
-  int done;       // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
+  int done;       // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf, 4 diverged
   // Convergence detected by the p-update of iteration `it` is recorded as
   // conv_it = it + 1 (-1: converged when armed). The p-update of the
   // converging iteration still runs in full, so the direction stays valid
@@ -85,6 +85,10 @@ struct FistaScal {
 };
 
 __device__ __forceinline__ bool bad(double x) { return !(x == x) || x - x != 0.0; }
+
+// Growth of the recursive <r, r> over its armed value that marks an FP32
+// segment of a residual-replacement solve as diverged.
+constexpr double kDiverge = 1e6;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -1048,6 +1052,16 @@ k_cg_pupdate(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ r, size
     }
     return;
   }
+  // An FP32 segment of a residual-replacement solve whose recursive residual
+  // has grown far beyond the one it started from is abandoned (the FP64
+  // iterate is untouched; the driver restarts from it).
+  if (sc->aux > 0.0 && rr_new > kDiverge * sc->aux) {
+    if (lead) {
+      sc->iter = it + 1;
+      sc->done = 4;
+    }
+    return;
+  }
   const double beta_d = rr_new / rr;
   const T alpha = (T)sc->alpha;  // not written in this kernel
   if (lead) {
@@ -1111,6 +1125,8 @@ k_cg_arm(CgScal* sc, const double* part, int nb, double thr_abs, double rel_tol2
   if (NV == 2) {
     sc->res2 = t[0];
     sc->aux = t[1];
+  } else {
+    sc->aux = 0.0;  // no divergence test outside residual replacement
   }
   sc->rr[0] = rr;
   sc->rr[1] = rr;

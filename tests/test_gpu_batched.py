@@ -93,3 +93,42 @@ def test_batched_iteration_cap_reports_noconv(batch):
         Xs, _, infos = cp.solve_batched(inst, [(0, 1.0, 1.0), (1, 10.0, 10.0)], fista_iters=5,
                                         tol=1e-14, max_iter=3, mode="fp64")
     assert all(i["status"] == 2 and i["iters"] == 3 for i in infos)
+
+
+@pytest.fixture(scope="module")
+def anisotropic():
+    # instance 5 of the batched workload (2077 x 287, helix rows, circle
+    # columns): at gamma = (0.1, 100) the system is too ill-conditioned for a
+    # plain FP32 CG recursion to keep its direction across residual
+    # replacements; the solver must restart and still converge
+    probs, _ = synth.cfg5_batch(0, count=6)
+    return probs[5]
+
+
+def test_fp32_ir_converges_on_anisotropic_gammas(anisotropic):
+    P = anisotropic
+    print(f"[case] anisotropic gammas {P.p}x{P.n}", flush=True)
+    d = dev_problem(P, torch.float32)
+    gam = (0.1, 100.0)
+    X32, i32 = cp.decode(d["Ytil"], d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], *gam,
+                         tol=1e-8, max_iter=50000, mode="fp32_ir")
+    assert i32["status"] == 0 and i32["rel_residual"] <= 1e-8
+    X64, i64 = cp.decode(d["Ytil"].double(), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"],
+                         *gam, tol=1e-12, max_iter=100000, mode="fp64")
+    assert i64["status"] == 0
+    e32 = rel(host(X32), host(X64))
+    print(f"[anisotropic] fp32_ir {i32['iters']} it / {i32['outer_iters']} replacements, "
+          f"fp64 {i64['iters']} it, rel.diff {e32:.2e}", flush=True)
+    assert e32 <= 1e-5
+    # the same task in a batch next to easy ones
+    inst = [cp.Instance(P.p, P.n, d["om_r"], d["om_c"], d["Lr"], d["Lc"], d["Lr_til"],
+                        d["Lc_til"], P.lmax_r_til, P.lmax_c_til, d["Ytil"])]
+    tasks = [(0, 0.1, 100.0), (0, 1.0, 1.0), (0, 100.0, 0.1)]
+    Xs, _, infos = cp.solve_batched(inst, tasks, fista_iters=20, tol=1e-8, max_iter=50000,
+                                    mode="fp32_ir")
+    assert all(i["status"] == 0 for i in infos)
+    Xt1, _ = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], 0.1, 100.0, P.lmax_r_til,
+                       P.lmax_c_til, max_iter=20)
+    X1, _ = cp.decode(Xt1.double(), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 0.1, 100.0,
+                      tol=1e-12, max_iter=100000, mode="fp64")
+    assert rel(host(Xs[0]), host(X1)) <= 1e-5
