@@ -234,8 +234,8 @@ cpca_status cpca_get_profile(cpca_handle h, const char* family,
  * workgroup's rows in LDS when they fit in 64 KiB, 0 = gather the X L_c
  * operands from global memory. kernel in {-1, 0, 1, 2} is the preference for
  * a banded L_c (most entries within 8 or 16 of the diagonal): -1 = automatic
- * (FP32: row panels where L_r rows hold at most 16 off-diagonal entries, else
- * column strips; FP64: column strips), 0 = row kernel, 1 = column strips, 2 = row panels (falls back to
+ * (row panels where L_r rows hold at most 16 off-diagonal entries, else
+ * column strips), 0 = row kernel, 1 = column strips, 2 = row panels (falls back to
  * column strips when a row of L_r is too long). Shapes differ only in the
  * order in which an output's terms are summed (the row-panel kernel adds the
  * diagonal of L_r first) and in the grid-level reduction order of the CG

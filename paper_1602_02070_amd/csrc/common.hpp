@@ -301,14 +301,23 @@ inline bool build_panels(const HostCsr& Lr, const std::vector<uint8_t>& mr, int 
           dg += Lr.v[e];
           continue;
         }
-        P.eidx[base + c] = (uint16_t)loc[(size_t)Lr.ci[e]];
+        P.eidx[base + c] = (uint16_t)(loc[(size_t)Lr.ci[e]] * kPanelRowBytes);
         P.ew[base + c] = Lr.v[e];
         ++c;
       }
       P.rows.push_back(v);
       P.diag.push_back(dg);
-      const int m4[4] = {v, loc[(size_t)v] | (c << 16), (int)mr[(size_t)v], 0};
+      const int m4[4] = {v, loc[(size_t)v] | (c << 16), (int)mr[(size_t)v], c};
       P.meta.insert(P.meta.end(), m4, m4 + 4);
+    }
+    // group count: the rows j of a panel are computed by waves in groups of
+    // 4 consecutive j (j = 16 pass + 4 wave + slot); each row carries the
+    // largest count of its group
+    const size_t r0 = P.rows.size() - R.size();
+    for (size_t g = 0; g < R.size(); g += 4) {
+      int mx = 0;
+      for (size_t j = g; j < std::min(R.size(), g + 4); ++j) mx = std::max(mx, P.meta[4 * (r0 + j) + 3]);
+      for (size_t j = g; j < std::min(R.size(), g + 4); ++j) P.meta[4 * (r0 + j) + 3] = mx;
     }
     ++k;
     P.u_off.push_back((int)P.u.size());
@@ -318,17 +327,19 @@ inline bool build_panels(const HostCsr& Lr, const std::vector<uint8_t>& mr, int 
   return true;
 }
 
-// Half-bandwidth of the diagonal (band) part of L_c: the smallest of 8 and
-// 16 that holds at least 90% of the entries, else 0 (sliced ELL only).
+// Half-bandwidth of the diagonal (band) part of L_c: the smallest of 6, 8
+// and 16 that holds at least 90% of the entries, else 0 (sliced ELL only).
 inline int choose_band(const HostCsr& Lc) {
   if (Lc.nnz == 0) return 0;
-  int64_t in8 = 0, in16 = 0;
+  int64_t in6 = 0, in8 = 0, in16 = 0;
   for (int64_t j = 0; j < Lc.n; ++j)
     for (int32_t e = Lc.rp[j]; e < Lc.rp[j + 1]; ++e) {
       const int64_t d = std::llabs((int64_t)Lc.ci[e] - j);
+      in6 += d <= 6;
       in8 += d <= 8;
       in16 += d <= 16;
     }
+  if (in6 * 10 >= Lc.nnz * 9) return 6;
   if (in8 * 10 >= Lc.nnz * 9) return 8;
   if (in16 * 10 >= Lc.nnz * 9) return 16;
   return 0;
@@ -494,11 +505,14 @@ ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem, int band =
   if (band > 0 && c.vec == W && h->force_band != 0) {
     if (h->force_R <= 0 && h->force_lds != 0 && h->force_kernel != 0) {
       // banded L_c: column strips with the diagonals held in registers, or
-      // (preferred where panel tables exist) the row-panel gather kernel
-      c.bw = band;
+      // (preferred where panel tables exist) the row-panel gather kernel.
+      // A 6-wide band is run by the 8-wide FP32 kernels (their two outer
+      // diagonals are then empty): on the video-shaped workload they measured
+      // 0.370 against 0.388 ms, both at two waves per SIMD; in FP64 the
+      // 6-wide kernels keep two waves per SIMD where the 8-wide ones fit one.
+      c.bw = (elem == 4 && band == 6) ? 8 : band;
       c.strip = h->force_band != 2;
-      // (FP64 rows need twice the registers; there the strip kernel measured faster)
-      if (c.strip && allow_panel && h->force_kernel != 1 && (elem == 4 || h->force_kernel == 2)) {
+      if (c.strip && allow_panel && h->force_kernel != 1) {
         c.panel = true;
         c.strip = false;
       }
@@ -605,17 +619,20 @@ hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p,
   constexpr int W = (int)(16 / sizeof(T));
   if (cfg.panel) {
     if (cfg.vec != W || g.Lp.npan != cfg.npan) return hipErrorInvalidValue;
+    if (cfg.bw == 6) return launch_panel_t<T, 6>(h, X, p, n, g, epi);
     if (cfg.bw == 8) return launch_panel_t<T, 8>(h, X, p, n, g, epi);
     if (cfg.bw == 16) return launch_panel_t<T, 16>(h, X, p, n, g, epi);
     return hipErrorInvalidValue;
   }
   if (cfg.strip) {
     if (cfg.vec != W) return hipErrorInvalidValue;
+    if (cfg.bw == 6) return launch_strip_t<T, 6>(h, X, p, n, g, epi);
     if (cfg.bw == 8) return launch_strip_t<T, 8>(h, X, p, n, g, epi);
     if (cfg.bw == 16) return launch_strip_t<T, 16>(h, X, p, n, g, epi);
     return hipErrorInvalidValue;
   }
   if constexpr (R <= 4) {
+    if (cfg.bw == 6 && cfg.lds && cfg.vec == W) return launch_apply_t<T, R, true, W, 6>(h, X, p, n, g, epi);
     if (cfg.bw == 8 && cfg.lds && cfg.vec == W) return launch_apply_t<T, R, true, W, 8>(h, X, p, n, g, epi);
     if (cfg.bw == 16 && cfg.lds && cfg.vec == W) return launch_apply_t<T, R, true, W, 16>(h, X, p, n, g, epi);
   }

@@ -732,6 +732,7 @@ constexpr int kPanelLanes = 16;   // lanes per row slot
 constexpr int kPanelRows = 64;    // rows per panel (max)
 constexpr int kPanelK = 16;       // off-diagonal L_r entries per row (max)
 constexpr int kPanelGroupMax = 16;
+constexpr int kPanelRowBytes = 256;  // LDS bytes of one staged union row (16 lanes x 16 bytes)
 template <typename T> struct PanelUnion { static constexpr int value = sizeof(T) == 4 ? 160 : 128; };
 
 template <typename T>
@@ -740,9 +741,11 @@ struct PanelDev {
   const int* u;            // union rows of each panel
   const int* r_off;        // npan + 1 offsets into the per-row arrays
   const int* rows;         // output rows, panel by panel
-  const uint16_t* eidx;    // [row][kPanelK] union-local index of each off-diagonal entry
-  const T* ew;             // [row][kPanelK] its value (0 beyond the row's count)
-  const int4* meta;        // [row] {row, local index | count << 16, row mask, 0}
+  const uint16_t* eidx;    // [row][kPanelK] LDS byte offset (union-local index x 256) of each
+                           // off-diagonal entry; 0 with value 0 beyond the row's count
+  const T* ew;             // [row][kPanelK] its value
+  const int4* meta;        // [row] {row, local index | count << 16, row mask, group count}:
+                           // group count = the largest count of the 4 rows one wave computes
   const T* diag;           // [row] diagonal entry of L_r
   int npan;
 };
@@ -767,6 +770,7 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
   constexpr int EM = (EV + kThreads - 1) / kThreads;
   constexpr int H = kWave * VEC;                 // SELL slice height
   static_assert(BW > 0 && UM % NS == 0 && KR % 8 == 0 && RM * KR == 4 * kThreads, "panel shape");
+  static_assert(W * sizeof(T) == kPanelRowBytes && UM * kPanelRowBytes <= 65536, "offset table");
   __shared__ __align__(16) T su[UM * W];
   __shared__ __align__(16) T shl[RM * PAD];
   __shared__ __align__(16) T shr[RM * PAD];
@@ -905,10 +909,14 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
         if (kk + 2 < np) load_idx(kk + 2);
       }
       if (ok) {
+        const char* sub = reinterpret_cast<const char*>(su) + ls * VEC * sizeof(T);
         for (int j = rs; j < nr; j += NS) {
           const int4 mt = smeta[j];
-          const int row = mt.x, ctr = mt.y & 0xffff, cnt = mt.y >> 16;
+          const int row = mt.x, ctr = mt.y & 0xffff;
           const uint8_t mri = (uint8_t)mt.z;
+          // entries beyond a row's own count (up to its wave's largest) have
+          // value 0 and offset 0, so the loop bound is wave-uniform
+          const int cnt = __builtin_amdgcn_readfirstlane(mt.w);
           uint16_t id[KR];
 #pragma unroll
           for (int q = 0; q < KR; q += 8) {
@@ -950,7 +958,7 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
           for (int e = 0; e < KR; ++e) {
             if (e < cnt) {
               T u4[VEC];
-              vld<T, VEC>(&su[id[e] * W + ls * VEC], u4);
+              vld<T, VEC>(reinterpret_cast<const T*>(sub + id[e]), u4);
 #pragma unroll
               for (int v = 0; v < VEC; ++v) accr[v] += wv[e] * u4[v];
             }
