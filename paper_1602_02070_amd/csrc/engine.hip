@@ -423,11 +423,12 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   STCHK(fetch_csr("Lc_til", Lc_t, Lc));
   const size_t N = (size_t)rho_r * rho_c;
   std::vector<uint8_t> mr((size_t)rho_r, 0), mc((size_t)rho_c, 0);
-  const ApplyCfg cfg = choose_cfg(h, rho_r, rho_c, sizeof(double), choose_band(Lc));
+  ApplyCfg cfg = choose_cfg(h, rho_r, rho_c, sizeof(double), choose_band(Lc));
   Staging stg;
   const GraphImage<double> gi = stage_graph<double>(stg, Lr, Lc, mr, mc, slice_height(cfg), cfg.bw);
-  const int ag = apply_grid(cfg, (int)rho_r, (int)rho_c);
-  const int maxgrid = std::max(ag, 2048);
+  // partial sums sized for every launch shape the tuner may pick
+  const int maxgrid = std::max({apply_grid(cfg, (int)rho_r, (int)rho_c),
+                                max_apply_grid((int)rho_r, (int)rho_c), 2048});
   char* img = nullptr;
   double *pa = nullptr, *pb = nullptr, *Y = nullptr, *S = nullptr, *Za = nullptr, *Zb = nullptr;
   auto layout = [&](Arena& a) {
@@ -449,6 +450,17 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   layout(a);
   HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
   const DevGraph<double> g = bind_graph<double>(gi, img);
+  if (h->force_R == -1) {
+    // autotuned launch shape of the FISTA product, timed on the sampled data
+    const std::string key = tune_key("fista", sizeof(double), rho_r, rho_c, Lr.nnz + Lc.nnz);
+    STCHK(autotune(h, key, rho_c, sizeof(double), cfg,
+                   [&](const ApplyCfg& c) -> cpca_status {
+                     EpiApply<double> epi{Zb, 1.0, 1.0, pb};
+                     return launch_apply<double>(h, c, Za, (int)rho_r, (int)rho_c, g, epi, FAM_OTHER);
+                   },
+                   &cfg));
+  }
+  const int ag = apply_grid(cfg, (int)rho_r, (int)rho_c);
   FistaScal* fs = fista_ptr(h);
   const int vg = vec_grid(N);
   const bool f32 = mode != CPCA_FP64;

@@ -359,3 +359,29 @@ def test_invalid_inputs_are_rejected_on_device(cfg1):
         X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
                             tol=1e-14, max_iter=3)
     assert info["status"] == 2 and info["iters"] == 3
+
+
+def test_autotuned_pipeline_matches_oracle():
+    # with autotuning on, the FISTA and CG products run in the shapes the
+    # tuner picks on the live operands; results stay at parity
+    P = synth.small_problem(21, p_shape=(20, 24), n=400, rank=4, frac=0.3, fista_iters=150,
+                            col_kind="band")
+    _announce(f"autotuned pipeline {P.p}x{P.n}")
+    d = dev_problem(P)
+    ref_t, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, P.gamma_r, P.gamma_c, P.lmax_r_til,
+                        P.lmax_c_til, 150)
+    ref = OD.decode(ref_t, P.p, P.n, P.omega_r, P.omega_c, P.Lr, P.Lc, P.gamma_r, P.gamma_c)
+    cp.set_apply_config(-1, -1)
+    try:
+        for _ in range(2):  # the second call takes the cached choices
+            Xt, _ = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], P.gamma_r, P.gamma_c,
+                              P.lmax_r_til, P.lmax_c_til, max_iter=150)
+            assert rel(host(Xt), ref_t) <= 1e-11
+            X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], P.gamma_r,
+                                P.gamma_c, tol=1e-12, mode="fp64")
+            assert info["status"] == 0 and rel(host(X), ref) <= 1e-9
+            X32, _ = cp.decode(Xt.float(), d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"],
+                               P.gamma_r, P.gamma_c, tol=1e-9)
+            assert rel(host(X32), ref) <= 1e-6
+    finally:
+        cp.set_apply_config(0, -1)
