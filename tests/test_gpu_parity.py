@@ -385,3 +385,81 @@ def test_autotuned_pipeline_matches_oracle():
             assert rel(host(X32), ref) <= 1e-6
     finally:
         cp.set_apply_config(0, -1)
+
+
+def _decode_both(Xtil, om_r, om_c, p, n, Lr, Lc, gr, gc):
+    """GPU decode in FP64 and FP32_IR with the default launch shapes."""
+    Lrg, Lcg = cp.Graph.from_scipy(Lr), cp.Graph.from_scipy(Lc)
+    r = torch.from_numpy(om_r).cuda()
+    c = torch.from_numpy(om_c).cuda()
+    X64, i64 = cp.decode(torch.from_numpy(Xtil).cuda(), r, c, p, n, Lrg, Lcg, gr, gc, tol=1e-13,
+                         mode="fp64")
+    X32, i32 = cp.decode(torch.from_numpy(Xtil).float().cuda(), r, c, p, n, Lrg, Lcg, gr, gc,
+                         tol=1e-9)
+    return host(X64), i64, host(X32), i32
+
+
+@pytest.mark.parametrize("single", ["row", "column"])
+def test_decode_single_row_or_column(single):
+    # one node on one side: its Laplacian is the empty 1 x 1 matrix
+    import scipy.sparse as sps
+    _announce(f"degenerate single {single}")
+    rng = np.random.default_rng(31)
+    L1 = sps.csr_matrix((1, 1))
+    Lother, _ = synth.knn_laplacian(synth.circle_coords(300, rng, noise_std=0.05), 10)
+    if single == "row":
+        p, n, Lr, Lc = 1, 300, L1, Lother
+        om_r = np.array([0], np.int32)
+        om_c = np.sort(rng.choice(n, 60, replace=False)).astype(np.int32)
+    else:
+        p, n, Lr, Lc = 300, 1, Lother, L1
+        om_r = np.sort(rng.choice(p, 60, replace=False)).astype(np.int32)
+        om_c = np.array([0], np.int32)
+    Xtil = rng.standard_normal((len(om_r), len(om_c)))
+    ref = OD.decode(Xtil, p, n, om_r, om_c, Lr, Lc, 0.7, 1.3)
+    X64, i64, X32, i32 = _decode_both(Xtil, om_r, om_c, p, n, Lr, Lc, 0.7, 1.3)
+    assert i64["status"] == 0 and i32["status"] == 0
+    assert rel(X64, ref) <= 1e-10
+    assert rel(X32, ref) <= 1e-6
+
+
+def test_decode_with_isolated_nodes_in_both_graphs():
+    # rows / columns of degree 0 (empty CSR rows): the panel tables hold no
+    # entries for them; sampled isolated rows keep the system definite
+    import scipy.sparse as sps
+    _announce("degenerate isolated nodes")
+    rng = np.random.default_rng(32)
+    Lg, _ = synth.knn_laplacian(synth.grid_coords(12, 14), 10)
+    Lr = sps.block_diag([Lg, sps.csr_matrix((5, 5))], format="csr")
+    Lb, _ = synth.knn_laplacian(np.arange(596.0)[:, None], 10)
+    Lc = sps.block_diag([Lb, sps.csr_matrix((4, 4))], format="csr")
+    p, n = Lr.shape[0], Lc.shape[0]
+    om_r = np.sort(np.concatenate([rng.choice(168, 40, replace=False),
+                                   np.arange(168, 173)])).astype(np.int32)
+    om_c = np.sort(np.concatenate([rng.choice(596, 90, replace=False),
+                                   np.arange(596, 600)])).astype(np.int32)
+    Xtil = rng.standard_normal((len(om_r), len(om_c)))
+    ref = OD.decode(Xtil, p, n, om_r, om_c, Lr, Lc, 1.1, 0.6, method="cg", tol=1e-13)
+    for kernel in ("panel", "strip", "rows"):
+        cp.set_apply_config(0, -1, kernel)
+        try:
+            X64, i64, X32, i32 = _decode_both(Xtil, om_r, om_c, p, n, Lr, Lc, 1.1, 0.6)
+        finally:
+            cp.set_apply_config(0, -1)
+        assert i64["status"] == 0 and i32["status"] == 0, kernel
+        assert rel(X64, ref) <= 1e-9, kernel
+        assert rel(X32, ref) <= 1e-6, kernel
+
+
+def test_full_sampling_without_regularisation_returns_samples():
+    # every entry sampled and gamma = 0: the system is the identity, X = X~
+    _announce("degenerate full sampling gamma 0")
+    P = synth.small_problem(33, p_shape=(9, 12), n=200, frac=1.0)
+    rng = np.random.default_rng(33)
+    Xtil = rng.standard_normal((P.p, P.n))
+    om_r = np.arange(P.p, dtype=np.int32)
+    om_c = np.arange(P.n, dtype=np.int32)
+    X64, i64, X32, i32 = _decode_both(Xtil, om_r, om_c, P.p, P.n, P.Lr, P.Lc, 0.0, 0.0)
+    assert i64["status"] == 0 and i64["iters"] <= 1
+    assert np.array_equal(X64, Xtil)
+    assert rel(X32, Xtil) <= 1e-7
