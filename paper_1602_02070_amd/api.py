@@ -305,10 +305,12 @@ class Instance:
 
 def solve_batched(instances, tasks, fista_iters: int = 500, tol: float = 1e-9,
                   max_iter: int = 20000, mode: str | None = None, want_xtil: bool = False,
-                  raise_errors: bool = True):
+                  raise_errors: bool = True, h=None):
     """FISTA + alternate decoder for every task (instance index, gamma_r,
     gamma_c) in one batched run. Returns (X list, X~ list or None, infos).
-    With raise_errors=False a failed task is reported only in its info."""
+    With raise_errors=False a failed task is reported only in its info.
+    h: library handle (default: the one of the inputs' device and the
+    current stream)."""
     if not instances or not tasks:
         raise ValueError("need at least one instance and one task")
     mode = mode_for(instances[0].Ytil.dtype, mode)
@@ -336,7 +338,7 @@ def solve_batched(instances, tasks, fista_iters: int = 500, tol: float = 1e-9,
         ctk[t] = CpcaTask(int(inst), 0, float(gr), float(gc), X.data_ptr(),
                           None if Xt is None else Xt.data_ptr())
     infos = (CpcaInfo * len(tasks))()
-    st = _lib.load().cpca_solve_batched(handle(instances[0].Ytil.device), _lib.MODES[mode], cin,
+    st = _lib.load().cpca_solve_batched(h or handle(instances[0].Ytil.device), _lib.MODES[mode], cin,
                                         len(instances), ctk, len(tasks), int(fista_iters),
                                         float(tol), int(max_iter), infos)
     if raise_errors:

@@ -96,13 +96,15 @@ struct Grids {
 };
 
 // Block tables for rows-per-workgroup R (the apply and FISTA slices depend
-// on R, the vector slices do not).
+// on R, the vector slices do not). With `only`, tasks whose entry is 0 get no
+// blocks (their block ranges keep stale values that no block reads).
 void build_tables(std::vector<BTask>& bt, int R, std::vector<int>& atab, std::vector<int>& ftab,
-                  std::vector<int>& vtab, Grids& g) {
+                  std::vector<int>& vtab, Grids& g, const std::vector<char>* only = nullptr) {
   atab.clear();
   ftab.clear();
   vtab.clear();
   for (size_t t = 0; t < bt.size(); ++t) {
+    if (only && !(*only)[t]) continue;
     BTask& k = bt[t];
     k.anrb = (k.p + R - 1) / R;
     k.aper = (k.anrb + 7) / 8;
@@ -446,33 +448,78 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
 
   // ---- CG over all tasks, chunks of iterations replayed as a graph
   constexpr int kChunk = 16;  // even: the parity of every replay matches the capture
+  // Tail compaction: once at most half of the tasks in the current block
+  // tables are still running, the tables are rebuilt over the running tasks
+  // and the chunk graph is captured again, so that the slow tasks at the end
+  // no longer launch a workgroup per row block of every converged task. A
+  // task keeps its own block order and reduction order, so results are
+  // unchanged. The full tables are restored before returning.
   auto run_cg = [&](int max_it, int* ran) -> cpca_status {
     hipStream_t cs;
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipEvent_t ev;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    Grids gr = g;  // grids of the tables on the device
     auto enqueue_iter = [&](hipStream_t st, int par) -> hipError_t {
-      hipError_t e = cg_launch(st, bc, g.a, par);
+      hipError_t e = cg_launch(st, bc, gr.a, par);
       if (e != hipSuccess) return e;
       if (cg32) {
-        k_update_batched<float><<<g.v, kThreads, 0, st>>>(d_tasks, d_vtab, pa, pb, par);
-        k_pupdate_batched<float><<<g.v, kThreads, 0, st>>>(d_tasks, d_vtab, pb, par);
+        k_update_batched<float><<<gr.v, kThreads, 0, st>>>(d_tasks, d_vtab, pa, pb, par);
+        k_pupdate_batched<float><<<gr.v, kThreads, 0, st>>>(d_tasks, d_vtab, pb, par);
       } else {
-        k_update_batched<double><<<g.v, kThreads, 0, st>>>(d_tasks, d_vtab, pa, pb, par);
-        k_pupdate_batched<double><<<g.v, kThreads, 0, st>>>(d_tasks, d_vtab, pb, par);
+        k_update_batched<double><<<gr.v, kThreads, 0, st>>>(d_tasks, d_vtab, pa, pb, par);
+        k_pupdate_batched<double><<<gr.v, kThreads, 0, st>>>(d_tasks, d_vtab, pb, par);
       }
       return hipGetLastError();
     };
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    auto capture = [&]() -> hipError_t {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+      if (max_it < kChunk) return hipSuccess;
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      for (int k = 0; k < kChunk && e == hipSuccess; ++k) e = enqueue_iter(cs, k & 1);
+      const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      return e;
+    };
+    // the tables of the running tasks; called with the streams idle
+    int in_tables = ntasks;
+    bool compacted = false;
+    std::vector<char> live((size_t)ntasks, 0);
+    std::vector<BTask> btc;
+    std::vector<int> atc, ftc, vtc;
+    auto compact = [&](int n_live, int it_now) -> hipError_t {
+      btc = bt;
+      build_tables(btc, bc.R, atc, ftc, vtc, gr, &live);
+      hipError_t e = hipMemcpyAsync(d_tasks, btc.data(), sizeof(BTask) * btc.size(),
+                                    hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d_atab, atc.data(), sizeof(int) * atc.size(), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d_vtab, vtc.data(), sizeof(int) * vtc.size(), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (h->debug)
+        std::fprintf(stderr, "[cpca] batched CG: tables compacted from %d to %d tasks at iteration %d\n",
+                     in_tables, n_live, it_now);
+      in_tables = n_live;
+      compacted = true;
+      return e;
+    };
     hipError_t err = hipSuccess;
-    if (max_it >= kChunk) {
-      err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-      for (int k = 0; k < kChunk && err == hipSuccess; ++k) err = enqueue_iter(cs, k & 1);
-      hipError_t e2 = hipStreamEndCapture(cs, &graph);
-      if (err == hipSuccess) err = e2;
-      if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (h->batch_compact) {
+      int n_live = 0;
+      for (int32_t t = 0; t < ntasks; ++t) {
+        live[(size_t)t] = bt[(size_t)t].active ? 1 : 0;
+        n_live += live[(size_t)t];
+      }
+      if (n_live > 0 && 2 * n_live <= in_tables) err = compact(n_live, 0);
     }
+    if (err == hipSuccess) err = capture();
     int it = 0;
     cpca_status st = CPCA_OK;
     if (err == hipSuccess) err = hipEventRecord(ev, s);
@@ -488,10 +535,19 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
       if (err == hipSuccess) err = hipEventRecord(ev, cs);
       if (err == hipSuccess) err = hipStreamWaitEvent(s, ev, 0);
       if (err != hipSuccess) break;
-      if ((st = read_sc()) != CPCA_OK) break;
-      bool all = true;
-      for (const CgScal& c : hsc) all = all && c.done != 0;
-      if (all) break;
+      if ((st = read_sc()) != CPCA_OK) break;  // both streams are idle after this
+      int n_live = 0;
+      for (int32_t t = 0; t < ntasks; ++t) {
+        live[(size_t)t] = hsc[(size_t)t].done == 0 ? 1 : 0;
+        n_live += live[(size_t)t];
+      }
+      if (n_live == 0) break;
+      // recapture only while whole chunks remain (the parity of the next
+      // iteration is even there, as in the capture)
+      if (h->batch_compact && exec && 2 * n_live <= in_tables && it + kChunk <= max_it) {
+        err = compact(n_live, it);
+        if (err == hipSuccess) err = capture();
+      }
     }
     const hipError_t e3 = hipStreamSynchronize(cs);
     if (err == hipSuccess) err = e3;
@@ -500,6 +556,7 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
     (void)hipEventDestroy(ev);
     (void)hipStreamDestroy(cs);
     if (err != hipSuccess) return fail(CPCA_EHIP, std::string("batched CG: ") + hipGetErrorString(err));
+    if (compacted) STCHK(upload_tasks());
     *ran = it;
     return st;
   };

@@ -263,7 +263,11 @@ k_pupdate_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_
   }
 }
 
-// Per-task start of CG from zero: x = 0, r = p = B; partials of <B, B>.
+// Per-task start of CG from zero: x = 0, r = p = B, q = 0; partials of
+// <B, B>. q is cleared over the whole padded extent: the FP64 product (2
+// columns per thread) writes q only up to n rounded to 2, while the vector
+// kernels run over p * ld with ld = n rounded to 4; cleared, the padding of
+// q (and so of r, p and x) stays zero.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_init_zero_batched(const BTask* __restrict__ tasks, const int* __restrict__ vblk_task,
@@ -272,6 +276,7 @@ k_init_zero_batched(const BTask* __restrict__ tasks, const int* __restrict__ vbl
   T* x = BVec<T>::x(tk);
   T* r = BVec<T>::r(tk);
   T* p = BVec<T>::p(tk);
+  T* q = BVec<T>::q(tk);
   const T* B = BVec<T>::B(tk);
   const size_t N = (size_t)tk.p * tk.ld;
   const size_t stride = (size_t)tk.nvblk * blockDim.x;
@@ -281,6 +286,7 @@ k_init_zero_batched(const BTask* __restrict__ tasks, const int* __restrict__ vbl
     x[e] = T(0);
     r[e] = bv;
     p[e] = bv;
+    q[e] = T(0);
     acc[0] += (double)bv * (double)bv;
   }
   block_partials<1>(acc, part);

@@ -40,6 +40,7 @@ struct cpca_handle_s {
   int force_kernel = -1;       // banded-L_c kernel preference (-1 auto, 0 rows, 1 strip, 2 panel)
   bool debug = false;          // per-segment trace on stderr (CPCA_DEBUG=1)
   bool ir_restart = false;     // FP32_IR as restarted refinement only (CPCA_IR_MODE=restart)
+  bool batch_compact = true;   // batched CG: shrink the block tables in the tail (CPCA_BATCH_COMPACT=0 off)
   std::vector<std::pair<std::string, std::pair<int, int>>> tuned;  // autotuner cache
   bool prof = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)

@@ -555,6 +555,7 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
   if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
   if (const char* s = std::getenv("CPCA_BAND")) h->force_band = std::atoi(s);
   if (const char* s = std::getenv("CPCA_IR_MODE")) h->ir_restart = std::string(s) == "restart";
+  if (const char* s = std::getenv("CPCA_BATCH_COMPACT")) h->batch_compact = std::atoi(s) != 0;
   if (const char* s = std::getenv("CPCA_KERNEL")) {
     const std::string k = s;
     h->force_kernel = k == "rows" ? 0 : k == "strip" ? 1 : k == "panel" ? 2 : -1;

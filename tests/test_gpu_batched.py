@@ -1,10 +1,14 @@
 """Batched solves (many instances of uneven sizes, gamma grids) against the
 single-problem calls and against the FP64 oracle."""
+import ctypes
+import os
+
 import numpy as np
 import pytest
 import torch
 
 import paper_1602_02070_amd as cp
+from paper_1602_02070_amd import _lib
 import synth
 from oracle import decoder as OD
 from oracle import frpcag as OF
@@ -85,6 +89,64 @@ def test_batched_deterministic_and_autotuned(batch):
         cp.set_apply_config(0, -1)
     X2, _ = cp.decode(I.Ytil, I.omega_r, I.omega_c, P.p, P.n, I.Lr, I.Lc, 1.0, 1.0, tol=1e-10)
     assert rel(host(X1), host(X2)) <= 1e-6
+
+
+def _handle_with_env(env):
+    """A new library handle on the current stream, created under `env`."""
+    lib = _lib.load()
+    hp = ctypes.c_void_p()
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        st = lib.cpca_create(ctypes.byref(hp),
+                             ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream)))
+    finally:
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+    assert st == 0
+    return hp.value
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+def test_batched_tail_compaction_changes_nothing(batch, mode, capfd):
+    # the block tables shrink to the running tasks as tasks converge; every
+    # task keeps its own blocks and reduction order, so the outputs and
+    # iteration counts must be bit-identical to a run with full tables
+    print(f"[case] batched tail compaction {mode}", flush=True)
+    dt = torch.float64 if mode == "fp64" else torch.float32
+    inst = _instances(batch, dt)
+    tasks = _tasks(batch)
+    tol = 1e-13 if mode == "fp64" else 1e-10
+    lib = _lib.load()
+    h_on = _handle_with_env({"CPCA_DEBUG": "1"})
+    h_off = _handle_with_env({"CPCA_BATCH_COMPACT": "0"})
+    try:
+        # leave FP32 data in the first handle's workspace: the padding
+        # columns of the CG vectors must not carry it into the dot products
+        # (the second handle's workspace is new)
+        cp.solve_batched(_instances(batch, torch.float32), tasks, fista_iters=J, tol=1e-10,
+                         mode="fp32_ir", h=h_on)
+        torch.cuda.synchronize()
+        capfd.readouterr()
+        a, _, ia = cp.solve_batched(inst, tasks, fista_iters=J, tol=tol, mode=mode, h=h_on)
+        torch.cuda.synchronize()
+        log = capfd.readouterr().err
+        b, _, ib = cp.solve_batched(inst, tasks, fista_iters=J, tol=tol, mode=mode, h=h_off)
+        torch.cuda.synchronize()
+    finally:
+        lib.cpca_destroy(h_on)
+        lib.cpca_destroy(h_off)
+    n_comp = log.count("tables compacted")
+    its = [i["iters"] for i in ia]
+    print(f"[compaction] iterations {min(its)}..{max(its)}, {n_comp} compactions", flush=True)
+    assert n_comp >= 1
+    assert all(i["status"] == 0 for i in ia)
+    assert [i["iters"] for i in ib] == its
+    assert [i["outer_iters"] for i in ib] == [i["outer_iters"] for i in ia]
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
 
 
 def test_batched_iteration_cap_reports_noconv(batch):
