@@ -182,6 +182,63 @@ cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode,
                                  double* dgamma_c, cpca_info* info);
 
 /*
+ * Subspace-upsampling approximate decoder (Section V.C, Algorithm 2). With
+ * the thin SVD X~ = U~ S~ V~^T (singular values descending):
+ *   1. k = the number of singular values >= sigma_ratio * S~[0] that are
+ *      positive (the paper takes sigma_ratio = 0.1), at most k_max;
+ *   2. each kept column u~ of U~ is upsampled over L_r (and each v~ of V~
+ *      over L_c) as min u^T L u subject to u[omega] = u~ (eq. approx_uv),
+ *      whose solution (the graph-upsampling lemma) keeps u~ on omega and
+ *      solves L(omega-bar, omega-bar) u = -L(omega-bar, omega) u~ on the rest
+ *      (Jacobi-preconditioned CG per column, FP64);
+ *   3. the upsampled columns are normalised to unit norm, the singular values
+ *      scaled by sqrt(n p / (rho_r rho_c (1 - delta))), and
+ *      X = U diag(scaled S~[:k]) V^T is written.
+ * The SVD (one-sided Jacobi), the CG and all scalars are FP64 in every mode;
+ * the FP32 modes convert the input and round the output.
+ * Xtil        rho_r x rho_c (row a, column b belongs at (omega_r[a], omega_c[b])),
+ *             min(rho_r, rho_c) <= 4096.
+ * omega_r/_c  rho_r / rho_c distinct int32 indices in [0, p) / [0, n).
+ * Lr, Lc      p x p and n x n Laplacians (symmetric PSD; values used in
+ *             place on the device). Where a connected component of the
+ *             unsampled nodes has no edge to a sampled node, its rows get the
+ *             minimum-norm value 0.
+ * delta       RIP constant in [0, 1).
+ * sigma_ratio in [0, 1]; k_max in [1, 64].
+ * tol         > 0: per-column CG stop ||r|| <= tol ||b|| (recursive residual).
+ * max_iter    >= 0: cap on CG iterations (both graphs run together).
+ * X_out       p x n output (mode type). sigma_out: optional HOST array of
+ *             min(rho_r, rho_c) doubles receiving all singular values of X~,
+ *             descending.
+ * X is unique when the kept singular values are distinct (the sign of each
+ * singular pair cancels).
+ * Returns OK, EINVAL, ENOCONV (CG cap reached or the SVD did not converge in
+ * 40 sweeps; X is written either way), ENOTSPD, ENAN, EHIP, ENOMEM.
+ */
+typedef struct {
+  int32_t k;               /* kept singular values                           */
+  int32_t svd_sweeps;      /* Jacobi sweeps run                              */
+  int32_t iters_r;         /* CG iterations, row graph (largest column)      */
+  int32_t iters_c;         /* CG iterations, column graph                    */
+  int32_t status;          /* same value as the call's return code           */
+  int32_t reserved;
+  double rel_residual_r;   /* largest per-column ||r|| / ||b||, row graph    */
+  double rel_residual_c;   /* same, column graph                             */
+  double scale;            /* sqrt(n p / (rho_r rho_c (1 - delta)))          */
+  double ms;               /* wall time of the call                          */
+} cpca_approx_info;
+
+cpca_status cpca_approx_decode(cpca_handle h, cpca_mode mode,
+                               const void* Xtil, int64_t rho_r, int64_t rho_c,
+                               const int32_t* omega_r, const int32_t* omega_c,
+                               int64_t p, int64_t n,
+                               const cpca_csr* Lr, const cpca_csr* Lc,
+                               double delta, double sigma_ratio, int32_t k_max,
+                               double tol, int32_t max_iter,
+                               void* X_out, double* sigma_out,
+                               cpca_approx_info* info);
+
+/*
  * One application of the decoder operator (the fused two-sided sparse
  * product of eq. alternatedecoder's normal equations):
  *   Q = (m_r m_c^T) o P + gamma_r L_r P + gamma_c P L_c,  *pq = <P, Q> (FP64).

@@ -12,10 +12,13 @@ Contents (each function cites the passage it follows):
              normal-equation operator, right-hand side, exact solution by a
              dense Kronecker factorisation, a sparse direct factorisation or
              textbook conjugate gradient, and the adjoint (backward) of the
-             decode map.
+             decode map;
+  approx  -- the subspace-upsampling approximate decoder (Algorithm 2,
+             Section V.C): thin SVD, rank selection, graph upsampling by the
+             closed form of its lemma, normalisation, RIP scaling.
 
 Every floating-point computation is FP64. Parity status of each function is
 stated in its docstring; all functions here are pinned by tests that check
 them against closed forms, brute force or invariants fixed by the paper.
 """
-from . import frpcag, decoder  # noqa: F401
+from . import frpcag, decoder, approx  # noqa: F401

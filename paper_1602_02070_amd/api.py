@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
+from ._lib import CpcaApproxInfo, CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
 
 __all__ = ["CpcaError", "Graph", "handle", "frpcag", "decode", "decode_backward",
            "apply_operator", "Decode", "DecodeProblem", "profiling", "get_profile",
@@ -195,6 +195,36 @@ def decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tensor, p: 
                                  ctypes.byref(info))
     _check(st, "cpca_decode")
     return out, info.as_dict()
+
+
+def approx_decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tensor, p: int,
+                  n: int, Lr: Graph, Lc: Graph, delta: float = 0.0, sigma_ratio: float = 0.1,
+                  k_max: int = 64, tol: float = 1e-10, max_iter: int = 20000,
+                  mode: str | None = None, out: torch.Tensor | None = None, h=None):
+    """Subspace-upsampling approximate decoder (Section V.C, Algorithm 2).
+
+    Returns (X, sigma, info): X is p x n, sigma the singular values of Xtil
+    (descending, FP64 host array), info the call's cpca_approx_info."""
+    mode = mode_for(Xtil.dtype, mode)
+    dt = _dtype_of(mode)
+    Xt = _need(Xtil, "Xtil", dt)
+    om_r = _index(omega_r, "omega_r")
+    om_c = _index(omega_c, "omega_c")
+    if Xt.shape != (om_r.numel(), om_c.numel()):
+        raise ValueError("Xtil shape must be (len(omega_r), len(omega_c))")
+    if out is None:
+        out = torch.empty((p, n), dtype=dt, device=Xt.device)
+    else:
+        out = _need(out, "out", dt, (p, n))
+    sigma = (ctypes.c_double * max(1, min(Xt.shape)))()
+    info = CpcaApproxInfo()
+    st = _lib.load().cpca_approx_decode(h or handle(Xt.device), _lib.MODES[mode], _ptr(Xt),
+                                        Xt.shape[0], Xt.shape[1], _ptr(om_r), _ptr(om_c), int(p),
+                                        int(n), ctypes.byref(Lr.desc), ctypes.byref(Lc.desc),
+                                        float(delta), float(sigma_ratio), int(k_max), float(tol),
+                                        int(max_iter), _ptr(out), sigma, ctypes.byref(info))
+    _check(st, "cpca_approx_decode")
+    return out, [sigma[i] for i in range(min(Xt.shape))], info.as_dict()
 
 
 def decode_backward(G: torch.Tensor, X: torch.Tensor, omega_r, omega_c, p: int, n: int,

@@ -1,0 +1,930 @@
+// Subspace-upsampling approximate decoder (Algorithm 2, Section V-C) on
+// gfx950: cpca_approx_decode.
+//
+//   1. Thin SVD of X~ by one-sided (Hestenes) Jacobi: the rows of
+//      W = X~^T (rho_r >= rho_c) or W = X~ (rho_r < rho_c) are orthogonalised
+//      pairwise, in round-robin order (every round rotates m/2 disjoint
+//      pairs, one workgroup per pair; m - 1 rounds make a sweep, captured as
+//      one HIP graph and replayed until a sweep rotates nothing). The same
+//      rotations applied to the identity give the other singular vectors.
+//   2. k = the number of singular values >= ratio * sigma_max (positive,
+//      at most k_max), chosen on the device with the order of the values.
+//   3. Graph upsampling of the k kept left vectors over L_r and right
+//      vectors over L_c: the lemma of Section V-C gives the unknown rows as
+//      the solution of L(omega-bar, omega-bar) u = -L(omega-bar, omega) u~,
+//      solved by Jacobi-preconditioned CG, one independent CG per column,
+//      both graphs in the same launches, chunks of iterations as HIP graphs.
+//   4.-6. Column norms, the RIP scale sqrt(n p / (rho_r rho_c (1 - delta)))
+//      and X = U S V^T as one rank-k product that streams X to HBM.
+//
+// Everything before the last step works on small arrays and is latency
+// bound; the last step writes the p x n output once and is HBM bound.
+#include "common.hpp"
+
+namespace {
+
+constexpr int kApproxKMax = 64;       // largest k (columns per row in the CG layout)
+constexpr int kMaxSweeps = 40;        // Jacobi sweeps before giving up
+constexpr int kUpChunk = 16;          // CG iterations per graph replay (even)
+constexpr int kUpMaxBlocks = 256;     // workgroups per graph side in the CG kernels
+constexpr int kSvdMaxM = 4096;        // min(rho_r, rho_c) held in LDS by the rank kernel
+
+// ------------------------------------------------------------ block sums
+// Sum of NV values over the workgroup (kThreads threads); every thread gets
+// the totals.
+template <int NV>
+__device__ void block_sum(double (&v)[NV]) {
+  __shared__ double red[NV][kMaxWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) red[k][wid] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < kMaxWaves; ++w) s += red[k][w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Per-column sums over a workgroup whose thread t holds column t % KP (KP a
+// power of two <= 64): a fixed-order tree in LDS, so results do not depend
+// on timing. On return red[c] holds the sum of column c (c < KP).
+__device__ void column_tree(double* red, int KP) {
+  for (int s = kThreads / 2; s >= KP; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- SVD kernels
+// W (m x len) from X~ (rho_r x rho_c, row-major, type TI): W = X~^T when
+// trans, else X~. Q = I (m x m).
+template <typename TI>
+__global__ void __launch_bounds__(kThreads)
+k_jac_load(double* __restrict__ W, double* __restrict__ Q, const TI* __restrict__ Xt, int rho_r,
+           int rho_c, int trans, int m) {
+  const size_t N = (size_t)rho_r * rho_c;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+    const size_t i = e / rho_c, j = e - i * rho_c;
+    const double v = (double)Xt[e];
+    if (trans) W[j * rho_r + i] = v;
+    else W[e] = v;
+  }
+  const size_t M2 = (size_t)m * m;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < M2; e += stride)
+    Q[e] = (e / m == e % m) ? 1.0 : 0.0;
+}
+
+// ||W||_F^2 (one workgroup); rotations leave it unchanged.
+__global__ void __launch_bounds__(kThreads)
+k_jac_fro(const double* __restrict__ W, size_t N, double* __restrict__ fro2) {
+  double s[1] = {0.0};
+  for (size_t e = threadIdx.x; e < N; e += kThreads) s[0] += W[e] * W[e];
+  block_sum<1>(s);
+  if (threadIdx.x == 0) fro2[0] = s[0];
+}
+
+// One round of one-sided Jacobi: workgroup b rotates the pair of rows
+// pairs[b] of W (length len) so that they become orthogonal, and applies the
+// same rotation to the rows of Q (length m). Pairs whose normalised inner
+// product is at most tol are left alone, and so are rows whose squared norm
+// is at most floor_rel * ||W||_F^2: those are rounding noise of a
+// rank-deficient X~, and rotating them against each other would never stop.
+// count gathers the rotations done.
+__global__ void __launch_bounds__(kThreads)
+k_jac_round(double* __restrict__ W, double* __restrict__ Q, int m, int len,
+            const int2* __restrict__ pairs, double tol, const double* __restrict__ fro2,
+            double floor_rel, int* __restrict__ count) {
+  const int2 pr = pairs[blockIdx.x];
+  if (pr.x >= m || pr.y >= m) return;  // the idle slot of an odd m
+  double* wa = W + (size_t)pr.x * len;
+  double* wb = W + (size_t)pr.y * len;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < len; i += kThreads) {
+    const double x = wa[i], y = wb[i];
+    s[0] += x * x;
+    s[1] += y * y;
+    s[2] += x * y;
+  }
+  block_sum<3>(s);
+  const double al = s[0], be = s[1], ga = s[2];
+  const double floor2 = floor_rel * fro2[0];
+  if (!(al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return;
+  // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0, makes the
+  // rotated rows orthogonal: (c wa - s wb) . (s wa + c wb) = 0
+  const double zeta = (be - al) / (2.0 * ga);
+  const double az = fabs(zeta);
+  const double t = copysign(1.0 / (az + (az < 1e150 ? sqrt(1.0 + az * az) : az)), zeta);
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double sn = c * t;
+  for (int i = threadIdx.x; i < len; i += kThreads) {
+    const double x = wa[i], y = wb[i];
+    wa[i] = c * x - sn * y;
+    wb[i] = sn * x + c * y;
+  }
+  double* qa = Q + (size_t)pr.x * m;
+  double* qb = Q + (size_t)pr.y * m;
+  for (int i = threadIdx.x; i < m; i += kThreads) {
+    const double x = qa[i], y = qb[i];
+    qa[i] = c * x - sn * y;
+    qb[i] = sn * x + c * y;
+  }
+  if (threadIdx.x == 0) atomicAdd(count, 1);
+}
+
+__global__ void k_zero_int(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// One workgroup: sigma_j = ||W_j||, their descending order (ties by index),
+// and k. Outputs: sig[r] = r-th largest value, perm[r] = its row of W,
+// kout[0] = k.
+__global__ void __launch_bounds__(kThreads)
+k_svd_rank(const double* __restrict__ W, int m, int len, double ratio, int kmax,
+           double* __restrict__ sig, int* __restrict__ perm, int* __restrict__ kout) {
+  __shared__ double sg[kSvdMaxM];
+  __shared__ int kc;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  for (int j = wid; j < m; j += kMaxWaves) {
+    const double* w = W + (size_t)j * len;
+    double s = 0.0;
+    for (int i = lane; i < len; i += kWave) s += w[i] * w[i];
+    s = wave_sum(s);
+    // NaN is ordered below every value, so the ranks below always form a
+    // permutation
+    if (lane == 0) sg[j] = s == s ? sqrt(s) : -1.0;
+  }
+  if (threadIdx.x == 0) kc = 0;
+  __syncthreads();
+  double mx = 0.0;
+  for (int j = 0; j < m; ++j) mx = fmax(mx, sg[j]);
+  int cnt = 0;
+  for (int j = threadIdx.x; j < m; j += kThreads) {
+    const double v = sg[j];
+    int r = 0;
+    for (int i = 0; i < m; ++i) r += (sg[i] > v || (sg[i] == v && i < j)) ? 1 : 0;
+    sig[r] = v;
+    perm[r] = j;
+    cnt += (v > 0.0 && v >= ratio * mx) ? 1 : 0;
+  }
+  atomicAdd(&kc, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0) kout[0] = min(kc, kmax);
+}
+
+// The k kept singular vectors in the CG layout (rows x KP, zero-padded):
+// the long side (length len) from the rows of W divided by sigma, the short
+// side (length m) from the rows of Q. lv/sv receive the long/short side.
+__global__ void __launch_bounds__(kThreads)
+k_svd_vectors(const double* __restrict__ W, const double* __restrict__ Q, int m, int len,
+              const double* __restrict__ sig, const int* __restrict__ perm, int k, int KP,
+              double* __restrict__ lv, double* __restrict__ sv) {
+  const size_t NL = (size_t)len * KP, NS = (size_t)m * KP;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < NL + NS; e += stride) {
+    if (e < NL) {
+      const int i = (int)(e / KP), c = (int)(e % KP);
+      lv[e] = c < k ? W[(size_t)perm[c] * len + i] / sig[c] : 0.0;
+    } else {
+      const size_t f = e - NL;
+      const int i = (int)(f / KP), c = (int)(f % KP);
+      sv[f] = c < k ? Q[(size_t)perm[c] * m + i] : 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------------- upsampling by CG
+// One graph side: the unknown rows (not sampled) of S solve
+// L(unknown, unknown) x = -L(unknown, sampled) R column by column. Vectors
+// are c x KP row-major; the sampled rows of r, z, p and q stay zero.
+struct UpSide {
+  const int32_t* rp = nullptr;   // CSR of the full c x c Laplacian (caller's, FP64)
+  const int32_t* ci = nullptr;
+  const double* v = nullptr;
+  const double* dinv = nullptr;  // 1 / L_ii on unknown rows (1 where L_ii <= 0), 0 on sampled rows
+  const int32_t* inv = nullptr;  // position in omega of a sampled row, -1 otherwise
+  const double* R = nullptr;     // sampled values (rho x KP)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double* S = nullptr;           // upsampled vectors (c x KP), the result
+  double* pa = nullptr;          // nb x KP partials (product, norms)
+  double* pb = nullptr;          // nb x 2 KP partials (start, update)
+  double* scal = nullptr;        // per column: rz[2], rr[2], bb, thr (6 KP doubles)
+  int* state = nullptr;          // per column: done, iters (2 KP ints)
+  int c = 0, nb = 0;
+};
+
+// scal layout
+__device__ __forceinline__ double* s_rz(const UpSide& s, int par) { return s.scal + par * kApproxKMax; }
+__device__ __forceinline__ double* s_rr(const UpSide& s, int par) { return s.scal + (2 + par) * kApproxKMax; }
+__device__ __forceinline__ double* s_bb(const UpSide& s) { return s.scal + 4 * kApproxKMax; }
+__device__ __forceinline__ double* s_thr(const UpSide& s) { return s.scal + 5 * kApproxKMax; }
+__device__ __forceinline__ int* s_done(const UpSide& s) { return s.state; }
+__device__ __forceinline__ int* s_iters(const UpSide& s) { return s.state + kApproxKMax; }
+
+// The workgroup's side and its index within that side.
+__device__ __forceinline__ const UpSide& pick(const UpSide& a, const UpSide& b, int& local) {
+  local = (int)blockIdx.x < a.nb ? (int)blockIdx.x : (int)blockIdx.x - a.nb;
+  return (int)blockIdx.x < a.nb ? a : b;
+}
+
+// (L y)_row for the CG layout: sum over the CSR row of v * y[col, c].
+__device__ __forceinline__ double lap_row(const UpSide& s, const double* __restrict__ y, int row,
+                                          int c, int KP) {
+  double acc = 0.0;
+  const int e1 = s.rp[row + 1];
+  for (int e = s.rp[row]; e < e1; ++e) acc += s.v[e] * y[(size_t)s.ci[e] * KP + c];
+  return acc;
+}
+
+// Start: S = R on sampled rows (0 elsewhere), x = 0, b = -(L S) on unknown
+// rows, r = b, z = D^-1 r, p = z. Partials: <r, z>, <r, r>.
+__global__ void __launch_bounds__(kThreads)
+k_up_start(UpSide a, UpSide b2, int KP, int pass) {
+  int lb;
+  const UpSide& s = pick(a, b2, lb);
+  const int c = threadIdx.x & (KP - 1);
+  const int rpb = kThreads / KP;
+  double acc[2] = {0.0, 0.0};
+  for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
+    const size_t e = (size_t)row * KP + c;
+    if (pass == 0) {
+      const int pos = s.inv[row];
+      s.S[e] = pos >= 0 ? s.R[(size_t)pos * KP + c] : 0.0;
+      s.x[e] = 0.0;
+    } else {
+      const double bv = s.inv[row] >= 0 ? 0.0 : -lap_row(s, s.S, row, c, KP);
+      const double zv = s.dinv[row] * bv;
+      s.r[e] = bv;
+      s.z[e] = zv;
+      s.p[e] = zv;
+      s.q[e] = 0.0;
+      acc[0] += bv * zv;
+      acc[1] += bv * bv;
+    }
+  }
+  if (pass == 0) return;
+  __shared__ double red[2][kThreads];
+  red[0][threadIdx.x] = acc[0];
+  red[1][threadIdx.x] = acc[1];
+  for (int st = kThreads / 2; st >= KP; st >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < KP) {
+    s.pb[(size_t)lb * 2 * KP + threadIdx.x] = red[0][threadIdx.x];
+    s.pb[(size_t)lb * 2 * KP + KP + threadIdx.x] = red[1][threadIdx.x];
+  }
+}
+
+// Per-column total over the side's workgroups of partials laid out as NV
+// groups of KP per workgroup (group g).
+__device__ __forceinline__ double col_total(const double* part, int nb, int KP, int g, int NV,
+                                            int c) {
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += part[(size_t)b * NV * KP + g * KP + c];
+  return t;
+}
+
+// One workgroup per side: arm the scalars from the start partials.
+__global__ void __launch_bounds__(kThreads)
+k_up_arm(UpSide a, UpSide b2, int KP, int k, double tol2) {
+  const UpSide& s = blockIdx.x == 0 ? a : b2;
+  const int c = threadIdx.x;
+  if (c >= KP) return;
+  const double rz = col_total(s.pb, s.nb, KP, 0, 2, c), rr = col_total(s.pb, s.nb, KP, 1, 2, c);
+  s_rz(s, 0)[c] = s_rz(s, 1)[c] = rz;
+  s_rr(s, 0)[c] = s_rr(s, 1)[c] = rr;
+  s_bb(s)[c] = rr;
+  s_thr(s)[c] = tol2 * rr;
+  s_iters(s)[c] = 0;
+  // columns past k, and columns with a zero right-hand side (x = 0), are done
+  s_done(s)[c] = (c >= k || !(rr > 0.0)) ? 1 : (bad(rr) || bad(rz) ? 3 : 0);
+}
+
+// q = (L p) on unknown rows; partials <p, q>.
+__global__ void __launch_bounds__(kThreads)
+k_up_apply(UpSide a, UpSide b2, int KP) {
+  int lb;
+  const UpSide& s = pick(a, b2, lb);
+  const int c = threadIdx.x & (KP - 1);
+  const int rpb = kThreads / KP;
+  const bool live = s_done(s)[c] == 0;
+  double acc = 0.0;
+  if (live) {
+    for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
+      if (s.inv[row] >= 0) continue;  // sampled row: q stays 0
+      const size_t e = (size_t)row * KP + c;
+      const double qv = lap_row(s, s.p, row, c, KP);
+      s.q[e] = qv;
+      acc += s.p[e] * qv;
+    }
+  }
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = acc;
+  column_tree(red, KP);
+  if ((int)threadIdx.x < KP) s.pa[(size_t)lb * KP + threadIdx.x] = red[threadIdx.x];
+}
+
+// alpha = <r, z> / <p, q>; x += alpha p; r -= alpha q; z = D^-1 r; partials
+// <r, z>, <r, r>. A column whose <r, r> is at most its threshold is marked
+// done here, where every workgroup reads the same value.
+__global__ void __launch_bounds__(kThreads)
+k_up_update(UpSide a, UpSide b2, int KP, int par) {
+  int lb;
+  const UpSide& s = pick(a, b2, lb);
+  const int c = threadIdx.x & (KP - 1);
+  const int rpb = kThreads / KP;
+  const bool lead = lb == 0 && (int)threadIdx.x < KP;
+  bool live = s_done(s)[c] == 0;
+  double alpha = 0.0;
+  if (live) {
+    const double rr = s_rr(s, par)[c];
+    if (rr <= s_thr(s)[c]) {
+      if (lead) s_done(s)[c] = 1;
+      live = false;
+    } else {
+      const double pq = col_total(s.pa, s.nb, KP, 0, 1, c);
+      if (bad(pq) || !(pq > 0.0)) {
+        if (lead) s_done(s)[c] = bad(pq) ? 3 : 2;
+        live = false;
+      } else {
+        alpha = s_rz(s, par)[c] / pq;
+      }
+    }
+  }
+  double acc[2] = {0.0, 0.0};
+  if (live) {
+    for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
+      if (s.inv[row] >= 0) continue;
+      const size_t e = (size_t)row * KP + c;
+      s.x[e] += alpha * s.p[e];
+      const double rv = s.r[e] - alpha * s.q[e];
+      const double zv = s.dinv[row] * rv;
+      s.r[e] = rv;
+      s.z[e] = zv;
+      acc[0] += rv * zv;
+      acc[1] += rv * rv;
+    }
+  }
+  __shared__ double red[2][kThreads];
+  red[0][threadIdx.x] = acc[0];
+  red[1][threadIdx.x] = acc[1];
+  for (int st = kThreads / 2; st >= KP; st >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < KP) {
+    // written for every column: the p-update reads them only for live ones
+    s.pb[(size_t)lb * 2 * KP + threadIdx.x] = red[0][threadIdx.x];
+    s.pb[(size_t)lb * 2 * KP + KP + threadIdx.x] = red[1][threadIdx.x];
+  }
+}
+
+// beta = <r, z>_new / <r, z>; p = z + beta p; the new scalars go to the
+// other parity.
+__global__ void __launch_bounds__(kThreads)
+k_up_pupdate(UpSide a, UpSide b2, int KP, int par) {
+  int lb;
+  const UpSide& s = pick(a, b2, lb);
+  const int c = threadIdx.x & (KP - 1);
+  const int rpb = kThreads / KP;
+  const bool lead = lb == 0 && (int)threadIdx.x < KP;
+  if (s_done(s)[c] != 0) return;  // uniform per column; no barrier below
+  const double rz_new = col_total(s.pb, s.nb, KP, 0, 2, c);
+  const double rr_new = col_total(s.pb, s.nb, KP, 1, 2, c);
+  if (bad(rz_new) || bad(rr_new)) {
+    if (lead) s_done(s)[c] = 3;
+    return;
+  }
+  const double beta = rz_new / s_rz(s, par)[c];
+  if (lead) {
+    s_rz(s, par ^ 1)[c] = rz_new;
+    s_rr(s, par ^ 1)[c] = rr_new;
+    s_iters(s)[c] += 1;
+  }
+  for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
+    if (s.inv[row] >= 0) continue;
+    const size_t e = (size_t)row * KP + c;
+    s.p[e] = s.z[e] + beta * s.p[e];
+  }
+}
+
+// S = x on unknown rows (the sampled rows already hold R); partials of the
+// column norms ||S_c||^2.
+__global__ void __launch_bounds__(kThreads)
+k_up_finish(UpSide a, UpSide b2, int KP) {
+  int lb;
+  const UpSide& s = pick(a, b2, lb);
+  const int c = threadIdx.x & (KP - 1);
+  const int rpb = kThreads / KP;
+  double acc = 0.0;
+  for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
+    const size_t e = (size_t)row * KP + c;
+    double v = s.S[e];
+    if (s.inv[row] < 0) {
+      v = s.x[e];
+      s.S[e] = v;
+    }
+    acc += v * v;
+  }
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = acc;
+  column_tree(red, KP);
+  if ((int)threadIdx.x < KP) s.pa[(size_t)lb * KP + threadIdx.x] = red[threadIdx.x];
+}
+
+// One workgroup: w_c = scale sigma_c / (||u_c|| ||v_c||) for c < k, 0 past
+// k (U from side a, V from side b). Also the relative residuals.
+__global__ void __launch_bounds__(kThreads)
+k_up_weights(UpSide a, UpSide b2, int KP, int k, const double* __restrict__ sig, double scale,
+             double* __restrict__ w, double* __restrict__ rel) {
+  const int c = threadIdx.x;
+  if (c >= KP) return;
+  const double nu = sqrt(col_total(a.pa, a.nb, KP, 0, 1, c));
+  const double nv = sqrt(col_total(b2.pa, b2.nb, KP, 0, 1, c));
+  w[c] = c < k ? scale * sig[c] / (nu * nv) : 0.0;
+  // final recursive residuals (the parity of the last update is not known
+  // here, so the smaller of the two is taken; both are <= the threshold
+  // once a column has converged)
+  for (int side = 0; side < 2; ++side) {
+    const UpSide& s = side == 0 ? a : b2;
+    const double bb = s_bb(s)[c];
+    const double rr = fmin(s_rr(s, 0)[c], s_rr(s, 1)[c]);
+    rel[side * KP + c] = c < k && bb > 0.0 ? sqrt(rr / bb) : 0.0;
+  }
+}
+
+// ----------------------------------------------------------- rank-k output
+// X[i, j] = sum_c U[i, c] w_c V[j, c] for i < p, j < n (row-major, leading
+// dimension n, type TO). A workgroup owns a strip of kThreads * VEC
+// columns and a range of rows: it keeps w * V of its columns in registers
+// and streams the rows, reading each U row (KP values, the same for the
+// whole workgroup) once. VEC-wide stores need n % VEC == 0.
+template <typename TO, int KPT, int VEC>
+__global__ void __launch_bounds__(kThreads)
+k_rank_k(TO* __restrict__ X, const double* __restrict__ U, const double* __restrict__ V,
+         const double* __restrict__ w, int p, int n, int KP, int rows_per, int nstrips) {
+  const int strip = blockIdx.x % nstrips;
+  const int rg = blockIdx.x / nstrips;
+  const int j0 = (strip * kThreads + (int)threadIdx.x) * VEC;
+  const int i0 = rg * rows_per;
+  const int i1 = min(p, i0 + rows_per);
+  double vw[VEC][KPT];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q)
+#pragma unroll
+    for (int c = 0; c < KPT; ++c)
+      vw[q][c] = (j0 + q < n && c < KP) ? V[(size_t)(j0 + q) * KP + c] * w[c] : 0.0;
+  if (j0 >= n) return;
+  for (int i = i0; i < i1; ++i) {
+    const double* u = U + (size_t)i * KP;
+    double uc[KPT];
+#pragma unroll
+    for (int c = 0; c < KPT; ++c) uc[c] = c < KP ? u[c] : 0.0;
+    TO out[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < KPT; ++c) acc += uc[c] * vw[q][c];
+      out[q] = (TO)acc;
+    }
+    TO* dst = X + (size_t)i * n + j0;
+    if (VEC > 1 && j0 + VEC <= n) {
+      vst<TO, VEC>(dst, out);
+    } else {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q)
+        if (j0 + q < n) dst[q] = out[q];
+    }
+  }
+}
+
+template <typename TO>
+__global__ void __launch_bounds__(kThreads) k_fill_zero(TO* __restrict__ X, size_t N) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) X[e] = TO(0);
+}
+
+// ------------------------------------------------------------------- host
+int pow2_at_least(int k) {
+  int v = 1;
+  while (v < k) v <<= 1;
+  return v;
+}
+
+// Round-robin (circle) schedule: m players (plus an idle slot when m is
+// odd), M - 1 rounds of M / 2 disjoint pairs, every pair met once a sweep.
+std::vector<int2> round_robin(int m) {
+  const int M = m + (m & 1);
+  std::vector<int2> t;
+  if (M < 2) return t;
+  t.reserve((size_t)(M - 1) * (M / 2));
+  for (int r = 0; r < M - 1; ++r) {
+    auto at = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + r) % (M - 1)) + 1; };
+    for (int k = 0; k < M / 2; ++k) t.push_back(make_int2(at(k), at(M - 1 - k)));
+  }
+  return t;
+}
+
+template <int KPT, typename TO>
+hipError_t launch_rank_k_t(hipStream_t st, TO* X, const double* U, const double* V,
+                           const double* w, int p, int n, int KP) {
+  // 16-byte stores where the rows allow it; small KP leaves room for more
+  // columns per thread
+  constexpr int VW = KPT <= 16 ? (int)(16 / sizeof(TO)) : 1;  // registers: VW * KPT doubles
+  const bool vec = VW > 1 && n % VW == 0;
+  const int cols = kThreads * (vec ? VW : 1);
+  const int nstrips = (n + cols - 1) / cols;
+  // about 2048 workgroups, at least 8 rows each
+  const int rows_per = std::max(8, (int)(((int64_t)p * nstrips + 2047) / 2048));
+  const int ngroups = (p + rows_per - 1) / rows_per;
+  const int grid = nstrips * ngroups;
+  if (vec)
+    k_rank_k<TO, KPT, VW><<<grid, kThreads, 0, st>>>(X, U, V, w, p, n, KP, rows_per, nstrips);
+  else
+    k_rank_k<TO, KPT, 1><<<grid, kThreads, 0, st>>>(X, U, V, w, p, n, KP, rows_per, nstrips);
+  return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_rank_k(hipStream_t st, TO* X, const double* U, const double* V, const double* w,
+                         int p, int n, int KP) {
+  switch (KP) {
+    case 1: return launch_rank_k_t<1>(st, X, U, V, w, p, n, KP);
+    case 2: return launch_rank_k_t<2>(st, X, U, V, w, p, n, KP);
+    case 4: return launch_rank_k_t<4>(st, X, U, V, w, p, n, KP);
+    case 8: return launch_rank_k_t<8>(st, X, U, V, w, p, n, KP);
+    case 16: return launch_rank_k_t<16>(st, X, U, V, w, p, n, KP);
+    case 32: return launch_rank_k_t<32>(st, X, U, V, w, p, n, KP);
+    case 64: return launch_rank_k_t<64>(st, X, U, V, w, p, n, KP);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+struct SideHost {
+  std::vector<int32_t> inv;
+  std::vector<double> dinv;
+};
+
+// Host tables of one side: the inverse of omega and the Jacobi
+// preconditioner of the unknown rows.
+SideHost side_tables(const HostCsr& L, const std::vector<int32_t>& omega) {
+  SideHost s;
+  s.inv.assign((size_t)L.n, -1);
+  for (size_t a = 0; a < omega.size(); ++a) s.inv[(size_t)omega[a]] = (int32_t)a;
+  s.dinv.assign((size_t)L.n, 0.0);
+  for (int64_t i = 0; i < L.n; ++i) {
+    if (s.inv[(size_t)i] >= 0) continue;
+    double d = 0.0;
+    for (int32_t e = L.rp[(size_t)i]; e < L.rp[(size_t)i + 1]; ++e)
+      if (L.ci[(size_t)e] == i) d += L.v[(size_t)e];
+    s.dinv[(size_t)i] = d > 0.0 ? 1.0 / d : 1.0;
+  }
+  return s;
+}
+
+cpca_status fetch_indices(const char* name, const int32_t* idx, int64_t count, int64_t dim,
+                          std::vector<int32_t>& out) {
+  std::vector<uint8_t> mask;
+  STCHK(fetch_index_set(name, idx, count, dim, mask));
+  out.resize((size_t)count);
+  HIPCHK(hipMemcpy(out.data(), idx, sizeof(int32_t) * count, hipMemcpyDefault));
+  return CPCA_OK;
+}
+
+template <typename T>
+cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
+                       const int32_t* om_r, const int32_t* om_c, int64_t p, int64_t n,
+                       const cpca_csr* Lr, const cpca_csr* Lc, double delta, double ratio,
+                       int32_t k_max, double tol, int32_t max_iter, T* X_out, double* sigma_out,
+                       cpca_approx_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipStreamSynchronize(h->stream));  // inputs may still be in flight
+  HostCsr hLr, hLc;
+  STCHK(fetch_csr("Lr", Lr, hLr));
+  STCHK(fetch_csr("Lc", Lc, hLc));
+  std::vector<int32_t> wr, wc;
+  STCHK(fetch_indices("omega_r", om_r, rho_r, p, wr));
+  STCHK(fetch_indices("omega_c", om_c, rho_c, n, wc));
+  const SideHost sr = side_tables(hLr, wr), sc = side_tables(hLc, wc);
+
+  const int trans = rho_r >= rho_c ? 1 : 0;
+  const int m = (int)std::min(rho_r, rho_c);
+  const int len = (int)std::max(rho_r, rho_c);
+  if (m > kSvdMaxM) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "approx_decode: min(rho_r, rho_c) = %d exceeds %d", m, kSvdMaxM);
+    return fail(CPCA_EINVAL, buf);
+  }
+  const std::vector<int2> rr_tab = round_robin(m);
+  const int M = m + (m & 1);
+  const int npair = M / 2;
+  const int KPmax = pow2_at_least(k_max);
+
+  // ---- workspace
+  double *W = nullptr, *Q = nullptr, *sig = nullptr, *lv = nullptr, *sv = nullptr, *wts = nullptr,
+         *rel = nullptr, *fro2 = nullptr;
+  int2* pairs = nullptr;
+  int *cnt = nullptr, *perm = nullptr, *kdev = nullptr, *inv_r = nullptr, *inv_c = nullptr;
+  double *dinv_r = nullptr, *dinv_c = nullptr;
+  UpSide A, B;  // A: rows (L_r), B: columns (L_c)
+  auto grid_for = [&](int64_t c) {
+    const int rpb = kThreads / KPmax;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kUpMaxBlocks, (c + rpb - 1) / rpb));
+  };
+  auto layout = [&](Arena& a) {
+    W = a.take<double>((size_t)m * len);
+    Q = a.take<double>((size_t)m * m);
+    pairs = a.take<int2>(std::max<size_t>(rr_tab.size(), 1));
+    cnt = a.take<int>(1);
+    fro2 = a.take<double>(1);
+    sig = a.take<double>((size_t)m);
+    perm = a.take<int>((size_t)m);
+    kdev = a.take<int>(1);
+    lv = a.take<double>((size_t)len * KPmax);
+    sv = a.take<double>((size_t)m * KPmax);
+    wts = a.take<double>(kApproxKMax);
+    rel = a.take<double>(2 * kApproxKMax);
+    inv_r = a.take<int>((size_t)p);
+    inv_c = a.take<int>((size_t)n);
+    dinv_r = a.take<double>((size_t)p);
+    dinv_c = a.take<double>((size_t)n);
+    for (int side = 0; side < 2; ++side) {
+      UpSide& s = side == 0 ? A : B;
+      const int64_t c = side == 0 ? p : n;
+      s.c = (int)c;
+      s.nb = grid_for(c);
+      const size_t N = (size_t)c * KPmax;
+      s.x = a.take<double>(N);
+      s.r = a.take<double>(N);
+      s.z = a.take<double>(N);
+      s.p = a.take<double>(N);
+      s.q = a.take<double>(N);
+      s.S = a.take<double>(N);
+      s.pa = a.take<double>((size_t)s.nb * KPmax);
+      s.pb = a.take<double>((size_t)s.nb * 2 * KPmax);
+      s.scal = a.take<double>(6 * kApproxKMax);
+      s.state = a.take<int>(2 * kApproxKMax);
+    }
+  };
+  {
+    Arena a;
+    layout(a);
+    STCHK(ensure_ws(h, a.off));
+  }
+  Arena ar;
+  ar.base = h->ws;
+  layout(ar);
+  hipStream_t st = h->stream;
+  if (!rr_tab.empty())
+    HIPCHK(hipMemcpyAsync(pairs, rr_tab.data(), sizeof(int2) * rr_tab.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(inv_r, sr.inv.data(), sizeof(int) * p, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(inv_c, sc.inv.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dinv_r, sr.dinv.data(), sizeof(double) * p, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dinv_c, sc.dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+
+  // ---- 1. one-sided Jacobi SVD
+  k_jac_load<T><<<vec_grid((size_t)rho_r * rho_c), kThreads, 0, st>>>(W, Q, Xt, (int)rho_r,
+                                                                       (int)rho_c, trans, m);
+  LAUNCHCHK();
+  k_jac_fro<<<1, kThreads, 0, st>>>(W, (size_t)m * len, fro2);
+  LAUNCHCHK();
+  // rotations stop once the normalised inner product of every pair is
+  // within rounding of the dot products (len units in the last place); rows
+  // below len ulps of ||X~||_F count as zero
+  const double jac_tol = 2.220446049250313e-16 * std::max(len, 16);
+  const double floor_rel = jac_tol * jac_tol;
+  int sweeps = 0;
+  bool svd_ok = true;
+  if (npair > 0 && m > 1) {
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev;
+    hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+      k_zero_int<<<1, 64, 0, cs>>>(cnt, 1);
+      for (int r = 0; r < M - 1; ++r)
+        k_jac_round<<<npair, kThreads, 0, cs>>>(W, Q, m, len, pairs + (size_t)r * npair, jac_tol,
+                                                fro2, floor_rel, cnt);
+      err = hipGetLastError();
+      hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      if (err == hipSuccess) err = e2;
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (err == hipSuccess) err = hipEventRecord(ev, st);
+    if (err == hipSuccess) err = hipStreamWaitEvent(cs, ev, 0);
+    int hc = 1;
+    while (err == hipSuccess && sweeps < kMaxSweeps) {
+      err = hipGraphLaunch(exec, cs);
+      if (err == hipSuccess) err = hipMemcpyAsync(&hc, cnt, sizeof(int), hipMemcpyDeviceToHost, cs);
+      if (err == hipSuccess) err = hipStreamSynchronize(cs);
+      ++sweeps;
+      if (err != hipSuccess || hc == 0) break;
+    }
+    if (err == hipSuccess) err = hipEventRecord(ev, cs);
+    if (err == hipSuccess) err = hipStreamWaitEvent(st, ev, 0);
+    const hipError_t e3 = hipStreamSynchronize(cs);
+    if (err == hipSuccess) err = e3;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cs);
+    if (err != hipSuccess) return fail(CPCA_EHIP, std::string("approx_decode SVD: ") + hipGetErrorString(err));
+    svd_ok = hc == 0;
+  }
+  // ---- 2. order of the singular values and k
+  k_svd_rank<<<1, kThreads, 0, st>>>(W, m, len, ratio, k_max, sig, perm, kdev);
+  LAUNCHCHK();
+  std::vector<double> hsig((size_t)m);
+  int k = 0;
+  HIPCHK(hipMemcpyAsync(hsig.data(), sig, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&k, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (sigma_out) std::copy(hsig.begin(), hsig.end(), sigma_out);
+  auto finish_info = [&](cpca_status s, int it_r, int it_c, double rel_r, double rel_c) {
+    if (!info) return;
+    info->k = k;
+    info->svd_sweeps = sweeps;
+    info->iters_r = it_r;
+    info->iters_c = it_c;
+    info->status = (int32_t)s;
+    info->reserved = 0;
+    info->rel_residual_r = rel_r;
+    info->rel_residual_c = rel_c;
+    info->scale = std::sqrt((double)n * (double)p / ((double)rho_r * (double)rho_c * (1.0 - delta)));
+    info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
+  const size_t NX = (size_t)p * n;
+  if (k == 0) {
+    k_fill_zero<T><<<vec_grid(NX), kThreads, 0, st>>>(X_out, NX);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+    const cpca_status s = svd_ok ? CPCA_OK : CPCA_ENOCONV;
+    finish_info(s, 0, 0, 0.0, 0.0);
+    if (!svd_ok) return fail(CPCA_ENOCONV, "approx_decode: Jacobi SVD did not converge");
+    return CPCA_OK;
+  }
+  const int KP = pow2_at_least(k);
+  // the CG layout was sized for KPmax; smaller k uses the same blocks
+  for (int side = 0; side < 2; ++side) {
+    UpSide& s = side == 0 ? A : B;
+    const cpca_csr* L = side == 0 ? Lr : Lc;
+    s.rp = L->rowptr;
+    s.ci = L->colind;
+    s.v = L->vals;
+    s.inv = side == 0 ? inv_r : inv_c;
+    s.dinv = side == 0 ? dinv_r : dinv_c;
+  }
+  // long side = columns of W's rows: left vectors when trans, else right
+  A.R = trans ? lv : sv;
+  B.R = trans ? sv : lv;
+  k_svd_vectors<<<vec_grid((size_t)(len + m) * KP), kThreads, 0, st>>>(W, Q, m, len, sig, perm, k, KP,
+                                                                       lv, sv);
+  LAUNCHCHK();
+
+  // ---- 3. upsampling, both graphs in the same launches
+  const int gup = A.nb + B.nb;
+  k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 0);
+  LAUNCHCHK();
+  k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 1);
+  LAUNCHCHK();
+  k_up_arm<<<2, kThreads, 0, st>>>(A, B, KP, k, tol * tol);
+  LAUNCHCHK();
+  std::vector<int> hstate(2 * 2 * kApproxKMax);
+  auto read_state = [&]() -> cpca_status {
+    HIPCHK(hipMemcpyAsync(hstate.data(), A.state, sizeof(int) * 2 * kApproxKMax, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hstate.data() + 2 * kApproxKMax, B.state, sizeof(int) * 2 * kApproxKMax,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CPCA_OK;
+  };
+  auto all_done = [&]() {
+    for (int side = 0; side < 2; ++side)
+      for (int c = 0; c < k; ++c)
+        if (hstate[(size_t)side * 2 * kApproxKMax + c] == 0) return false;
+    return true;
+  };
+  STCHK(read_state());
+  {
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipEvent_t ev;
+    hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    auto enqueue = [&](hipStream_t s2, int par) -> hipError_t {
+      k_up_apply<<<gup, kThreads, 0, s2>>>(A, B, KP);
+      k_up_update<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
+      k_up_pupdate<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
+      return hipGetLastError();
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (err == hipSuccess && max_iter >= kUpChunk) {
+      err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      for (int j = 0; j < kUpChunk && err == hipSuccess; ++j) err = enqueue(cs, j & 1);
+      const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      if (err == hipSuccess) err = e2;
+      if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    }
+    if (err == hipSuccess) err = hipEventRecord(ev, st);
+    if (err == hipSuccess) err = hipStreamWaitEvent(cs, ev, 0);
+    int it = 0;
+    cpca_status sst = CPCA_OK;
+    while (err == hipSuccess && it < max_iter && !all_done()) {
+      if (exec && it + kUpChunk <= max_iter) {
+        err = hipGraphLaunch(exec, cs);
+        it += kUpChunk;
+      } else {
+        err = enqueue(cs, it & 1);
+        it += 1;
+      }
+      if (err == hipSuccess) err = hipEventRecord(ev, cs);
+      if (err == hipSuccess) err = hipStreamWaitEvent(st, ev, 0);
+      if (err != hipSuccess) break;
+      if ((sst = read_state()) != CPCA_OK) break;
+    }
+    const hipError_t e3 = hipStreamSynchronize(cs);
+    if (err == hipSuccess) err = e3;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cs);
+    if (err != hipSuccess) return fail(CPCA_EHIP, std::string("approx_decode CG: ") + hipGetErrorString(err));
+    STCHK(sst);
+  }
+  // ---- 4.-6. norms, weights, X = U diag(w) V^T
+  k_up_finish<<<gup, kThreads, 0, st>>>(A, B, KP);
+  LAUNCHCHK();
+  const double scale = std::sqrt((double)n * (double)p / ((double)rho_r * (double)rho_c * (1.0 - delta)));
+  k_up_weights<<<1, kThreads, 0, st>>>(A, B, KP, k, sig, scale, wts, rel);
+  LAUNCHCHK();
+  HIPCHK(launch_rank_k<T>(st, X_out, A.S, B.S, wts, (int)p, (int)n, KP));
+  std::vector<double> hrel(2 * (size_t)KP);
+  HIPCHK(hipMemcpyAsync(hrel.data(), rel, sizeof(double) * 2 * KP, hipMemcpyDeviceToHost, st));
+  STCHK(read_state());
+  int it_r = 0, it_c = 0, worst = 0;
+  double rel_r = 0.0, rel_c = 0.0;
+  for (int c = 0; c < k; ++c) {
+    const int dr = hstate[(size_t)c], dc = hstate[(size_t)2 * kApproxKMax + c];
+    it_r = std::max(it_r, hstate[(size_t)kApproxKMax + c]);
+    it_c = std::max(it_c, hstate[(size_t)3 * kApproxKMax + c]);
+    rel_r = std::max(rel_r, hrel[(size_t)c]);
+    rel_c = std::max(rel_c, hrel[(size_t)KP + c]);
+    for (int d : {dr, dc})
+      if (d != 1) worst = std::max(worst, d == 0 ? 1 : d);  // 1: not converged
+  }
+  cpca_status s = CPCA_OK;
+  if (worst == 3) s = CPCA_ENAN;
+  else if (worst == 2) s = CPCA_ENOTSPD;
+  else if (worst == 1 || !svd_ok) s = CPCA_ENOCONV;
+  finish_info(s, it_r, it_c, rel_r, rel_c);
+  if (s == CPCA_ENAN) return fail(s, "approx_decode: NaN/Inf in the upsampling CG");
+  if (s == CPCA_ENOTSPD) return fail(s, "approx_decode: upsampling CG breakdown (p^T A p <= 0)");
+  if (s == CPCA_ENOCONV)
+    return fail(s, svd_ok ? "approx_decode: upsampling CG reached max_iter"
+                          : "approx_decode: Jacobi SVD did not converge");
+  return CPCA_OK;
+}
+
+}  // namespace
+
+extern "C" cpca_status cpca_approx_decode(cpca_handle h, cpca_mode mode, const void* Xtil,
+                                          int64_t rho_r, int64_t rho_c, const int32_t* omega_r,
+                                          const int32_t* omega_c, int64_t p, int64_t n,
+                                          const cpca_csr* Lr, const cpca_csr* Lc, double delta,
+                                          double sigma_ratio, int32_t k_max, double tol,
+                                          int32_t max_iter, void* X_out, double* sigma_out,
+                                          cpca_approx_info* info) {
+  clear_error();
+  STCHK(check_approx_args(mode, rho_r, rho_c, omega_r, omega_c, p, n, Lr, Lc, delta, sigma_ratio,
+                          k_max, tol, max_iter));
+  if (!Xtil || !X_out) return fail(CPCA_EINVAL, "approx_decode: null data pointer");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  if (mode == CPCA_FP64)
+    return run_approx<double>(h, static_cast<const double*>(Xtil), rho_r, rho_c, omega_r, omega_c,
+                              p, n, Lr, Lc, delta, sigma_ratio, k_max, tol, max_iter,
+                              static_cast<double*>(X_out), sigma_out, info);
+  return run_approx<float>(h, static_cast<const float*>(Xtil), rho_r, rho_c, omega_r, omega_c, p,
+                           n, Lr, Lc, delta, sigma_ratio, k_max, tol, max_iter,
+                           static_cast<float*>(X_out), sigma_out, info);
+}

@@ -180,6 +180,31 @@ cpca_status check_decode_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
   return CPCA_OK;
 }
 
+cpca_status check_approx_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
+                              const int32_t* om_r, const int32_t* om_c, int64_t p, int64_t n,
+                              const cpca_csr* Lr, const cpca_csr* Lc, double delta,
+                              double ratio, int32_t k_max, double tol, int32_t max_iter) {
+  cpca_status st;
+  if ((st = check_mode(mode))) return st;
+  if ((st = check_dims("X", p, n))) return st;
+  if ((unsigned long long)p * (unsigned long long)n > (1ull << 40))
+    return fail(CPCA_EINVAL, "approx_decode: p * n too large");
+  if ((st = check_dims("Xtil", rho_r, rho_c))) return st;
+  if (rho_r > p || rho_c > n)
+    return fail(CPCA_EINVAL, "approx_decode: more samples than rows/columns");
+  if (!om_r || !om_c) return fail(CPCA_EINVAL, "approx_decode: null index set");
+  if ((st = check_csr_shape("Lr", Lr, p))) return st;
+  if ((st = check_csr_shape("Lc", Lc, n))) return st;
+  if (!std::isfinite(delta) || delta < 0 || !(delta < 1))
+    return fail(CPCA_EINVAL, "approx_decode: delta must be in [0, 1)");
+  if (!std::isfinite(ratio) || ratio < 0 || ratio > 1)
+    return fail(CPCA_EINVAL, "approx_decode: sigma_ratio must be in [0, 1]");
+  if (k_max < 1 || k_max > 64) return fail(CPCA_EINVAL, "approx_decode: k_max must be in [1, 64]");
+  if (!std::isfinite(tol) || !(tol > 0)) return fail(CPCA_EINVAL, "approx_decode: tol must be > 0");
+  if (max_iter < 0) return fail(CPCA_EINVAL, "approx_decode: max_iter < 0");
+  return CPCA_OK;
+}
+
 }  // namespace cpca
 
 extern "C" cpca_status cpca_check_csr_host(int64_t n, int64_t nnz, const int32_t* rowptr,

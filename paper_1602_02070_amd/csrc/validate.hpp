@@ -29,5 +29,9 @@ cpca_status check_decode_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
                               const int32_t* om_r, const int32_t* om_c, int64_t p, int64_t n,
                               const cpca_csr* Lr, const cpca_csr* Lc, double gr, double gc,
                               double tol, int32_t max_iter);
+cpca_status check_approx_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
+                              const int32_t* om_r, const int32_t* om_c, int64_t p, int64_t n,
+                              const cpca_csr* Lr, const cpca_csr* Lc, double delta,
+                              double ratio, int32_t k_max, double tol, int32_t max_iter);
 
 }  // namespace cpca

@@ -121,3 +121,30 @@ def test_entry_points_reject_bad_scalars_before_device_work(lib):
     assert fr(gr=0.0, lr=0.0) == _lib.EINVAL and "null handle" in _lib.last_error()
     assert lib.cpca_create(None, None) == _lib.EINVAL
     assert lib.cpca_destroy(None) == _lib.OK
+
+
+def test_approx_decode_rejects_bad_arguments_before_device_work(lib):
+    info = _lib.CpcaApproxInfo()
+    dummy = ctypes.c_void_p(16)
+    Lr, k1 = _csr(10)
+    Lc, k2 = _csr(20)
+    base = dict(mode=1, rho_r=5, rho_c=6, p=10, n=20, delta=0.0, ratio=0.1, kmax=16, tol=1e-10,
+                it=100)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return lib.cpca_approx_decode(None, a["mode"], dummy, a["rho_r"], a["rho_c"], dummy, dummy,
+                                      a["p"], a["n"], ctypes.byref(Lr), ctypes.byref(Lc),
+                                      a["delta"], a["ratio"], a["kmax"], a["tol"], a["it"], dummy,
+                                      None, ctypes.byref(info))
+
+    cases = [(dict(mode=5), "mode"), (dict(n=0), "size"), (dict(rho_c=21), "samples"),
+             (dict(delta=1.0), "delta"), (dict(delta=-0.1), "delta"),
+             (dict(ratio=1.5), "sigma_ratio"), (dict(ratio=float("nan")), "sigma_ratio"),
+             (dict(kmax=0), "k_max"), (dict(kmax=65), "k_max"), (dict(tol=-1.0), "tol"),
+             (dict(it=-1), "max_iter"), (dict(p=11), "Lr")]
+    for kw, word in cases:
+        assert call(**kw) == _lib.EINVAL, kw
+        assert word in _lib.last_error(), (kw, _lib.last_error())
+    assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
+    assert call(it=0, ratio=0.0, kmax=64) == _lib.EINVAL and "null handle" in _lib.last_error()
