@@ -272,7 +272,8 @@ cpca_status cpca_check_index_set_host(int64_t count, int64_t dim,
  * every launch of the named kernel family. Families: "apply" (the fused
  * two-sided sparse product with the CG epilogue), "update" (the CG x/r
  * update), "fista" (the fused FISTA step), "other" (the fused product with
- * any other epilogue: residual, objective, adjoint dots, plain apply).
+ * any other epilogue: residual, objective, adjoint dots, plain apply),
+ * "rankk" (the rank-k output product of cpca_approx_decode).
  * Enabling resets the counters.
  * cpca_get_profile returns the number of timed launches and their summed
  * duration in milliseconds.

@@ -140,6 +140,60 @@ k_jac_round(double* __restrict__ W, double* __restrict__ Q, int m, int len,
   if (threadIdx.x == 0) atomicAdd(count, 1);
 }
 
+// The same round with both rows of W and of Q held in registers (EPT
+// elements per thread, len <= EPT * kThreads): every load is issued before
+// the first reduction, and the rotation works on the registers.
+template <int EPT>
+__global__ void __launch_bounds__(kThreads)
+k_jac_round_reg(double* __restrict__ W, double* __restrict__ Q, int m, int len,
+                const int2* __restrict__ pairs, double tol, const double* __restrict__ fro2,
+                double floor_rel, int* __restrict__ count) {
+  const int2 pr = pairs[blockIdx.x];
+  if (pr.x >= m || pr.y >= m) return;
+  double* wa = W + (size_t)pr.x * len;
+  double* wb = W + (size_t)pr.y * len;
+  double* qa = Q + (size_t)pr.x * m;
+  double* qb = Q + (size_t)pr.y * m;
+  double xa[EPT], xb[EPT], ya[EPT], yb[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = (int)threadIdx.x + e * kThreads;
+    xa[e] = i < len ? wa[i] : 0.0;
+    xb[e] = i < len ? wb[i] : 0.0;
+    ya[e] = i < m ? qa[i] : 0.0;
+    yb[e] = i < m ? qb[i] : 0.0;
+  }
+  double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    s[0] += xa[e] * xa[e];
+    s[1] += xb[e] * xb[e];
+    s[2] += xa[e] * xb[e];
+  }
+  block_sum<3>(s);
+  const double al = s[0], be = s[1], ga = s[2];
+  const double floor2 = floor_rel * fro2[0];
+  if (!(al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double az = fabs(zeta);
+  const double t = copysign(1.0 / (az + (az < 1e150 ? sqrt(1.0 + az * az) : az)), zeta);
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double sn = c * t;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = (int)threadIdx.x + e * kThreads;
+    if (i < len) {
+      wa[i] = c * xa[e] - sn * xb[e];
+      wb[i] = sn * xa[e] + c * xb[e];
+    }
+    if (i < m) {
+      qa[i] = c * ya[e] - sn * yb[e];
+      qb[i] = sn * ya[e] + c * yb[e];
+    }
+  }
+  if (threadIdx.x == 0) atomicAdd(count, 1);
+}
+
 __global__ void k_zero_int(int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -289,12 +343,19 @@ k_up_start(UpSide a, UpSide b2, int KP, int pass) {
   }
 }
 
-// Per-column total over the side's workgroups of partials laid out as NV
-// groups of KP per workgroup (group g).
-__device__ __forceinline__ double col_total(const double* part, int nb, int KP, int g, int NV,
-                                            int c) {
-  double t = 0.0;
-  for (int b = 0; b < nb; ++b) t += part[(size_t)b * NV * KP + g * KP + c];
+// Per-column totals over the side's workgroups of partials laid out as NV
+// groups of KP per workgroup (group g), summed by the whole workgroup in a
+// fixed order (strided loads, then the LDS tree). Every thread receives the
+// total of its column t % KP; all threads of the workgroup must call it.
+__device__ double col_total(const double* part, int nb, int KP, int g, int NV, double* red) {
+  const int c = threadIdx.x & (KP - 1);
+  const int rpb = kThreads / KP;
+  double s = 0.0;
+  for (int b = (int)threadIdx.x / KP; b < nb; b += rpb) s += part[(size_t)b * NV * KP + g * KP + c];
+  red[threadIdx.x] = s;
+  column_tree(red, KP);
+  const double t = red[c];
+  __syncthreads();  // red is reused by the caller
   return t;
 }
 
@@ -302,9 +363,11 @@ __device__ __forceinline__ double col_total(const double* part, int nb, int KP, 
 __global__ void __launch_bounds__(kThreads)
 k_up_arm(UpSide a, UpSide b2, int KP, int k, double tol2) {
   const UpSide& s = blockIdx.x == 0 ? a : b2;
+  __shared__ double red[kThreads];
+  const double rz = col_total(s.pb, s.nb, KP, 0, 2, red);
+  const double rr = col_total(s.pb, s.nb, KP, 1, 2, red);
   const int c = threadIdx.x;
   if (c >= KP) return;
-  const double rz = col_total(s.pb, s.nb, KP, 0, 2, c), rr = col_total(s.pb, s.nb, KP, 1, 2, c);
   s_rz(s, 0)[c] = s_rz(s, 1)[c] = rz;
   s_rr(s, 0)[c] = s_rr(s, 1)[c] = rr;
   s_bb(s)[c] = rr;
@@ -348,6 +411,8 @@ k_up_update(UpSide a, UpSide b2, int KP, int par) {
   const int c = threadIdx.x & (KP - 1);
   const int rpb = kThreads / KP;
   const bool lead = lb == 0 && (int)threadIdx.x < KP;
+  __shared__ double red[2][kThreads];
+  const double pq = col_total(s.pa, s.nb, KP, 0, 1, red[0]);
   bool live = s_done(s)[c] == 0;
   double alpha = 0.0;
   if (live) {
@@ -356,7 +421,6 @@ k_up_update(UpSide a, UpSide b2, int KP, int par) {
       if (lead) s_done(s)[c] = 1;
       live = false;
     } else {
-      const double pq = col_total(s.pa, s.nb, KP, 0, 1, c);
       if (bad(pq) || !(pq > 0.0)) {
         if (lead) s_done(s)[c] = bad(pq) ? 3 : 2;
         live = false;
@@ -379,7 +443,6 @@ k_up_update(UpSide a, UpSide b2, int KP, int par) {
       acc[1] += rv * rv;
     }
   }
-  __shared__ double red[2][kThreads];
   red[0][threadIdx.x] = acc[0];
   red[1][threadIdx.x] = acc[1];
   for (int st = kThreads / 2; st >= KP; st >>= 1) {
@@ -406,9 +469,10 @@ k_up_pupdate(UpSide a, UpSide b2, int KP, int par) {
   const int c = threadIdx.x & (KP - 1);
   const int rpb = kThreads / KP;
   const bool lead = lb == 0 && (int)threadIdx.x < KP;
-  if (s_done(s)[c] != 0) return;  // uniform per column; no barrier below
-  const double rz_new = col_total(s.pb, s.nb, KP, 0, 2, c);
-  const double rr_new = col_total(s.pb, s.nb, KP, 1, 2, c);
+  __shared__ double red[kThreads];
+  const double rz_new = col_total(s.pb, s.nb, KP, 0, 2, red);
+  const double rr_new = col_total(s.pb, s.nb, KP, 1, 2, red);
+  if (s_done(s)[c] != 0) return;  // no barrier below
   if (bad(rz_new) || bad(rr_new)) {
     if (lead) s_done(s)[c] = 3;
     return;
@@ -455,10 +519,11 @@ k_up_finish(UpSide a, UpSide b2, int KP) {
 __global__ void __launch_bounds__(kThreads)
 k_up_weights(UpSide a, UpSide b2, int KP, int k, const double* __restrict__ sig, double scale,
              double* __restrict__ w, double* __restrict__ rel) {
+  __shared__ double red[kThreads];
+  const double nu = sqrt(col_total(a.pa, a.nb, KP, 0, 1, red));
+  const double nv = sqrt(col_total(b2.pa, b2.nb, KP, 0, 1, red));
   const int c = threadIdx.x;
   if (c >= KP) return;
-  const double nu = sqrt(col_total(a.pa, a.nb, KP, 0, 1, c));
-  const double nv = sqrt(col_total(b2.pa, b2.nb, KP, 0, 1, c));
   w[c] = c < k ? scale * sig[c] / (nu * nv) : 0.0;
   // final recursive residuals (the parity of the last update is not known
   // here, so the smaller of the two is taken; both are <= the threshold
@@ -646,10 +711,7 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
   int *cnt = nullptr, *perm = nullptr, *kdev = nullptr, *inv_r = nullptr, *inv_c = nullptr;
   double *dinv_r = nullptr, *dinv_c = nullptr;
   UpSide A, B;  // A: rows (L_r), B: columns (L_c)
-  auto grid_for = [&](int64_t c) {
-    const int rpb = kThreads / KPmax;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kUpMaxBlocks, (c + rpb - 1) / rpb));
-  };
+  auto grid_for = [&](int64_t) { return kUpMaxBlocks; };  // partial buffers: the largest grid
   auto layout = [&](Arena& a) {
     W = a.take<double>((size_t)m * len);
     Q = a.take<double>((size_t)m * m);
@@ -724,9 +786,21 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
     if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (err == hipSuccess) {
       k_zero_int<<<1, 64, 0, cs>>>(cnt, 1);
-      for (int r = 0; r < M - 1; ++r)
-        k_jac_round<<<npair, kThreads, 0, cs>>>(W, Q, m, len, pairs + (size_t)r * npair, jac_tol,
-                                                fro2, floor_rel, cnt);
+      // rows of up to 2048 elements stay in registers (m <= len)
+      const int ept = (len + kThreads - 1) / kThreads;
+      for (int r = 0; r < M - 1; ++r) {
+        const int2* pr = pairs + (size_t)r * npair;
+        if (ept <= 1)
+          k_jac_round_reg<1><<<npair, kThreads, 0, cs>>>(W, Q, m, len, pr, jac_tol, fro2, floor_rel, cnt);
+        else if (ept <= 2)
+          k_jac_round_reg<2><<<npair, kThreads, 0, cs>>>(W, Q, m, len, pr, jac_tol, fro2, floor_rel, cnt);
+        else if (ept <= 4)
+          k_jac_round_reg<4><<<npair, kThreads, 0, cs>>>(W, Q, m, len, pr, jac_tol, fro2, floor_rel, cnt);
+        else if (ept <= 8)
+          k_jac_round_reg<8><<<npair, kThreads, 0, cs>>>(W, Q, m, len, pr, jac_tol, fro2, floor_rel, cnt);
+        else
+          k_jac_round<<<npair, kThreads, 0, cs>>>(W, Q, m, len, pr, jac_tol, fro2, floor_rel, cnt);
+      }
       err = hipGetLastError();
       hipError_t e2 = hipStreamEndCapture(cs, &graph);
       if (err == hipSuccess) err = e2;
@@ -786,9 +860,10 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
     return CPCA_OK;
   }
   const int KP = pow2_at_least(k);
-  // the CG layout was sized for KPmax; smaller k uses the same blocks
+  // the buffers were sized for KPmax; the grids follow the actual KP
   for (int side = 0; side < 2; ++side) {
     UpSide& s = side == 0 ? A : B;
+    s.nb = (int)std::max<int64_t>(1, std::min<int64_t>(kUpMaxBlocks, ((int64_t)s.c * KP + kThreads - 1) / kThreads));
     const cpca_csr* L = side == 0 ? Lr : Lc;
     s.rp = L->rowptr;
     s.ci = L->colind;
@@ -878,10 +953,13 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
   const double scale = std::sqrt((double)n * (double)p / ((double)rho_r * (double)rho_c * (1.0 - delta)));
   k_up_weights<<<1, kThreads, 0, st>>>(A, B, KP, k, sig, scale, wts, rel);
   LAUNCHCHK();
+  STCHK(prof_begin(h, FAM_RANKK));
   HIPCHK(launch_rank_k<T>(st, X_out, A.S, B.S, wts, (int)p, (int)n, KP));
+  STCHK(prof_end(h));
   std::vector<double> hrel(2 * (size_t)KP);
   HIPCHK(hipMemcpyAsync(hrel.data(), rel, sizeof(double) * 2 * KP, hipMemcpyDeviceToHost, st));
   STCHK(read_state());
+  STCHK(prof_collect(h));
   int it_r = 0, it_c = 0, worst = 0;
   double rel_r = 0.0, rel_c = 0.0;
   for (int c = 0; c < k; ++c) {

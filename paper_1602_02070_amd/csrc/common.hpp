@@ -23,7 +23,7 @@ using namespace cpca;
 namespace {
 
 // apply: the CG operator application; other: residual / objective / dot launches
-enum Family { FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_COUNT = 4 };
+enum Family { FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_RANKK = 4, FAM_COUNT = 5 };
 
 }  // namespace
 
@@ -46,8 +46,8 @@ struct cpca_handle_s {
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   std::vector<int> ev_fam;
   size_t ev_used = 0;
-  int64_t prof_n[FAM_COUNT] = {0, 0, 0, 0};
-  double prof_ms[FAM_COUNT] = {0, 0, 0, 0};
+  int64_t prof_n[FAM_COUNT] = {};
+  double prof_ms[FAM_COUNT] = {};
 };
 
 namespace {

@@ -607,6 +607,7 @@ extern "C" cpca_status cpca_get_profile(cpca_handle h, const char* family, int64
   if (!std::strcmp(family, "update")) k = FAM_UPDATE;
   if (!std::strcmp(family, "fista")) k = FAM_FISTA;
   if (!std::strcmp(family, "other")) k = FAM_OTHER;
+  if (!std::strcmp(family, "rankk")) k = FAM_RANKK;
   if (k < 0) return fail(CPCA_EINVAL, "unknown kernel family");
   if (launches) *launches = h->prof_n[k];
   if (total_ms) *total_ms = h->prof_ms[k];
