@@ -239,6 +239,50 @@ cpca_status cpca_approx_decode(cpca_handle h, cpca_mode mode,
                                cpca_approx_info* info);
 
 /*
+ * Approximate decoder for clustering (Section VI, Algorithm 3). The rho_c
+ * columns of X~ are the sampled points (dimension rho_r):
+ *   1. k-means (Lloyd) from the k seed points init[0..k): assign each point
+ *      to the nearest centroid in squared Euclidean distance (ties to the
+ *      lower index), move each centroid to the mean of its points (an empty
+ *      cluster keeps its centroid), until no assignment changes or after
+ *      kmeans_max_iter updates;
+ *   2. each cluster indicator column is upsampled over L_c as
+ *      min c^T L_c c subject to c[omega_c] = c~ (eq. approx_c): the graph-
+ *      upsampling lemma, solved by Jacobi-preconditioned CG per column (FP64);
+ *   3. max pooling: sample i gets the column of its largest C[i, j] (ties to
+ *      the lower index).
+ * k-means, the CG and C are FP64 in every mode; the mode sets X~'s type.
+ * Xtil        rho_r x rho_c (column b is sample omega_c[b]).
+ * omega_c     rho_c distinct int32 indices in [0, n) (device).
+ * Lc          n x n Laplacian (symmetric PSD, used in place on the device).
+ *             Rows of a component with no sample get C = 0 (label 0).
+ * k           clusters, in [1, 64] and <= rho_c.
+ * init        k distinct int32 positions in [0, rho_c) (device): the seeds.
+ * kmeans_max_iter >= 0; tol > 0 (per-column ||r|| <= tol ||b||); max_iter >= 0.
+ * labels_out  n int32 cluster labels (device).
+ * C_out       optional n x k FP64 upsampled indicators (device), or NULL.
+ * sample_labels_out  optional rho_c int32 k-means labels (device), or NULL.
+ * Returns OK, EINVAL, ENOCONV (CG cap; outputs are written either way),
+ * ENOTSPD, ENAN, EHIP, ENOMEM.
+ */
+typedef struct {
+  int32_t kmeans_iters;    /* centroid updates run                           */
+  int32_t cg_iters;        /* CG iterations (largest column)                 */
+  int32_t status;          /* same value as the call's return code           */
+  int32_t reserved;
+  double rel_residual;     /* largest per-column ||r|| / ||b||               */
+  double ms;               /* wall time of the call                          */
+} cpca_cluster_info;
+
+cpca_status cpca_cluster_decode(cpca_handle h, cpca_mode mode,
+                                const void* Xtil, int64_t rho_r, int64_t rho_c,
+                                const int32_t* omega_c, int64_t n,
+                                const cpca_csr* Lc, int32_t k, const int32_t* init,
+                                int32_t kmeans_max_iter, double tol, int32_t max_iter,
+                                int32_t* labels_out, double* C_out,
+                                int32_t* sample_labels_out, cpca_cluster_info* info);
+
+/*
  * One application of the decoder operator (the fused two-sided sparse
  * product of eq. alternatedecoder's normal equations):
  *   Q = (m_r m_c^T) o P + gamma_r L_r P + gamma_c P L_c,  *pq = <P, Q> (FP64).

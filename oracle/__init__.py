@@ -16,9 +16,12 @@ Contents (each function cites the passage it follows):
   approx  -- the subspace-upsampling approximate decoder (Algorithm 2,
              Section V.C): thin SVD, rank selection, graph upsampling by the
              closed form of its lemma, normalisation, RIP scaling.
+  cluster -- the approximate decoder for clustering (Algorithm 3, Section
+             VI): Lloyd's k-means from given seeds, upsampling of the cluster
+             indicators over the column graph, max pooling.
 
 Every floating-point computation is FP64. Parity status of each function is
 stated in its docstring; all functions here are pinned by tests that check
 them against closed forms, brute force or invariants fixed by the paper.
 """
-from . import frpcag, decoder, approx  # noqa: F401
+from . import frpcag, decoder, approx, cluster  # noqa: F401

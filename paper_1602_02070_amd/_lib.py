@@ -16,7 +16,7 @@ EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
            "cpca_set_stream", "cpca_frpcag", "cpca_decode", "cpca_decode_backward",
            "cpca_apply", "cpca_check_csr_host", "cpca_check_index_set_host",
            "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config",
-           "cpca_solve_batched", "cpca_approx_decode"]
+           "cpca_solve_batched", "cpca_approx_decode", "cpca_cluster_decode"]
 
 
 class CpcaCsr(ctypes.Structure):
@@ -38,6 +38,14 @@ class CpcaApproxInfo(ctypes.Structure):
                 ("iters_c", c_int32), ("status", c_int32), ("reserved", c_int32),
                 ("rel_residual_r", c_double), ("rel_residual_c", c_double),
                 ("scale", c_double), ("ms", c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class CpcaClusterInfo(ctypes.Structure):
+    _fields_ = [("kmeans_iters", c_int32), ("cg_iters", c_int32), ("status", c_int32),
+                ("reserved", c_int32), ("rel_residual", c_double), ("ms", c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -89,6 +97,9 @@ def _declare(lib):
         "cpca_approx_decode": (st, [P, c_int32, P, c_int64, c_int64, P, P, c_int64, c_int64, csr,
                                     csr, c_double, c_double, c_int32, c_double, c_int32, P,
                                     POINTER(c_double), POINTER(CpcaApproxInfo)]),
+        "cpca_cluster_decode": (st, [P, c_int32, P, c_int64, c_int64, P, c_int64, csr, c_int32, P,
+                                     c_int32, c_double, c_int32, P, P, P,
+                                     POINTER(CpcaClusterInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import CpcaApproxInfo, CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
+from ._lib import CpcaApproxInfo, CpcaClusterInfo, CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
 
 __all__ = ["CpcaError", "Graph", "handle", "frpcag", "decode", "decode_backward",
            "apply_operator", "Decode", "DecodeProblem", "profiling", "get_profile",
@@ -225,6 +225,35 @@ def approx_decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tens
                                         int(max_iter), _ptr(out), sigma, ctypes.byref(info))
     _check(st, "cpca_approx_decode")
     return out, [sigma[i] for i in range(min(Xt.shape))], info.as_dict()
+
+
+def cluster_decode(Xtil: torch.Tensor, omega_c: torch.Tensor, n: int, Lc: Graph, init,
+                   kmeans_max_iter: int = 100, tol: float = 1e-10, max_iter: int = 20000,
+                   mode: str | None = None, want_C: bool = False, h=None):
+    """Approximate decoder for clustering (Section VI, Algorithm 3).
+
+    init: the k seed columns of Xtil (positions in [0, rho_c)). Returns
+    (labels (n, int32), sample_labels (rho_c, int32), C (n x k FP64) or None,
+    info)."""
+    mode = mode_for(Xtil.dtype, mode)
+    dt = _dtype_of(mode)
+    Xt = _need(Xtil, "Xtil", dt)
+    om_c = _index(omega_c, "omega_c")
+    if Xt.shape[1] != om_c.numel():
+        raise ValueError("Xtil must have len(omega_c) columns")
+    seeds = _index(torch.as_tensor(init, dtype=torch.int32).to(Xt.device), "init")
+    k = seeds.numel()
+    labels = torch.empty(n, dtype=torch.int32, device=Xt.device)
+    slab = torch.empty(Xt.shape[1], dtype=torch.int32, device=Xt.device)
+    C = torch.empty((n, k), dtype=torch.float64, device=Xt.device) if want_C else None
+    info = CpcaClusterInfo()
+    st = _lib.load().cpca_cluster_decode(h or handle(Xt.device), _lib.MODES[mode], _ptr(Xt),
+                                         Xt.shape[0], Xt.shape[1], _ptr(om_c), int(n),
+                                         ctypes.byref(Lc.desc), int(k), _ptr(seeds),
+                                         int(kmeans_max_iter), float(tol), int(max_iter),
+                                         _ptr(labels), _ptr(C), _ptr(slab), ctypes.byref(info))
+    _check(st, "cpca_cluster_decode")
+    return labels, slab, C, info.as_dict()
 
 
 def decode_backward(G: torch.Tensor, X: torch.Tensor, omega_r, omega_c, p: int, n: int,

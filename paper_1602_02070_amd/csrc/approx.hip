@@ -1,6 +1,9 @@
-// Subspace-upsampling approximate decoder (Algorithm 2, Section V-C) on
-// gfx950: cpca_approx_decode.
+// The approximate decoders on gfx950: cpca_approx_decode (subspace
+// upsampling, Algorithm 2, Section V-C) and cpca_cluster_decode (clustering,
+// Algorithm 3, Section VI: k-means on the columns of X~, the same
+// upsampling CG on the cluster indicators over L_c, max pooling).
 //
+// Algorithm 2:
 //   1. Thin SVD of X~ by one-sided (Hestenes) Jacobi: the rows of
 //      W = X~^T (rho_r >= rho_c) or W = X~ (rho_r < rho_c) are orthogonalised
 //      pairwise, in round-robin order (every round rotates m/2 disjoint
@@ -588,6 +591,116 @@ __global__ void __launch_bounds__(kThreads) k_fill_zero(TO* __restrict__ X, size
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) X[e] = TO(0);
 }
 
+// ---------------------------------------------- clustering (Algorithm 3)
+// Points (rho_c x rho_r, FP64): point j is column j of X~ (rho_r x rho_c).
+template <typename TI>
+__global__ void __launch_bounds__(kThreads)
+k_km_points(double* __restrict__ P, const TI* __restrict__ Xt, int rho_r, int rho_c) {
+  const size_t N = (size_t)rho_r * rho_c;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+    const size_t i = e / rho_c, j = e - i * rho_c;
+    P[j * rho_r + i] = (double)Xt[e];
+  }
+}
+
+// Centroids from the seed points; labels = -1 (every point changes on the
+// first assignment).
+__global__ void __launch_bounds__(kThreads)
+k_km_seed(double* __restrict__ Cen, const double* __restrict__ P, const int* __restrict__ init,
+          int k, int d, int* __restrict__ labels, int N) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)k * d; e += stride) {
+    const size_t j = e / d, t = e - j * d;
+    Cen[e] = P[(size_t)init[j] * d + t];
+  }
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)N; e += stride)
+    labels[e] = -1;
+}
+
+// Assignment (one workgroup per point): the nearest centroid in squared
+// Euclidean distance, the lower index on ties; changed counts new labels.
+__global__ void __launch_bounds__(kThreads)
+k_km_assign(const double* __restrict__ P, const double* __restrict__ Cen, int d, int k,
+            int* __restrict__ labels, int* __restrict__ changed) {
+  const double* x = P + (size_t)blockIdx.x * d;
+  double best = 0.0;
+  int bj = -1;
+  for (int j0 = 0; j0 < k; j0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int t = threadIdx.x; t < d; t += kThreads) {
+      const double xv = x[t];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (j0 + q < k) {
+          const double df = xv - Cen[(size_t)(j0 + q) * d + t];
+          acc[q] += df * df;
+        }
+      }
+    }
+    block_sum<8>(acc);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (j0 + q < k && (bj < 0 || acc[q] < best)) {
+        best = acc[q];
+        bj = j0 + q;
+      }
+  }
+  if (threadIdx.x == 0 && labels[blockIdx.x] != bj) {
+    labels[blockIdx.x] = bj;
+    atomicAdd(changed, 1);
+  }
+}
+
+// Update: centroid j (workgroup j % k, dimension slice blockIdx.x / k)
+// becomes the mean of its points; an empty cluster keeps its centroid.
+__global__ void __launch_bounds__(kThreads)
+k_km_update(const double* __restrict__ P, double* __restrict__ Cen, const int* __restrict__ labels,
+            int N, int d, int k) {
+  const int j = blockIdx.x % k;
+  const int t = (blockIdx.x / k) * kThreads + threadIdx.x;
+  int cnt = 0;
+  double sum = 0.0;
+  for (int i = 0; i < N; ++i) {
+    if (labels[i] == j) {
+      ++cnt;
+      if (t < d) sum += P[(size_t)i * d + t];
+    }
+  }
+  if (cnt > 0 && t < d) Cen[(size_t)j * d + t] = sum / cnt;
+}
+
+// The indicator columns of the sample labels in the CG layout (rho_c x KP).
+__global__ void __launch_bounds__(kThreads)
+k_km_onehot(double* __restrict__ R, const int* __restrict__ labels, int N, int KP) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)N * KP; e += stride)
+    R[e] = labels[e / KP] == (int)(e % KP) ? 1.0 : 0.0;
+}
+
+// Max pooling: the column of the largest of the k upsampled indicators of
+// every row (the lower index on ties); optionally C itself (n x k, FP64).
+__global__ void __launch_bounds__(kThreads)
+k_max_pool(const double* __restrict__ S, int n, int KP, int k, int* __restrict__ out,
+           double* __restrict__ C) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) {
+    const double* row = S + i * KP;
+    double best = row[0];
+    int bj = 0;
+    for (int c = 1; c < k; ++c)
+      if (row[c] > best) {
+        best = row[c];
+        bj = c;
+      }
+    out[i] = bj;
+    if (C)
+      for (int c = 0; c < k; ++c) C[i * k + c] = row[c];
+  }
+}
+
 // ------------------------------------------------------------------- host
 int pow2_at_least(int k) {
   int v = 1;
@@ -672,6 +785,90 @@ cpca_status fetch_indices(const char* name, const int32_t* idx, int64_t count, i
   STCHK(fetch_index_set(name, idx, count, dim, mask));
   out.resize((size_t)count);
   HIPCHK(hipMemcpy(out.data(), idx, sizeof(int32_t) * count, hipMemcpyDefault));
+  return CPCA_OK;
+}
+
+// Per side: done flags then iteration counts (kApproxKMax each), sides A, B.
+cpca_status read_states(cpca_handle h, const UpSide& A, const UpSide& B, int nsides,
+                        std::vector<int>& hs) {
+  hs.assign(2 * 2 * kApproxKMax, 1);
+  HIPCHK(hipMemcpyAsync(hs.data(), A.state, sizeof(int) * 2 * kApproxKMax, hipMemcpyDeviceToHost,
+                        h->stream));
+  if (nsides > 1)
+    HIPCHK(hipMemcpyAsync(hs.data() + 2 * kApproxKMax, B.state, sizeof(int) * 2 * kApproxKMax,
+                          hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return CPCA_OK;
+}
+
+// Upsampling CG over nsides graph sides (A, and B when nsides = 2) in shared
+// launches: start vectors from S's sampled rows, per-column CG to
+// ||r|| <= tol ||b|| or max_iter, then S on the unknown rows and the column
+// norm partials. Chunks of kUpChunk iterations are replayed as a HIP graph
+// on a side stream; the host reads the done flags between chunks.
+cpca_status upsample_solve(cpca_handle h, const UpSide& A, const UpSide& B, int nsides, int KP,
+                           int k, double tol, int max_iter, std::vector<int>& hstate) {
+  hipStream_t st = h->stream;
+  const int gup = A.nb + (nsides > 1 ? B.nb : 0);
+  k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 0);
+  LAUNCHCHK();
+  k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 1);
+  LAUNCHCHK();
+  k_up_arm<<<nsides, kThreads, 0, st>>>(A, B, KP, k, tol * tol);
+  LAUNCHCHK();
+  auto all_done = [&]() {
+    for (int side = 0; side < nsides; ++side)
+      for (int c = 0; c < k; ++c)
+        if (hstate[(size_t)side * 2 * kApproxKMax + c] == 0) return false;
+    return true;
+  };
+  STCHK(read_states(h, A, B, nsides, hstate));
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipEvent_t ev;
+  hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  auto enqueue = [&](hipStream_t s2, int par) -> hipError_t {
+    k_up_apply<<<gup, kThreads, 0, s2>>>(A, B, KP);
+    k_up_update<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
+    k_up_pupdate<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
+    return hipGetLastError();
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (err == hipSuccess && max_iter >= kUpChunk) {
+    err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int j = 0; j < kUpChunk && err == hipSuccess; ++j) err = enqueue(cs, j & 1);
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (err == hipSuccess) err = e2;
+    if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  }
+  if (err == hipSuccess) err = hipEventRecord(ev, st);
+  if (err == hipSuccess) err = hipStreamWaitEvent(cs, ev, 0);
+  int it = 0;
+  cpca_status sst = CPCA_OK;
+  while (err == hipSuccess && it < max_iter && !all_done()) {
+    if (exec && it + kUpChunk <= max_iter) {
+      err = hipGraphLaunch(exec, cs);
+      it += kUpChunk;
+    } else {
+      err = enqueue(cs, it & 1);
+      it += 1;
+    }
+    if (err == hipSuccess) err = hipEventRecord(ev, cs);
+    if (err == hipSuccess) err = hipStreamWaitEvent(st, ev, 0);
+    if (err != hipSuccess) break;
+    if ((sst = read_states(h, A, B, nsides, hstate)) != CPCA_OK) break;
+  }
+  const hipError_t e3 = hipStreamSynchronize(cs);
+  if (err == hipSuccess) err = e3;
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipEventDestroy(ev);
+  (void)hipStreamDestroy(cs);
+  if (err != hipSuccess) return fail(CPCA_EHIP, std::string("upsampling CG: ") + hipGetErrorString(err));
+  STCHK(sst);
+  k_up_finish<<<gup, kThreads, 0, st>>>(A, B, KP);
+  LAUNCHCHK();
   return CPCA_OK;
 }
 
@@ -879,77 +1076,9 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
   LAUNCHCHK();
 
   // ---- 3. upsampling, both graphs in the same launches
-  const int gup = A.nb + B.nb;
-  k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 0);
-  LAUNCHCHK();
-  k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 1);
-  LAUNCHCHK();
-  k_up_arm<<<2, kThreads, 0, st>>>(A, B, KP, k, tol * tol);
-  LAUNCHCHK();
-  std::vector<int> hstate(2 * 2 * kApproxKMax);
-  auto read_state = [&]() -> cpca_status {
-    HIPCHK(hipMemcpyAsync(hstate.data(), A.state, sizeof(int) * 2 * kApproxKMax, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hstate.data() + 2 * kApproxKMax, B.state, sizeof(int) * 2 * kApproxKMax,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    return CPCA_OK;
-  };
-  auto all_done = [&]() {
-    for (int side = 0; side < 2; ++side)
-      for (int c = 0; c < k; ++c)
-        if (hstate[(size_t)side * 2 * kApproxKMax + c] == 0) return false;
-    return true;
-  };
-  STCHK(read_state());
-  {
-    hipStream_t cs;
-    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipEvent_t ev;
-    hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    auto enqueue = [&](hipStream_t s2, int par) -> hipError_t {
-      k_up_apply<<<gup, kThreads, 0, s2>>>(A, B, KP);
-      k_up_update<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
-      k_up_pupdate<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
-      return hipGetLastError();
-    };
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    if (err == hipSuccess && max_iter >= kUpChunk) {
-      err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-      for (int j = 0; j < kUpChunk && err == hipSuccess; ++j) err = enqueue(cs, j & 1);
-      const hipError_t e2 = hipStreamEndCapture(cs, &graph);
-      if (err == hipSuccess) err = e2;
-      if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    }
-    if (err == hipSuccess) err = hipEventRecord(ev, st);
-    if (err == hipSuccess) err = hipStreamWaitEvent(cs, ev, 0);
-    int it = 0;
-    cpca_status sst = CPCA_OK;
-    while (err == hipSuccess && it < max_iter && !all_done()) {
-      if (exec && it + kUpChunk <= max_iter) {
-        err = hipGraphLaunch(exec, cs);
-        it += kUpChunk;
-      } else {
-        err = enqueue(cs, it & 1);
-        it += 1;
-      }
-      if (err == hipSuccess) err = hipEventRecord(ev, cs);
-      if (err == hipSuccess) err = hipStreamWaitEvent(st, ev, 0);
-      if (err != hipSuccess) break;
-      if ((sst = read_state()) != CPCA_OK) break;
-    }
-    const hipError_t e3 = hipStreamSynchronize(cs);
-    if (err == hipSuccess) err = e3;
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipEventDestroy(ev);
-    (void)hipStreamDestroy(cs);
-    if (err != hipSuccess) return fail(CPCA_EHIP, std::string("approx_decode CG: ") + hipGetErrorString(err));
-    STCHK(sst);
-  }
+  std::vector<int> hstate;
+  STCHK(upsample_solve(h, A, B, 2, KP, k, tol, max_iter, hstate));
   // ---- 4.-6. norms, weights, X = U diag(w) V^T
-  k_up_finish<<<gup, kThreads, 0, st>>>(A, B, KP);
-  LAUNCHCHK();
   const double scale = std::sqrt((double)n * (double)p / ((double)rho_r * (double)rho_c * (1.0 - delta)));
   k_up_weights<<<1, kThreads, 0, st>>>(A, B, KP, k, sig, scale, wts, rel);
   LAUNCHCHK();
@@ -958,7 +1087,7 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
   STCHK(prof_end(h));
   std::vector<double> hrel(2 * (size_t)KP);
   HIPCHK(hipMemcpyAsync(hrel.data(), rel, sizeof(double) * 2 * KP, hipMemcpyDeviceToHost, st));
-  STCHK(read_state());
+  STCHK(read_states(h, A, B, 2, hstate));
   STCHK(prof_collect(h));
   int it_r = 0, it_c = 0, worst = 0;
   double rel_r = 0.0, rel_c = 0.0;
@@ -984,7 +1113,152 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
   return CPCA_OK;
 }
 
+
+template <typename T>
+cpca_status run_cluster(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
+                        const int32_t* om_c, int64_t n, const cpca_csr* Lc, int32_t k,
+                        const int32_t* init, int32_t km_max_iter, double tol, int32_t max_iter,
+                        int32_t* labels_out, double* C_out, int32_t* sample_labels_out,
+                        cpca_cluster_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipStreamSynchronize(h->stream));  // inputs may still be in flight
+  HostCsr hLc;
+  STCHK(fetch_csr("Lc", Lc, hLc));
+  std::vector<int32_t> wc, seeds;
+  STCHK(fetch_indices("omega_c", om_c, rho_c, n, wc));
+  STCHK(fetch_indices("init", init, k, rho_c, seeds));
+  const SideHost sc = side_tables(hLc, wc);
+  const int KP = pow2_at_least(k);
+  const int d = (int)rho_r, N = (int)rho_c;
+  double *P = nullptr, *Cen = nullptr, *R = nullptr, *dinv = nullptr;
+  int *lab = nullptr, *chg = nullptr, *inv = nullptr, *dseeds = nullptr;
+  UpSide A, B;
+  auto layout = [&](Arena& a) {
+    P = a.take<double>((size_t)N * d);
+    Cen = a.take<double>((size_t)k * d);
+    lab = a.take<int>((size_t)N);
+    chg = a.take<int>(1);
+    dseeds = a.take<int>((size_t)k);
+    R = a.take<double>((size_t)N * KP);
+    inv = a.take<int>((size_t)n);
+    dinv = a.take<double>((size_t)n);
+    const size_t NV = (size_t)n * KP;
+    A.c = (int)n;
+    A.nb = (int)std::max<int64_t>(1, std::min<int64_t>(kUpMaxBlocks, ((int64_t)n * KP + kThreads - 1) / kThreads));
+    A.x = a.take<double>(NV);
+    A.r = a.take<double>(NV);
+    A.z = a.take<double>(NV);
+    A.p = a.take<double>(NV);
+    A.q = a.take<double>(NV);
+    A.S = a.take<double>(NV);
+    A.pa = a.take<double>((size_t)A.nb * KP);
+    A.pb = a.take<double>((size_t)A.nb * 2 * KP);
+    A.scal = a.take<double>(6 * kApproxKMax);
+    A.state = a.take<int>(2 * kApproxKMax);
+  };
+  {
+    Arena a;
+    layout(a);
+    STCHK(ensure_ws(h, a.off));
+  }
+  Arena ar;
+  ar.base = h->ws;
+  layout(ar);
+  hipStream_t st = h->stream;
+  HIPCHK(hipMemcpyAsync(inv, sc.inv.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dinv, sc.dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dseeds, seeds.data(), sizeof(int) * k, hipMemcpyHostToDevice, st));
+
+  // ---- 1. k-means on the columns of X~ (Lloyd, from the given seeds)
+  k_km_points<T><<<vec_grid((size_t)N * d), kThreads, 0, st>>>(P, Xt, d, N);
+  LAUNCHCHK();
+  k_km_seed<<<vec_grid((size_t)std::max(k * d, N)), kThreads, 0, st>>>(Cen, P, dseeds, k, d, lab, N);
+  LAUNCHCHK();
+  const int ugrid = k * ((d + kThreads - 1) / kThreads);
+  int km_it = 0;
+  for (;;) {
+    k_zero_int<<<1, 64, 0, st>>>(chg, 1);
+    k_km_assign<<<N, kThreads, 0, st>>>(P, Cen, d, k, lab, chg);
+    LAUNCHCHK();
+    int hc = 0;
+    HIPCHK(hipMemcpyAsync(&hc, chg, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc == 0 || km_it >= km_max_iter) break;
+    k_km_update<<<ugrid, kThreads, 0, st>>>(P, Cen, lab, N, d, k);
+    LAUNCHCHK();
+    ++km_it;
+  }
+  if (sample_labels_out)
+    HIPCHK(hipMemcpyAsync(sample_labels_out, lab, sizeof(int) * N, hipMemcpyDeviceToDevice, st));
+
+  // ---- 2. upsampling of the k indicator columns over L_c
+  k_km_onehot<<<vec_grid((size_t)N * KP), kThreads, 0, st>>>(R, lab, N, KP);
+  LAUNCHCHK();
+  A.rp = Lc->rowptr;
+  A.ci = Lc->colind;
+  A.v = Lc->vals;
+  A.inv = inv;
+  A.dinv = dinv;
+  A.R = R;
+  std::vector<int> hstate;
+  STCHK(upsample_solve(h, A, B, 1, KP, k, tol, max_iter, hstate));
+
+  // ---- 3. max pooling
+  k_max_pool<<<vec_grid((size_t)n), kThreads, 0, st>>>(A.S, (int)n, KP, k, labels_out, C_out);
+  LAUNCHCHK();
+  std::vector<double> hscal(6 * kApproxKMax);
+  HIPCHK(hipMemcpyAsync(hscal.data(), A.scal, sizeof(double) * hscal.size(), hipMemcpyDeviceToHost, st));
+  STCHK(read_states(h, A, B, 1, hstate));
+  int it_max = 0, worst = 0;
+  double rel = 0.0;
+  for (int c = 0; c < k; ++c) {
+    const int dc = hstate[(size_t)c];
+    it_max = std::max(it_max, hstate[(size_t)kApproxKMax + c]);
+    const double bb = hscal[(size_t)4 * kApproxKMax + c];
+    const double rr = std::min(hscal[(size_t)2 * kApproxKMax + c], hscal[(size_t)3 * kApproxKMax + c]);
+    if (bb > 0.0) rel = std::max(rel, std::sqrt(rr / bb));
+    if (dc != 1) worst = std::max(worst, dc == 0 ? 1 : dc);
+  }
+  cpca_status s = CPCA_OK;
+  if (worst == 3) s = CPCA_ENAN;
+  else if (worst == 2) s = CPCA_ENOTSPD;
+  else if (worst == 1) s = CPCA_ENOCONV;
+  if (info) {
+    info->kmeans_iters = km_it;
+    info->cg_iters = it_max;
+    info->status = (int32_t)s;
+    info->reserved = 0;
+    info->rel_residual = rel;
+    info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (s == CPCA_ENAN) return fail(s, "cluster_decode: NaN/Inf in the upsampling CG");
+  if (s == CPCA_ENOTSPD) return fail(s, "cluster_decode: upsampling CG breakdown (p^T A p <= 0)");
+  if (s == CPCA_ENOCONV) return fail(s, "cluster_decode: upsampling CG reached max_iter");
+  return CPCA_OK;
+}
+
 }  // namespace
+
+extern "C" cpca_status cpca_cluster_decode(cpca_handle h, cpca_mode mode, const void* Xtil,
+                                           int64_t rho_r, int64_t rho_c, const int32_t* omega_c,
+                                           int64_t n, const cpca_csr* Lc, int32_t k,
+                                           const int32_t* init, int32_t kmeans_max_iter,
+                                           double tol, int32_t max_iter, int32_t* labels_out,
+                                           double* C_out, int32_t* sample_labels_out,
+                                           cpca_cluster_info* info) {
+  clear_error();
+  STCHK(check_cluster_args(mode, rho_r, rho_c, omega_c, n, Lc, k, init, kmeans_max_iter, tol,
+                           max_iter));
+  if (!Xtil || !labels_out) return fail(CPCA_EINVAL, "cluster_decode: null data pointer");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  if (mode == CPCA_FP64)
+    return run_cluster<double>(h, static_cast<const double*>(Xtil), rho_r, rho_c, omega_c, n, Lc,
+                               k, init, kmeans_max_iter, tol, max_iter, labels_out, C_out,
+                               sample_labels_out, info);
+  return run_cluster<float>(h, static_cast<const float*>(Xtil), rho_r, rho_c, omega_c, n, Lc, k,
+                            init, kmeans_max_iter, tol, max_iter, labels_out, C_out,
+                            sample_labels_out, info);
+}
 
 extern "C" cpca_status cpca_approx_decode(cpca_handle h, cpca_mode mode, const void* Xtil,
                                           int64_t rho_r, int64_t rho_c, const int32_t* omega_r,

@@ -205,6 +205,28 @@ cpca_status check_approx_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
   return CPCA_OK;
 }
 
+cpca_status check_cluster_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
+                               const int32_t* om_c, int64_t n, const cpca_csr* Lc, int32_t k,
+                               const int32_t* init, int32_t km_max_iter, double tol,
+                               int32_t max_iter) {
+  cpca_status st;
+  if ((st = check_mode(mode))) return st;
+  if ((st = check_dims("Xtil", rho_r, rho_c))) return st;
+  if (n < 1 || n > INT32_MAX) return fail(CPCA_EINVAL, "cluster_decode: n out of range");
+  if (rho_c > n) return fail(CPCA_EINVAL, "cluster_decode: more samples than columns");
+  if ((unsigned long long)rho_r * (unsigned long long)rho_c > (1ull << 34))
+    return fail(CPCA_EINVAL, "cluster_decode: Xtil too large");
+  if (!om_c) return fail(CPCA_EINVAL, "cluster_decode: null index set");
+  if ((st = check_csr_shape("Lc", Lc, n))) return st;
+  if (k < 1 || k > 64 || k > rho_c)
+    return fail(CPCA_EINVAL, "cluster_decode: k must be in [1, 64] and <= rho_c");
+  if (!init) return fail(CPCA_EINVAL, "cluster_decode: null init");
+  if (km_max_iter < 0) return fail(CPCA_EINVAL, "cluster_decode: kmeans_max_iter < 0");
+  if (!std::isfinite(tol) || !(tol > 0)) return fail(CPCA_EINVAL, "cluster_decode: tol must be > 0");
+  if (max_iter < 0) return fail(CPCA_EINVAL, "cluster_decode: max_iter < 0");
+  return CPCA_OK;
+}
+
 }  // namespace cpca
 
 extern "C" cpca_status cpca_check_csr_host(int64_t n, int64_t nnz, const int32_t* rowptr,

@@ -33,5 +33,9 @@ cpca_status check_approx_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
                               const int32_t* om_r, const int32_t* om_c, int64_t p, int64_t n,
                               const cpca_csr* Lr, const cpca_csr* Lc, double delta,
                               double ratio, int32_t k_max, double tol, int32_t max_iter);
+cpca_status check_cluster_args(cpca_mode mode, int64_t rho_r, int64_t rho_c,
+                               const int32_t* om_c, int64_t n, const cpca_csr* Lc, int32_t k,
+                               const int32_t* init, int32_t km_max_iter, double tol,
+                               int32_t max_iter);
 
 }  // namespace cpca

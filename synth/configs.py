@@ -23,7 +23,7 @@ from .graphs import knn_laplacian, laplacian_lmax, low_eigvecs
 
 __all__ = ["Problem", "round_count", "make_problem", "cfg1_tiny", "cfg2_face",
            "cfg3_video", "cfg5_batch", "small_problem", "grid_coords",
-           "circle_coords", "helix_coords"]
+           "circle_coords", "helix_coords", "cluster_digits"]
 
 
 @dataclasses.dataclass
@@ -46,6 +46,7 @@ class Problem:
     tol: float = 1e-10
     X_true: np.ndarray | None = None   # low-rank part (informational only)
     Y: np.ndarray | None = None        # full data (not needed by the solvers)
+    meta: dict = dataclasses.field(default_factory=dict)  # workload-specific extras
 
     @property
     def rho_r(self) -> int:
@@ -249,3 +250,46 @@ def cfg5_batch(seed: int = 0, count: int = 64, scale: float = 1.0):
     grid = [(gr, gc) for gr in (0.1, 1.0, 10.0, 100.0)
             for gc in (0.1, 1.0, 10.0, 100.0)]
     return out, grid
+
+
+def cluster_digits(seed: int = 0, n: int = 70000, side: int = 28, k: int = 10,
+                   frac_c: float = 0.05, K: int = 10, spread: float = 1.0) -> Problem:
+    """Clustering stand-in with the shape of the paper's large digit set
+    (p = 28 x 28 pixel features, n = 70000 samples, k = 10 classes; the
+    paper compresses such sets along the samples only, so every row is kept
+    and 5% of the columns are sampled).
+
+    Samples sit in a 3-D latent space around k class centres (std `spread`,
+    centres uniform in [0, 12]^3), and the column graph is the 10-NN graph on
+    those latent points. A sample's data column is its class template (a
+    smooth random image) plus a rank-3 within-class variation, Gaussian noise
+    (std 0.1) and 5% outliers U(-1, 1). The row graph is the 10-NN graph of
+    the pixel grid. Only the sampled columns are generated (Algorithm 3 needs
+    no other data). meta: labels (n true classes) and init (k sampled column
+    positions drawn at random, the seeds of k-means)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 12.0, size=(k, 3))
+    labels = rng.integers(0, k, size=n)
+    lat = centres[labels] + spread * rng.standard_normal((n, 3))
+    rows = grid_coords(side, side)
+    p = side * side
+    Lr, _ = knn_laplacian(rows, K)
+    Lc, _ = knn_laplacian(lat, K)
+    rho_c = round_count(frac_c, n, K + 2)
+    om_c = _sample(rng, n, rho_c)
+    om_r = np.arange(p, dtype=np.int32)
+    templates = _smooth_fields(rng, side, side, k, 2.0)
+    var = _smooth_fields(rng, side, side, 3, 2.0)
+    lab_s = labels[om_c]
+    Y = (templates[lab_s] + 0.3 * rng.standard_normal((rho_c, 3)) @ var
+         + 0.1 * rng.standard_normal((rho_c, p))).T
+    cnt = int(round(0.05 * p * rho_c))
+    pos = rng.choice(p * rho_c, size=cnt, replace=False)
+    Y.reshape(-1)[pos] += rng.uniform(-1.0, 1.0, size=cnt)
+    Ytil = np.ascontiguousarray(Y)
+    Lc_t, _ = knn_laplacian(lat[om_c], min(K, rho_c - 1))
+    init = np.sort(rng.choice(rho_c, size=k, replace=False)).astype(np.int32)
+    return Problem(name="cluster_digits", p=p, n=n, Lr=Lr, Lc=Lc, omega_r=om_r, omega_c=om_c,
+                   Ytil=Ytil, Lr_til=Lr, Lc_til=Lc_t, lmax_r_til=laplacian_lmax(Lr),
+                   lmax_c_til=laplacian_lmax(Lc_t), gamma_r=1.0, gamma_c=1.0,
+                   fista_iters=500, tol=1e-10, meta=dict(labels=labels, init=init, k=k))

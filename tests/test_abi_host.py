@@ -148,3 +148,25 @@ def test_approx_decode_rejects_bad_arguments_before_device_work(lib):
         assert word in _lib.last_error(), (kw, _lib.last_error())
     assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
     assert call(it=0, ratio=0.0, kmax=64) == _lib.EINVAL and "null handle" in _lib.last_error()
+
+
+def test_cluster_decode_rejects_bad_arguments_before_device_work(lib):
+    info = _lib.CpcaClusterInfo()
+    dummy = ctypes.c_void_p(16)
+    Lc, keep = _csr(50)
+    base = dict(mode=0, rho_r=8, rho_c=20, n=50, k=4, km=100, tol=1e-10, it=100)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return lib.cpca_cluster_decode(None, a["mode"], dummy, a["rho_r"], a["rho_c"], dummy,
+                                       a["n"], ctypes.byref(Lc), a["k"], dummy, a["km"], a["tol"],
+                                       a["it"], dummy, None, None, ctypes.byref(info))
+
+    cases = [(dict(mode=3), "mode"), (dict(rho_r=0), "size"), (dict(rho_c=51), "samples"),
+             (dict(n=51), "Lc"), (dict(k=0), "k must"), (dict(k=65), "k must"),
+             (dict(k=21), "k must"), (dict(km=-1), "kmeans_max_iter"), (dict(tol=0.0), "tol"),
+             (dict(it=-1), "max_iter")]
+    for kw, word in cases:
+        assert call(**kw) == _lib.EINVAL, kw
+        assert word in _lib.last_error(), (kw, _lib.last_error())
+    assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
