@@ -10,7 +10,7 @@ the HBM traffic of that kernel from the committed counter summary (null when
 the kernel sources changed since the counters were taken), and the FP64 CPU
 oracle timed on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--workload video|face|tiny|batch|video-approx]
+    python bench.py [--steps K] [--warmup W] [--workload video|face|tiny|batch|video-approx|cluster]
                     [--copy-probe]   (device copies of known size, for counter calibration)
 """
 from __future__ import annotations
@@ -67,6 +67,10 @@ WORKLOADS = {
                      "500 it, then the subspace-upsampling approximate decoder (Algorithm 2: "
                      "Jacobi SVD of X~, k at sigma_k/sigma_1 >= 0.1, FP64 PCG upsampling, FP32 "
                      "rank-k output)", 1e-10),
+    "cluster": ("cluster_digits", "digits-shaped 28x28 pixels x 70000 samples in 10 classes on a "
+                "latent 3-D 10-NN graph, 5% of the samples (all features), FISTA 500 it, then the "
+                "clustering decoder (Algorithm 3: k-means from 10 seeded samples, FP64 PCG "
+                "upsampling of the indicators, max pooling)", 1e-10),
     "batch": ("cfg5_batch", "64 instances, p log-uniform in [500, 4000] x n log-uniform in "
               "[200, 2000], rank 3-10, helix rows / circle columns, 5% outliers, 10% sampling, "
               "each swept over a 4 x 4 (gamma_r, gamma_c) grid in {0.1, 1, 10, 100}: 1024 tasks "
@@ -272,6 +276,117 @@ def run_approx(args, desc, tol):
     return 0
 
 
+def cluster_cpu_baseline(P, J, max_seconds=25.0):
+    """One step of the oracle on one core: FISTA timed for a bounded number
+    of iterations and extrapolated to J, then Algorithm 3 timed whole."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cluster as OC
+    from oracle import frpcag as OF
+    limiter = threadpool_limits(limits=1)
+    t0 = time.perf_counter()
+    OF.fista(P.Ytil, P.Lr_til, P.Lc_til, P.gamma_r, P.gamma_c, P.lmax_r_til, P.lmax_c_til, 2)
+    t2 = (time.perf_counter() - t0) / 2
+    jt = max(2, min(J, int(0.4 * max_seconds / max(t2, 1e-6))))
+    t0 = time.perf_counter()
+    Xt, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, P.gamma_r, P.gamma_c, P.lmax_r_til,
+                     P.lmax_c_til, jt)
+    t_f = (time.perf_counter() - t0) / jt * J
+    t0 = time.perf_counter()
+    OC.cluster_decode(Xt, P.n, P.omega_c, P.Lc, P.meta["init"])
+    t_d = time.perf_counter() - t0
+    limiter.unregister()
+    return {"value": P.n / (t_f + t_d), "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle: FISTA timed for {jt} of {J} iterations on Y~ "
+                       f"{P.rho_r}x{P.rho_c} and extrapolated ({t_f:.1f} s), Algorithm 3 on its "
+                       f"output timed whole ({t_d:.1f} s)")}
+
+
+def run_cluster(args, desc, tol):
+    """FISTA + the clustering decoder on the digits-shaped workload. The
+    roofline line is that of the FISTA product (the fused gradient, prox and
+    momentum step on the 784 x 3500 sampled matrix, FP64), the largest
+    HBM-bound share of the step; k-means and the upsampling CG on 70000 x 16
+    panels are latency bound."""
+    import torch
+
+    import paper_1602_02070_amd as cp
+    import synth
+    log("[bench] building inputs: cluster")
+    P = synth.cluster_digits(0)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    dt = torch.float64 if args.mode == "fp64" else torch.float32
+    Lc = cp.Graph.from_scipy(P.Lc)
+    Lrt, Lct = cp.Graph.from_scipy(P.Lr_til), cp.Graph.from_scipy(P.Lc_til)
+    om_c = torch.from_numpy(P.omega_c).to(dev)
+    Y = torch.from_numpy(P.Ytil).to(dt).to(dev)
+    init = P.meta["init"]
+    J = args.fista_iters
+    infos = {}
+
+    def step():
+        Xt, fi = cp.frpcag(Y, Lrt, Lct, P.gamma_r, P.gamma_c, P.lmax_r_til, P.lmax_c_til,
+                           max_iter=J)
+        lab, slab, _, ci = cp.cluster_decode(Xt, om_c, P.n, Lc, init, tol=tol)
+        infos["fista"], infos["cluster"], infos["labels"] = fi, ci, lab
+        return lab
+
+    for w in range(args.warmup):
+        step()
+        c = infos["cluster"]
+        log(f"[bench] warmup {w + 1}/{args.warmup}: k-means {c['kmeans_iters']} it, CG "
+            f"{c['cg_iters']} it, decoder {c['ms']:.1f} ms")
+    cp.profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_f, ms_f = cp.get_profile("fista")
+    cp.profiling(False)
+    c = infos["cluster"]
+    ent = P.rho_r * P.rho_c
+    graph = (P.Lr_til.nnz + P.Lc_til.nnz) * 12 + 4 * (P.rho_r + P.rho_c + 2)
+    bytes_f = 5 * 8 * ent + graph      # read Z, Y~, S_prev; write S, Z+ (FP64) + graphs
+    avg_f = ms_f / max(n_f, 1)
+    achieved = bytes_f / (avg_f * 1e-3) / 1e9
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+    truth = P.meta["labels"]
+    got = infos["labels"].cpu().numpy()
+    k = int(P.meta["k"])
+    M = np.zeros((k, k))
+    np.add.at(M, (got, truth), 1)
+    r_, c_ = linear_sum_assignment(-M)
+    extra = {"kmeans_iters": c["kmeans_iters"], "cg_iters": c["cg_iters"],
+             "decoder_ms": c["ms"], "fista_ms_per_step": ms_f / args.steps,
+             "fista_launch_ms_avg": avg_f,
+             "clustering_accuracy_vs_generator": float(M[r_, c_].sum() / P.n)}
+    line = {
+        "metric": "clustered samples/s (FRPCAG FISTA + clustering decoder, Algorithm 3)",
+        "value": P.n * args.steps / elapsed, "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64"}.get(args.mode, "f32 in (f64 FISTA state, k-means, PCG)"),
+        "data": "synthetic",
+        "config": {"workload": f"cluster: {desc}", "p": P.p, "n": P.n, "rho_r": P.rho_r,
+                   "rho_c": P.rho_c, "k": k, "fista_iters": J, "pcg_tol": tol,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "FISTA product (gradient, prox, momentum fused; FP64)",
+                     "algorithmic_bytes_per_launch": bytes_f},
+        "extra": extra,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle (one step, FISTA extrapolated)")
+        line["cpu_baseline"] = cluster_cpu_baseline(P, J)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def run_batch(args, desc, tol):
     """The batched workload: every task's FISTA + decode in one cpca_solve_batched
     call. The roofline line is a whole-solve rate: the algorithmic bytes of all
@@ -406,6 +521,8 @@ def main(argv=None):
         return run_batch(args, desc, tol)
     if args.workload == "video-approx":
         return run_approx(args, desc, tol)
+    if args.workload == "cluster":
+        return run_cluster(args, desc, tol)
     log(f"[bench] building inputs: {args.workload}")
     P = getattr(synth, builder)(0)
     dt = torch.float64 if args.mode == "fp64" else torch.float32

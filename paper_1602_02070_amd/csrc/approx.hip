@@ -28,8 +28,8 @@ namespace {
 
 constexpr int kApproxKMax = 64;       // largest k (columns per row in the CG layout)
 constexpr int kMaxSweeps = 40;        // Jacobi sweeps before giving up
-constexpr int kUpChunk = 16;          // CG iterations per graph replay (even)
-constexpr int kUpMaxBlocks = 256;     // workgroups per graph side in the CG kernels
+constexpr int kUpChunk = 16;          // CG iterations per graph replay
+constexpr int kUpMaxBlocks = 4096;    // workgroups per graph side in the streaming CG kernels
 constexpr int kSvdMaxM = 4096;        // min(rho_r, rho_c) held in LDS by the rank kernel
 
 // ------------------------------------------------------------ block sums
@@ -261,8 +261,14 @@ k_svd_vectors(const double* __restrict__ W, const double* __restrict__ Q, int m,
 
 // ------------------------------------------------------- upsampling by CG
 // One graph side: the unknown rows (not sampled) of S solve
-// L(unknown, unknown) x = -L(unknown, sampled) R column by column. Vectors
-// are c x KP row-major; the sampled rows of r, z, p and q stay zero.
+// L(unknown, unknown) x = -L(unknown, sampled) R column by column, one
+// Jacobi-preconditioned CG per column. Vectors are c x KP row-major; the
+// sampled rows of r, z, p and q stay zero. The streaming kernels (start,
+// product, update, p-update) run on as many workgroups as the rows need and
+// write per-workgroup partial sums of every column. A reduction kernel with
+// one workgroup per (side, column) then sums them in a fixed order and takes
+// every scalar decision of that column (alpha, beta, convergence,
+// breakdown): each scalar has a single writer.
 struct UpSide {
   const int32_t* rp = nullptr;   // CSR of the full c x c Laplacian (caller's, FP64)
   const int32_t* ci = nullptr;
@@ -272,22 +278,24 @@ struct UpSide {
   const double* R = nullptr;     // sampled values (rho x KP)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double* S = nullptr;           // upsampled vectors (c x KP), the result
-  double* pa = nullptr;          // nb x KP partials (product, norms)
-  double* pb = nullptr;          // nb x 2 KP partials (start, update)
-  double* scal = nullptr;        // per column: rz[2], rr[2], bb, thr (6 KP doubles)
-  int* state = nullptr;          // per column: done, iters (2 KP ints)
+  double* pa = nullptr;          // KP x nb partials (product, norms)
+  double* pb = nullptr;          // 2 x KP x nb partials (start, update)
+  double* scal = nullptr;        // per column: rz, rr, bb, thr, alpha, beta (6 x kApproxKMax)
+  int* state = nullptr;          // per column: done, iters (2 x kApproxKMax)
   int c = 0, nb = 0;
 };
 
-// scal layout
-__device__ __forceinline__ double* s_rz(const UpSide& s, int par) { return s.scal + par * kApproxKMax; }
-__device__ __forceinline__ double* s_rr(const UpSide& s, int par) { return s.scal + (2 + par) * kApproxKMax; }
-__device__ __forceinline__ double* s_bb(const UpSide& s) { return s.scal + 4 * kApproxKMax; }
-__device__ __forceinline__ double* s_thr(const UpSide& s) { return s.scal + 5 * kApproxKMax; }
+// scal / state layout
+__device__ __forceinline__ double* s_rz(const UpSide& s) { return s.scal; }
+__device__ __forceinline__ double* s_rr(const UpSide& s) { return s.scal + kApproxKMax; }
+__device__ __forceinline__ double* s_bb(const UpSide& s) { return s.scal + 2 * kApproxKMax; }
+__device__ __forceinline__ double* s_thr(const UpSide& s) { return s.scal + 3 * kApproxKMax; }
+__device__ __forceinline__ double* s_alpha(const UpSide& s) { return s.scal + 4 * kApproxKMax; }
+__device__ __forceinline__ double* s_beta(const UpSide& s) { return s.scal + 5 * kApproxKMax; }
 __device__ __forceinline__ int* s_done(const UpSide& s) { return s.state; }
 __device__ __forceinline__ int* s_iters(const UpSide& s) { return s.state + kApproxKMax; }
 
-// The workgroup's side and its index within that side.
+// The workgroup's side and its index within that side (streaming kernels).
 __device__ __forceinline__ const UpSide& pick(const UpSide& a, const UpSide& b, int& local) {
   local = (int)blockIdx.x < a.nb ? (int)blockIdx.x : (int)blockIdx.x - a.nb;
   return (int)blockIdx.x < a.nb ? a : b;
@@ -302,8 +310,57 @@ __device__ __forceinline__ double lap_row(const UpSide& s, const double* __restr
   return acc;
 }
 
-// Start: S = R on sampled rows (0 elsewhere), x = 0, b = -(L S) on unknown
-// rows, r = b, z = D^-1 r, p = z. Partials: <r, z>, <r, r>.
+// Writes the workgroup's per-column sums of NV values per thread (thread t
+// holds column t % KP) to part[g][c][lb], in a fixed-order LDS tree. The
+// partials of one column are contiguous, so the reductions read them
+// coalesced.
+template <int NV>
+__device__ void store_col_partials(const double (&acc)[NV], double* part, int lb, int nb, int KP) {
+  __shared__ double red[NV][kThreads];
+#pragma unroll
+  for (int g = 0; g < NV; ++g) red[g][threadIdx.x] = acc[g];
+  for (int st = kThreads / 2; st >= KP; st >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < st) {
+#pragma unroll
+      for (int g = 0; g < NV; ++g) red[g][threadIdx.x] += red[g][threadIdx.x + st];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < KP) {
+#pragma unroll
+    for (int g = 0; g < NV; ++g) part[((size_t)g * KP + threadIdx.x) * nb + lb] = red[g][threadIdx.x];
+  }
+}
+
+// Column total of group g over the side's nb workgroups, summed by the whole
+// workgroup in a fixed order (every thread receives it).
+__device__ double col_sum(const double* part, int nb, int KP, int g, int c) {
+  double t[1] = {0.0};
+  const double* col = part + ((size_t)g * KP + c) * nb;
+  for (int b = threadIdx.x; b < nb; b += kThreads) t[0] += col[b];
+  block_sum<1>(t);
+  return t[0];
+}
+
+// Per-column totals of every column at once (thread t receives the total of
+// column t % KP); for the one-workgroup epilogue kernels.
+__device__ double col_total(const double* part, int nb, int KP, int g, double* red) {
+  const int c = threadIdx.x & (KP - 1);
+  const int rpb = kThreads / KP;
+  double s = 0.0;
+  const double* col = part + ((size_t)g * KP + c) * nb;
+  for (int b = (int)threadIdx.x / KP; b < nb; b += rpb) s += col[b];
+  red[threadIdx.x] = s;
+  column_tree(red, KP);
+  const double t = red[c];
+  __syncthreads();  // red is reused by the caller
+  return t;
+}
+
+// Start: S = R on sampled rows (0 elsewhere), x = 0 (pass 0); b = -(L S) on
+// unknown rows, r = b, z = D^-1 r, p = z, q = 0, partials <r, z>, <r, r>
+// (pass 1).
 __global__ void __launch_bounds__(kThreads)
 k_up_start(UpSide a, UpSide b2, int KP, int pass) {
   int lb;
@@ -329,111 +386,76 @@ k_up_start(UpSide a, UpSide b2, int KP, int pass) {
     }
   }
   if (pass == 0) return;
-  __shared__ double red[2][kThreads];
-  red[0][threadIdx.x] = acc[0];
-  red[1][threadIdx.x] = acc[1];
-  for (int st = kThreads / 2; st >= KP; st >>= 1) {
-    __syncthreads();
-    if ((int)threadIdx.x < st) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + st];
-      red[1][threadIdx.x] += red[1][threadIdx.x + st];
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < KP) {
-    s.pb[(size_t)lb * 2 * KP + threadIdx.x] = red[0][threadIdx.x];
-    s.pb[(size_t)lb * 2 * KP + KP + threadIdx.x] = red[1][threadIdx.x];
-  }
+  store_col_partials<2>(acc, s.pb, lb, s.nb, KP);
 }
 
-// Per-column totals over the side's workgroups of partials laid out as NV
-// groups of KP per workgroup (group g), summed by the whole workgroup in a
-// fixed order (strided loads, then the LDS tree). Every thread receives the
-// total of its column t % KP; all threads of the workgroup must call it.
-__device__ double col_total(const double* part, int nb, int KP, int g, int NV, double* red) {
-  const int c = threadIdx.x & (KP - 1);
-  const int rpb = kThreads / KP;
-  double s = 0.0;
-  for (int b = (int)threadIdx.x / KP; b < nb; b += rpb) s += part[(size_t)b * NV * KP + g * KP + c];
-  red[threadIdx.x] = s;
-  column_tree(red, KP);
-  const double t = red[c];
-  __syncthreads();  // red is reused by the caller
-  return t;
-}
-
-// One workgroup per side: arm the scalars from the start partials.
+// One workgroup per (side, column): arm the scalars from the start partials.
+// Columns past k, and columns with a zero right-hand side (x = 0), are done.
 __global__ void __launch_bounds__(kThreads)
 k_up_arm(UpSide a, UpSide b2, int KP, int k, double tol2) {
-  const UpSide& s = blockIdx.x == 0 ? a : b2;
-  __shared__ double red[kThreads];
-  const double rz = col_total(s.pb, s.nb, KP, 0, 2, red);
-  const double rr = col_total(s.pb, s.nb, KP, 1, 2, red);
-  const int c = threadIdx.x;
-  if (c >= KP) return;
-  s_rz(s, 0)[c] = s_rz(s, 1)[c] = rz;
-  s_rr(s, 0)[c] = s_rr(s, 1)[c] = rr;
+  const int side = blockIdx.x / KP, c = blockIdx.x % KP;
+  const UpSide& s = side == 0 ? a : b2;
+  const double rz = col_sum(s.pb, s.nb, KP, 0, c);
+  const double rr = col_sum(s.pb, s.nb, KP, 1, c);
+  if (threadIdx.x != 0) return;
+  s_rz(s)[c] = rz;
+  s_rr(s)[c] = rr;
   s_bb(s)[c] = rr;
   s_thr(s)[c] = tol2 * rr;
   s_iters(s)[c] = 0;
-  // columns past k, and columns with a zero right-hand side (x = 0), are done
   s_done(s)[c] = (c >= k || !(rr > 0.0)) ? 1 : (bad(rr) || bad(rz) ? 3 : 0);
 }
 
-// q = (L p) on unknown rows; partials <p, q>.
+// q = (L p) on unknown rows of running columns; partials <p, q>.
 __global__ void __launch_bounds__(kThreads)
 k_up_apply(UpSide a, UpSide b2, int KP) {
   int lb;
   const UpSide& s = pick(a, b2, lb);
   const int c = threadIdx.x & (KP - 1);
   const int rpb = kThreads / KP;
-  const bool live = s_done(s)[c] == 0;
-  double acc = 0.0;
-  if (live) {
+  double acc[1] = {0.0};
+  if (s_done(s)[c] == 0) {
     for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
       if (s.inv[row] >= 0) continue;  // sampled row: q stays 0
       const size_t e = (size_t)row * KP + c;
       const double qv = lap_row(s, s.p, row, c, KP);
       s.q[e] = qv;
-      acc += s.p[e] * qv;
+      acc[0] += s.p[e] * qv;
     }
   }
-  __shared__ double red[kThreads];
-  red[threadIdx.x] = acc;
-  column_tree(red, KP);
-  if ((int)threadIdx.x < KP) s.pa[(size_t)lb * KP + threadIdx.x] = red[threadIdx.x];
+  store_col_partials<1>(acc, s.pa, lb, s.nb, KP);
 }
 
-// alpha = <r, z> / <p, q>; x += alpha p; r -= alpha q; z = D^-1 r; partials
-// <r, z>, <r, r>. A column whose <r, r> is at most its threshold is marked
-// done here, where every workgroup reads the same value.
+// One workgroup per (side, column): convergence of the previous iteration
+// (<r, r> at most the threshold), breakdown (<p, q> not positive, or not
+// finite), else alpha = <r, z> / <p, q>.
 __global__ void __launch_bounds__(kThreads)
-k_up_update(UpSide a, UpSide b2, int KP, int par) {
+k_up_alpha(UpSide a, UpSide b2, int KP) {
+  const int side = blockIdx.x / KP, c = blockIdx.x % KP;
+  const UpSide& s = side == 0 ? a : b2;
+  if (s_done(s)[c] != 0) return;  // uniform over the workgroup
+  const double pq = col_sum(s.pa, s.nb, KP, 0, c);
+  if (threadIdx.x != 0) return;
+  if (s_rr(s)[c] <= s_thr(s)[c]) {
+    s_done(s)[c] = 1;
+  } else if (bad(pq) || !(pq > 0.0)) {
+    s_done(s)[c] = bad(pq) ? 3 : 2;
+  } else {
+    s_alpha(s)[c] = s_rz(s)[c] / pq;
+  }
+}
+
+// x += alpha p; r -= alpha q; z = D^-1 r on unknown rows of running columns;
+// partials <r, z>, <r, r>.
+__global__ void __launch_bounds__(kThreads)
+k_up_update(UpSide a, UpSide b2, int KP) {
   int lb;
   const UpSide& s = pick(a, b2, lb);
   const int c = threadIdx.x & (KP - 1);
   const int rpb = kThreads / KP;
-  const bool lead = lb == 0 && (int)threadIdx.x < KP;
-  __shared__ double red[2][kThreads];
-  const double pq = col_total(s.pa, s.nb, KP, 0, 1, red[0]);
-  bool live = s_done(s)[c] == 0;
-  double alpha = 0.0;
-  if (live) {
-    const double rr = s_rr(s, par)[c];
-    if (rr <= s_thr(s)[c]) {
-      if (lead) s_done(s)[c] = 1;
-      live = false;
-    } else {
-      if (bad(pq) || !(pq > 0.0)) {
-        if (lead) s_done(s)[c] = bad(pq) ? 3 : 2;
-        live = false;
-      } else {
-        alpha = s_rz(s, par)[c] / pq;
-      }
-    }
-  }
   double acc[2] = {0.0, 0.0};
-  if (live) {
+  if (s_done(s)[c] == 0) {
+    const double alpha = s_alpha(s)[c];
     for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
       if (s.inv[row] >= 0) continue;
       const size_t e = (size_t)row * KP + c;
@@ -446,46 +468,38 @@ k_up_update(UpSide a, UpSide b2, int KP, int par) {
       acc[1] += rv * rv;
     }
   }
-  red[0][threadIdx.x] = acc[0];
-  red[1][threadIdx.x] = acc[1];
-  for (int st = kThreads / 2; st >= KP; st >>= 1) {
-    __syncthreads();
-    if ((int)threadIdx.x < st) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + st];
-      red[1][threadIdx.x] += red[1][threadIdx.x + st];
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < KP) {
-    // written for every column: the p-update reads them only for live ones
-    s.pb[(size_t)lb * 2 * KP + threadIdx.x] = red[0][threadIdx.x];
-    s.pb[(size_t)lb * 2 * KP + KP + threadIdx.x] = red[1][threadIdx.x];
-  }
+  store_col_partials<2>(acc, s.pb, lb, s.nb, KP);
 }
 
-// beta = <r, z>_new / <r, z>; p = z + beta p; the new scalars go to the
-// other parity.
+// One workgroup per (side, column): beta = <r, z>_new / <r, z>; the new
+// scalars replace the old ones.
 __global__ void __launch_bounds__(kThreads)
-k_up_pupdate(UpSide a, UpSide b2, int KP, int par) {
+k_up_beta(UpSide a, UpSide b2, int KP) {
+  const int side = blockIdx.x / KP, c = blockIdx.x % KP;
+  const UpSide& s = side == 0 ? a : b2;
+  if (s_done(s)[c] != 0) return;
+  const double rz_new = col_sum(s.pb, s.nb, KP, 0, c);
+  const double rr_new = col_sum(s.pb, s.nb, KP, 1, c);
+  if (threadIdx.x != 0) return;
+  if (bad(rz_new) || bad(rr_new)) {
+    s_done(s)[c] = 3;
+    return;
+  }
+  s_beta(s)[c] = rz_new / s_rz(s)[c];
+  s_rz(s)[c] = rz_new;
+  s_rr(s)[c] = rr_new;
+  s_iters(s)[c] += 1;
+}
+
+// p = z + beta p on unknown rows of running columns.
+__global__ void __launch_bounds__(kThreads)
+k_up_pupdate(UpSide a, UpSide b2, int KP) {
   int lb;
   const UpSide& s = pick(a, b2, lb);
   const int c = threadIdx.x & (KP - 1);
   const int rpb = kThreads / KP;
-  const bool lead = lb == 0 && (int)threadIdx.x < KP;
-  __shared__ double red[kThreads];
-  const double rz_new = col_total(s.pb, s.nb, KP, 0, 2, red);
-  const double rr_new = col_total(s.pb, s.nb, KP, 1, 2, red);
   if (s_done(s)[c] != 0) return;  // no barrier below
-  if (bad(rz_new) || bad(rr_new)) {
-    if (lead) s_done(s)[c] = 3;
-    return;
-  }
-  const double beta = rz_new / s_rz(s, par)[c];
-  if (lead) {
-    s_rz(s, par ^ 1)[c] = rz_new;
-    s_rr(s, par ^ 1)[c] = rr_new;
-    s_iters(s)[c] += 1;
-  }
+  const double beta = s_beta(s)[c];
   for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
     if (s.inv[row] >= 0) continue;
     const size_t e = (size_t)row * KP + c;
@@ -501,7 +515,7 @@ k_up_finish(UpSide a, UpSide b2, int KP) {
   const UpSide& s = pick(a, b2, lb);
   const int c = threadIdx.x & (KP - 1);
   const int rpb = kThreads / KP;
-  double acc = 0.0;
+  double acc[1] = {0.0};
   for (int row = lb * rpb + (int)threadIdx.x / KP; row < s.c; row += s.nb * rpb) {
     const size_t e = (size_t)row * KP + c;
     double v = s.S[e];
@@ -509,12 +523,9 @@ k_up_finish(UpSide a, UpSide b2, int KP) {
       v = s.x[e];
       s.S[e] = v;
     }
-    acc += v * v;
+    acc[0] += v * v;
   }
-  __shared__ double red[kThreads];
-  red[threadIdx.x] = acc;
-  column_tree(red, KP);
-  if ((int)threadIdx.x < KP) s.pa[(size_t)lb * KP + threadIdx.x] = red[threadIdx.x];
+  store_col_partials<1>(acc, s.pa, lb, s.nb, KP);
 }
 
 // One workgroup: w_c = scale sigma_c / (||u_c|| ||v_c||) for c < k, 0 past
@@ -523,19 +534,16 @@ __global__ void __launch_bounds__(kThreads)
 k_up_weights(UpSide a, UpSide b2, int KP, int k, const double* __restrict__ sig, double scale,
              double* __restrict__ w, double* __restrict__ rel) {
   __shared__ double red[kThreads];
-  const double nu = sqrt(col_total(a.pa, a.nb, KP, 0, 1, red));
-  const double nv = sqrt(col_total(b2.pa, b2.nb, KP, 0, 1, red));
+  const double nu = sqrt(col_total(a.pa, a.nb, KP, 0, red));
+  const double nv = sqrt(col_total(b2.pa, b2.nb, KP, 0, red));
   const int c = threadIdx.x;
   if (c >= KP) return;
   w[c] = c < k ? scale * sig[c] / (nu * nv) : 0.0;
-  // final recursive residuals (the parity of the last update is not known
-  // here, so the smaller of the two is taken; both are <= the threshold
-  // once a column has converged)
+  // final recursive residuals
   for (int side = 0; side < 2; ++side) {
     const UpSide& s = side == 0 ? a : b2;
     const double bb = s_bb(s)[c];
-    const double rr = fmin(s_rr(s, 0)[c], s_rr(s, 1)[c]);
-    rel[side * KP + c] = c < k && bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    rel[side * KP + c] = c < k && bb > 0.0 ? sqrt(s_rr(s)[c] / bb) : 0.0;
   }
 }
 
@@ -814,7 +822,7 @@ cpca_status upsample_solve(cpca_handle h, const UpSide& A, const UpSide& B, int 
   LAUNCHCHK();
   k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 1);
   LAUNCHCHK();
-  k_up_arm<<<nsides, kThreads, 0, st>>>(A, B, KP, k, tol * tol);
+  k_up_arm<<<nsides * KP, kThreads, 0, st>>>(A, B, KP, k, tol * tol);
   LAUNCHCHK();
   auto all_done = [&]() {
     for (int side = 0; side < nsides; ++side)
@@ -827,17 +835,19 @@ cpca_status upsample_solve(cpca_handle h, const UpSide& A, const UpSide& B, int 
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipEvent_t ev;
   hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-  auto enqueue = [&](hipStream_t s2, int par) -> hipError_t {
+  auto enqueue = [&](hipStream_t s2) -> hipError_t {
     k_up_apply<<<gup, kThreads, 0, s2>>>(A, B, KP);
-    k_up_update<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
-    k_up_pupdate<<<gup, kThreads, 0, s2>>>(A, B, KP, par);
+    k_up_alpha<<<nsides * KP, kThreads, 0, s2>>>(A, B, KP);
+    k_up_update<<<gup, kThreads, 0, s2>>>(A, B, KP);
+    k_up_beta<<<nsides * KP, kThreads, 0, s2>>>(A, B, KP);
+    k_up_pupdate<<<gup, kThreads, 0, s2>>>(A, B, KP);
     return hipGetLastError();
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   if (err == hipSuccess && max_iter >= kUpChunk) {
     err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int j = 0; j < kUpChunk && err == hipSuccess; ++j) err = enqueue(cs, j & 1);
+    for (int j = 0; j < kUpChunk && err == hipSuccess; ++j) err = enqueue(cs);
     const hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (err == hipSuccess) err = e2;
     if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -851,7 +861,7 @@ cpca_status upsample_solve(cpca_handle h, const UpSide& A, const UpSide& B, int 
       err = hipGraphLaunch(exec, cs);
       it += kUpChunk;
     } else {
-      err = enqueue(cs, it & 1);
+      err = enqueue(cs);
       it += 1;
     }
     if (err == hipSuccess) err = hipEventRecord(ev, cs);
@@ -1214,8 +1224,8 @@ cpca_status run_cluster(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c
   for (int c = 0; c < k; ++c) {
     const int dc = hstate[(size_t)c];
     it_max = std::max(it_max, hstate[(size_t)kApproxKMax + c]);
-    const double bb = hscal[(size_t)4 * kApproxKMax + c];
-    const double rr = std::min(hscal[(size_t)2 * kApproxKMax + c], hscal[(size_t)3 * kApproxKMax + c]);
+    const double bb = hscal[(size_t)2 * kApproxKMax + c];
+    const double rr = hscal[(size_t)kApproxKMax + c];
     if (bb > 0.0) rel = std::max(rel, std::sqrt(rr / bb));
     if (dc != 1) worst = std::max(worst, dc == 0 ? 1 : dc);
   }
