@@ -334,11 +334,15 @@ cpca_status cpca_get_profile(cpca_handle h, const char* family,
  * CPCA_TUNE_CACHE naming a file, choices are also appended to it and read
  * back by cpca_create). use_lds in {-1, 0, 1}: -1 = automatic, 1 = stage the
  * workgroup's rows in LDS when they fit in 64 KiB, 0 = gather the X L_c
- * operands from global memory. kernel in {-1, 0, 1, 2} is the preference for
- * a banded L_c (most entries within 8 or 16 of the diagonal): -1 = automatic
- * (row panels where L_r rows hold at most 16 off-diagonal entries, else
- * column strips), 0 = row kernel, 1 = column strips, 2 = row panels (falls back to
- * column strips when a row of L_r is too long). Shapes differ only in the
+ * operands from global memory. kernel in {-1, 0, 1, 2, 3} is the preference
+ * for a banded L_c (most entries within 8 or 16 of the diagonal): -1 =
+ * automatic (row panels where L_r rows hold at most 16 off-diagonal entries,
+ * else column strips; for bands up to 8 wide the panel variant of 3), 0 = row
+ * kernel, 1 = column strips, 2 = row panels that prefetch the next panel into
+ * registers (two waves per SIMD; falls back to column strips when a row of
+ * L_r is too long), 3 = row panels that load each panel just before staging
+ * it (three waves per SIMD, bands up to 8 wide; the autotuner times both).
+ * Shapes differ only in the
  * order in which an output's terms are summed (the row-panel kernel adds the
  * diagonal of L_r first) and in the grid-level reduction order of the CG
  * scalars; every shape is deterministic run to run.

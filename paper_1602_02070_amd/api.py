@@ -64,7 +64,7 @@ def profiling(enable: bool, h=None) -> None:
     _check(lib.cpca_set_profiling(h or handle(), int(bool(enable))), "cpca_set_profiling")
 
 
-KERNELS = {"auto": -1, "rows": 0, "strip": 1, "panel": 2}
+KERNELS = {"auto": -1, "rows": 0, "strip": 1, "panel": 2, "panel_lo": 3}
 
 
 def set_apply_config(rows_per_block: int = 0, use_lds: int = -1, kernel: str = "auto",
@@ -72,7 +72,7 @@ def set_apply_config(rows_per_block: int = 0, use_lds: int = -1, kernel: str = "
     """Launch shape of the fused two-sided product (0 / -1 = automatic).
 
     kernel: preference for a banded L_c, one of "auto", "rows", "strip",
-    "panel" (see cpca_set_apply_config)."""
+    "panel", "panel_lo" (see cpca_set_apply_config)."""
     lib = _lib.load()
     _check(lib.cpca_set_apply_config(h or handle(), int(rows_per_block), int(use_lds),
                                      KERNELS[kernel]),

@@ -470,6 +470,7 @@ struct ApplyCfg {
   int bw = 0;   // band half-width of L_c (0: sliced ELL only)
   bool strip = false;  // column-strip kernel (needs bw > 0 and full vectors)
   bool panel = false;  // row-panel gather kernel (needs bw > 0, full vectors, panel tables)
+  bool plo = false;    // ... in its variant without cross-panel prefetch (three waves per SIMD)
   int npan = 0;        // panels in the staged image
 };
 
@@ -515,6 +516,10 @@ ApplyCfg choose_cfg(cpca_handle h, int64_t p, int64_t n, size_t elem, int band =
       c.strip = h->force_band != 2;
       if (c.strip && allow_panel && h->force_kernel != 1) {
         c.panel = true;
+        // bands up to 8 wide: the variant without cross-panel prefetch
+        // (three waves per SIMD; 0.333 against 0.372 ms on the video-shaped
+        // workload in FP32) unless the prefetching kernel is asked for
+        c.plo = h->force_kernel != 2 && c.bw <= 8;
         c.strip = false;
       }
     }
@@ -535,6 +540,7 @@ inline void set_panels(ApplyCfg& c, int npan) {
   c.npan = npan;
   if (c.panel && npan == 0) {
     c.panel = false;
+    c.plo = false;
     c.strip = true;
   }
 }
@@ -600,7 +606,7 @@ hipError_t launch_strip_t(cpca_handle h, const T* X, int p, int n, const DevGrap
   return hipGetLastError();
 }
 
-template <typename T, int BW, class Epi>
+template <typename T, int BW, bool LO, class Epi>
 hipError_t launch_panel_t(cpca_handle h, const T* X, int p, int n, const DevGraph<T>& g,
                           const Epi& epi) {
   if (g.Lp.npan <= 0) return hipErrorInvalidValue;
@@ -609,8 +615,12 @@ hipError_t launch_panel_t(cpca_handle h, const T* X, int p, int n, const DevGrap
   const int ngroups = (g.Lp.npan + kPanelGroup - 1) / kPanelGroup;
   const int gpx = (ngroups + 7) / 8;
   static_assert(kPanelGroup <= kPanelGroupMax, "panel group");
-  k_apply_panel<T, BW, Epi><<<dim3(8 * gpx * nstrips), dim3(kThreads), 0, h->stream>>>(
-      X, p, n, g.Lp, g.Lc, g.Lb, g.mc, kPanelGroup, ngroups, gpx, epi);
+  if constexpr (LO)
+    k_apply_panel_lo<T, BW, Epi><<<dim3(8 * gpx * nstrips), dim3(kThreads), 0, h->stream>>>(
+        X, p, n, g.Lp, g.Lc, g.Lb, g.mc, kPanelGroup, ngroups, gpx, epi);
+  else
+    k_apply_panel<T, BW, Epi><<<dim3(8 * gpx * nstrips), dim3(kThreads), 0, h->stream>>>(
+        X, p, n, g.Lp, g.Lc, g.Lb, g.mc, kPanelGroup, ngroups, gpx, epi);
   return hipGetLastError();
 }
 
@@ -620,9 +630,16 @@ hipError_t launch_apply_r(cpca_handle h, const ApplyCfg& cfg, const T* X, int p,
   constexpr int W = (int)(16 / sizeof(T));
   if (cfg.panel) {
     if (cfg.vec != W || g.Lp.npan != cfg.npan) return hipErrorInvalidValue;
-    if (cfg.bw == 6) return launch_panel_t<T, 6>(h, X, p, n, g, epi);
-    if (cfg.bw == 8) return launch_panel_t<T, 8>(h, X, p, n, g, epi);
-    if (cfg.bw == 16) return launch_panel_t<T, 16>(h, X, p, n, g, epi);
+    // the variant without prefetch exists for bands up to 8 wide (the
+    // 16-wide band's registers alone exceed three waves per SIMD)
+    if (cfg.plo && cfg.bw <= 8) {
+      if (cfg.bw == 6) return launch_panel_t<T, 6, true>(h, X, p, n, g, epi);
+      if (cfg.bw == 8) return launch_panel_t<T, 8, true>(h, X, p, n, g, epi);
+      return hipErrorInvalidValue;
+    }
+    if (cfg.bw == 6) return launch_panel_t<T, 6, false>(h, X, p, n, g, epi);
+    if (cfg.bw == 8) return launch_panel_t<T, 8, false>(h, X, p, n, g, epi);
+    if (cfg.bw == 16) return launch_panel_t<T, 16, false>(h, X, p, n, g, epi);
     return hipErrorInvalidValue;
   }
   if (cfg.strip) {
@@ -708,21 +725,22 @@ inline std::string tune_key(const char* kind, size_t elem, int64_t p, int64_t n,
 }
 
 // Cached shape: rows per workgroup and a mode (0: no LDS, 1: LDS rows,
-// 2: column strips, 3: row panels).
+// 2: column strips, 3: row panels, 4: row panels without prefetch).
 inline bool tune_lookup(cpca_handle h, const std::string& key, ApplyCfg& c) {
   for (const auto& kv : h->tuned)
     if (kv.first == key) {
       c.R = kv.second.first;
       c.lds = kv.second.second != 0;
       c.strip = kv.second.second == 2;
-      c.panel = kv.second.second == 3;
+      c.panel = kv.second.second >= 3;
+      c.plo = kv.second.second == 4;
       return true;
     }
   return false;
 }
 
 inline void tune_store(cpca_handle h, const std::string& key, const ApplyCfg& c) {
-  const int mode = c.panel ? 3 : (c.strip ? 2 : (c.lds ? 1 : 0));
+  const int mode = c.panel ? (c.plo ? 4 : 3) : (c.strip ? 2 : (c.lds ? 1 : 0));
   h->tuned.push_back({key, {c.R, mode}});
   if (const char* path = std::getenv("CPCA_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
@@ -740,7 +758,7 @@ inline void tune_load_file(cpca_handle h) {
   char key[200];
   int R, lds;
   while (std::fscanf(f, "%199s %d %d", key, &R, &lds) == 3) {
-    if ((R == 1 || R == 2 || R == 4 || R == 8) && lds >= 0 && lds <= 3)
+    if ((R == 1 || R == 2 || R == 4 || R == 8) && lds >= 0 && lds <= 4)
       h->tuned.push_back({key, {R, lds}});
   }
   std::fclose(f);
@@ -756,7 +774,7 @@ cpca_status autotune(cpca_handle h, const std::string& key, int64_t ld, size_t e
     best->bw = base.bw;
     best->npan = base.npan;
     if (best->bw == 0) best->strip = false;
-    if (best->bw == 0 || best->npan == 0) best->panel = false;
+    if (best->bw == 0 || best->npan == 0) best->panel = best->plo = false;
     if (best->panel || best->strip) best->R = 1;
     return CPCA_OK;
   }
@@ -778,8 +796,13 @@ cpca_status autotune(cpca_handle h, const std::string& key, int64_t ld, size_t e
     if (base.npan > 0) {
       c.strip = false;
       c.panel = true;
+      c.plo = false;
       cands.push_back(c);
-      c.panel = false;
+      if (base.bw <= 8) {
+        c.plo = true;
+        cands.push_back(c);
+      }
+      c.panel = c.plo = false;
     }
     for (int R : {1, 2, 4}) {
       c.strip = false;

@@ -558,7 +558,7 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
   if (const char* s = std::getenv("CPCA_BATCH_COMPACT")) h->batch_compact = std::atoi(s) != 0;
   if (const char* s = std::getenv("CPCA_KERNEL")) {
     const std::string k = s;
-    h->force_kernel = k == "rows" ? 0 : k == "strip" ? 1 : k == "panel" ? 2 : -1;
+    h->force_kernel = k == "rows" ? 0 : k == "strip" ? 1 : k == "panel" ? 2 : k == "panel_lo" ? 3 : -1;
   }
   if (const char* s = std::getenv("CPCA_DEBUG")) h->debug = std::atoi(s) != 0;
   *out = h;
@@ -792,7 +792,7 @@ extern "C" cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_blo
         rows_per_block == 2 || rows_per_block == 4 || rows_per_block == 8))
     return fail(CPCA_EINVAL, "rows_per_block must be -1, 0, 1, 2, 4 or 8");
   if (use_lds < -1 || use_lds > 1) return fail(CPCA_EINVAL, "use_lds must be -1, 0 or 1");
-  if (kernel < -1 || kernel > 2) return fail(CPCA_EINVAL, "kernel must be -1, 0, 1 or 2");
+  if (kernel < -1 || kernel > 3) return fail(CPCA_EINVAL, "kernel must be -1, 0, 1, 2 or 3");
   h->force_R = rows_per_block;
   h->force_lds = use_lds;
   h->force_kernel = kernel;

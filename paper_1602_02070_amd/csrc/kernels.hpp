@@ -750,10 +750,16 @@ struct PanelDev {
   int npan;
 };
 
-template <typename T, int BW, class Epi>
-__global__ void __launch_bounds__(kThreads)
-k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> Lc, BandDev<T> Lb,
-              const uint8_t* __restrict__ mc, int G, int ngroups, int gpx, Epi epi) {
+// PF: the next panel's global loads are issued into registers before the
+// current panel is computed (more registers, two waves per SIMD); without PF
+// each panel is loaded right before it is staged, so those registers are
+// free during the computation and the kernel fits three waves per SIMD,
+// whose interleaving hides the load latency instead.
+template <typename T, int BW, class Epi, bool PF>
+__device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n,
+                                           const PanelDev<T>& pd, const SellDev<T>& Lc,
+                                           const BandDev<T>& Lb, const uint8_t* __restrict__ mc,
+                                           int G, int ngroups, int gpx, const Epi& epi) {
   if (epi.prologue()) return;
   constexpr int VEC = 16 / sizeof(T);
   constexpr int LN = kPanelLanes;
@@ -876,11 +882,17 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
         pdg = pd.diag[r0 + t];
       }
     };
-    load_idx(0);
-    load_data(0);
-    if (np > 1) load_idx(1);
+    if constexpr (PF) {
+      load_idx(0);
+      load_data(0);
+      if (np > 1) load_idx(1);
+    }
     for (int kk = 0; kk < np; ++kk) {
       const int nr = soff[1][kk + 1] - soff[1][kk];
+      if constexpr (!PF) {
+        load_idx(kk);
+        load_data(kk);
+      }
       __syncthreads();  // the previous panel's LDS reads are done
 #pragma unroll
       for (int m = 0; m < SM; ++m) vst<T, VEC>(&su[(rs + NS * m) * W + ls * VEC], px[m]);
@@ -904,9 +916,11 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
         sdg[t] = pdg;
       }
       __syncthreads();
-      if (kk + 1 < np) {
-        load_data(kk + 1);
-        if (kk + 2 < np) load_idx(kk + 2);
+      if constexpr (PF) {
+        if (kk + 1 < np) {
+          load_data(kk + 1);
+          if (kk + 2 < np) load_idx(kk + 2);
+        }
       }
       if (ok) {
         const char* sub = reinterpret_cast<const char*>(su) + ls * VEC * sizeof(T);
@@ -917,23 +931,6 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
           // entries beyond a row's own count (up to its wave's largest) have
           // value 0 and offset 0, so the loop bound is wave-uniform
           const int cnt = __builtin_amdgcn_readfirstlane(mt.w);
-          uint16_t id[KR];
-#pragma unroll
-          for (int q = 0; q < KR; q += 8) {
-            const uint4 v = *reinterpret_cast<const uint4*>(&sidx[j * KR + q]);
-            id[q + 0] = v.x & 0xffff; id[q + 1] = v.x >> 16;
-            id[q + 2] = v.y & 0xffff; id[q + 3] = v.y >> 16;
-            id[q + 4] = v.z & 0xffff; id[q + 5] = v.z >> 16;
-            id[q + 6] = v.w & 0xffff; id[q + 7] = v.w >> 16;
-          }
-          T wv[KR];
-#pragma unroll
-          for (int q = 0; q < KR; q += VEC) {
-            T w4[VEC];
-            vld<T, VEC>(&swt[j * KR + q], w4);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) wv[q + v] = w4[v];
-          }
           T win[2 * PAD + VEC];
 #pragma unroll
           for (int q = 0; q < 2 * PAD + VEC; q += VEC) {
@@ -954,13 +951,31 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
             accc[v] = T(0);
             mx[v] = (mri & mcv[v]) ? xv[v] : T(0);
           }
+          // local byte offsets and weights are read from LDS 8 entries at
+          // a time, so only one chunk of them is live in registers
 #pragma unroll
-          for (int e = 0; e < KR; ++e) {
-            if (e < cnt) {
-              T u4[VEC];
-              vld<T, VEC>(reinterpret_cast<const T*>(sub + id[e]), u4);
+          for (int q = 0; q < KR; q += 8) {
+            if (q < cnt) {
+              const uint4 iv = *reinterpret_cast<const uint4*>(&sidx[j * KR + q]);
+              const uint32_t iw[4] = {iv.x, iv.y, iv.z, iv.w};
+              T wv[8];
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) accr[v] += wv[e] * u4[v];
+              for (int h = 0; h < 8; h += VEC) {
+                T w4[VEC];
+                vld<T, VEC>(&swt[j * KR + q + h], w4);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) wv[h + v] = w4[v];
+              }
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                if (q + e < cnt) {
+                  const uint32_t off = (e & 1) ? (iw[e >> 1] >> 16) : (iw[e >> 1] & 0xffffu);
+                  T u4[VEC];
+                  vld<T, VEC>(reinterpret_cast<const T*>(sub + off), u4);
+#pragma unroll
+                  for (int v = 0; v < VEC; ++v) accr[v] += wv[e] * u4[v];
+                }
+              }
             }
           }
 #pragma unroll
@@ -982,6 +997,21 @@ k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> 
     }
   }
   if (epi.partials) block_partials<Epi::NV>(acc, epi.partials);
+}
+
+template <typename T, int BW, class Epi>
+__global__ void __launch_bounds__(kThreads)
+k_apply_panel(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> Lc, BandDev<T> Lb,
+              const uint8_t* __restrict__ mc, int G, int ngroups, int gpx, Epi epi) {
+  panel_body<T, BW, Epi, true>(X, p, n, pd, Lc, Lb, mc, G, ngroups, gpx, epi);
+}
+
+template <typename T, int BW, class Epi>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+k_apply_panel_lo(const T* __restrict__ X, int p, int n, PanelDev<T> pd, SellDev<T> Lc,
+                 BandDev<T> Lb, const uint8_t* __restrict__ mc, int G, int ngroups, int gpx,
+                 Epi epi) {
+  panel_body<T, BW, Epi, false>(X, p, n, pd, Lc, Lb, mc, G, ngroups, gpx, epi);
 }
 
 // ---------------------------------------------------------------------------

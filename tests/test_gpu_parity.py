@@ -74,7 +74,7 @@ def test_apply_matches_oracle_random_graphs(shape, dtype):
 
 @pytest.mark.parametrize("n", [333, 600, 1100])
 @pytest.mark.parametrize("R,lds,kernel", [(0, -1, "auto"), (0, -1, "strip"), (0, -1, "panel"),
-                                          (0, -1, "rows"), (1, 1, "auto"), (2, 1, "auto"),
+                                          (0, -1, "panel_lo"), (0, -1, "rows"), (1, 1, "auto"), (2, 1, "auto"),
                                           (4, 1, "auto"), (8, 1, "auto"), (1, 0, "auto"),
                                           (4, 0, "auto")])
 def test_apply_every_launch_shape(R, lds, kernel, n):
@@ -101,7 +101,7 @@ def test_apply_every_launch_shape(R, lds, kernel, n):
         cp.set_apply_config(0, -1)
 
 
-@pytest.mark.parametrize("kernel", ["panel", "strip", "rows"])
+@pytest.mark.parametrize("kernel", ["panel", "panel_lo", "strip", "rows"])
 @pytest.mark.parametrize("shape,n,K", [((48, 61), 1024, 10), ((30, 37), 1000, 10),
                                        ((20, 25), 512, 20)])
 def test_apply_banded_many_panels(kernel, shape, n, K):
@@ -440,7 +440,7 @@ def test_decode_with_isolated_nodes_in_both_graphs():
                                    np.arange(596, 600)])).astype(np.int32)
     Xtil = rng.standard_normal((len(om_r), len(om_c)))
     ref = OD.decode(Xtil, p, n, om_r, om_c, Lr, Lc, 1.1, 0.6, method="cg", tol=1e-13)
-    for kernel in ("panel", "strip", "rows"):
+    for kernel in ("panel", "panel_lo", "strip", "rows"):
         cp.set_apply_config(0, -1, kernel)
         try:
             X64, i64, X32, i32 = _decode_both(Xtil, om_r, om_c, p, n, Lr, Lc, 1.1, 0.6)
