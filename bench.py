@@ -620,7 +620,7 @@ def main(argv=None):
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(args.workload, args.mode),
                      "traffic_unit": "bytes per launch", "kernel_source_hash": kernel_source_hash(),
-                     "kernel": "fused two-sided SpMM with CG epilogue (row-panel gather kernel k_apply_panel for this banded L_c)",
+                     "kernel": "fused two-sided SpMM with CG epilogue (row-panel gather kernel k_apply_panel_lo for this banded L_c)",
                      "algorithmic_bytes_per_launch": bytes_apply},
         "extra": extra,
     }
