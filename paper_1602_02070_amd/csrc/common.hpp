@@ -474,7 +474,21 @@ struct ApplyCfg {
   int npan = 0;        // panels in the staged image
 };
 
-constexpr int kPanelGroup = 2;  // consecutive panels per workgroup of the panel kernel
+// Consecutive panels per workgroup of the panel kernels: the largest G <= 8
+// whose panel groups fill the 8 per-XCD ranges of a strip to within 4 % (an
+// empty range ends the launch early on its XCD), else 2. Fewer, longer
+// workgroups load the band diagonals into registers fewer times; on the
+// video-shaped operands (324 panels) G = 7 gives 0.322 ms against 0.334 ms
+// for G = 2 (FP32), while G = 5 and 8, which leave 10-15 % of the ranges
+// empty, gave 0.344 and 0.357 ms.
+inline int panel_group(int npan) {
+  for (int G = 8; G >= 2; --G) {
+    const int ng = (npan + G - 1) / G;
+    const int slots = 8 * ((ng + 7) / 8);
+    if (ng >= 8 && (slots - ng) * 25 <= slots) return G;
+  }
+  return 2;
+}
 
 constexpr int kStripRows = 16;  // rows per workgroup of the column-strip kernel
 
@@ -550,7 +564,8 @@ inline void set_panels(ApplyCfg& c, int npan) {
 inline int panel_grid(int npan, int n, int vec) {
   const int w = kPanelLanes * vec;
   const int nstrips = (n + w - 1) / w;
-  const int ngroups = (npan + kPanelGroup - 1) / kPanelGroup;
+  const int G = panel_group(npan);
+  const int ngroups = (npan + G - 1) / G;
   return 8 * ((ngroups + 7) / 8) * nstrips;
 }
 
@@ -612,15 +627,16 @@ hipError_t launch_panel_t(cpca_handle h, const T* X, int p, int n, const DevGrap
   if (g.Lp.npan <= 0) return hipErrorInvalidValue;
   constexpr int W = kPanelLanes * (int)(16 / sizeof(T));
   const int nstrips = (n + W - 1) / W;
-  const int ngroups = (g.Lp.npan + kPanelGroup - 1) / kPanelGroup;
+  const int G = panel_group(g.Lp.npan);
+  const int ngroups = (g.Lp.npan + G - 1) / G;
   const int gpx = (ngroups + 7) / 8;
-  static_assert(kPanelGroup <= kPanelGroupMax, "panel group");
+  static_assert(8 <= kPanelGroupMax, "panel group");
   if constexpr (LO)
     k_apply_panel_lo<T, BW, Epi><<<dim3(8 * gpx * nstrips), dim3(kThreads), 0, h->stream>>>(
-        X, p, n, g.Lp, g.Lc, g.Lb, g.mc, kPanelGroup, ngroups, gpx, epi);
+        X, p, n, g.Lp, g.Lc, g.Lb, g.mc, G, ngroups, gpx, epi);
   else
     k_apply_panel<T, BW, Epi><<<dim3(8 * gpx * nstrips), dim3(kThreads), 0, h->stream>>>(
-        X, p, n, g.Lp, g.Lc, g.Lb, g.mc, kPanelGroup, ngroups, gpx, epi);
+        X, p, n, g.Lp, g.Lc, g.Lb, g.mc, G, ngroups, gpx, epi);
   return hipGetLastError();
 }
 
