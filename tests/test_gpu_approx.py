@@ -170,3 +170,24 @@ def test_approx_decode_video_shape_sampled_entries():
     print(f"[approx] video k {k} sweeps {info['svd_sweeps']} iters {info['iters_r']}/"
           f"{info['iters_c']} {info['ms']:.1f} ms, sampled rel.err {e:.2e}", flush=True)
     assert e <= 1e-5
+
+
+@pytest.mark.parametrize("k_max", [20, 40])
+def test_approx_decode_wide_column_layouts(k_max):
+    # k = 20 and 40 kept values: the CG panels are 32 and 64 columns wide and
+    # the rank-k output takes its one-column-per-thread path (KP > 16)
+    P = synth.small_problem(66, p_shape=(16, 18), n=310, frac=0.3, rank=4)
+    print(f"[case] approx wide layout k_max {k_max}: {P.p}x{P.n}, Xtil {P.Ytil.shape}", flush=True)
+    d = dev_problem(P, torch.float64)
+    X_ref, ref = OA.approx_decode(P.Ytil, P.p, P.n, P.omega_r, P.omega_c, P.Lr, P.Lc,
+                                  ratio=0.0, k_max=k_max)
+    assert ref["k"] == k_max
+    X, sig, info = cp.approx_decode(d["Ytil"], d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"],
+                                    sigma_ratio=0.0, k_max=k_max, tol=TOL)
+    assert info["status"] == 0 and info["k"] == k_max
+    # the 40 leading singular values of this matrix are distinct (X is unique)
+    s = ref["sigma"][:k_max]
+    assert np.min(np.diff(-s) / s[0]) > 1e-8
+    e = rel(host(X), X_ref)
+    print(f"[approx] wide k {k_max}: rel.err {e:.2e}", flush=True)
+    assert e <= 1e-8

@@ -134,3 +134,12 @@ def test_cluster_decode_digits_shape():
     info, err, ties = _check(P, Xt, "fp32", P.meta["init"])
     print(f"[cluster] digits: kmeans {info['kmeans_iters']} it, CG {info['cg_iters']} it, "
           f"{info['ms']:.1f} ms, C err {err:.1e}, near-ties {ties}", flush=True)
+
+
+def test_cluster_decode_many_clusters():
+    # 33 clusters: the indicator panels are 64 columns wide
+    P = synth.cluster_digits(2, n=4000, side=8, k=33, frac_c=0.1)
+    print(f"[case] cluster k 33: n {P.n} rho_c {P.rho_c}", flush=True)
+    info, err, ties = _check(P, P.Ytil, "fp64", P.meta["init"])
+    print(f"[cluster] k 33: kmeans {info['kmeans_iters']} it, CG {info['cg_iters']} it, "
+          f"C err {err:.1e}, near-ties {ties}", flush=True)
