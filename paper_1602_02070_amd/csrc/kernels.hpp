@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace cpca {
 
 constexpr int kWave = 64;
@@ -735,6 +737,31 @@ constexpr int kPanelGroupMax = 16;
 constexpr int kPanelRowBytes = 256;  // LDS bytes of one staged union row (16 lanes x 16 bytes)
 template <typename T> struct PanelUnion { static constexpr int value = sizeof(T) == 4 ? 160 : 128; };
 
+// Lane E of every 16-lane row of the wave, broadcast to the whole row (DPP
+// row_newbcast): a register-only move.
+template <int E>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + E, 0xf, 0xf, false);
+}
+template <int E>
+__device__ __forceinline__ float row_bcast_t(float v) {
+  return __builtin_bit_cast(float, row_bcast<E>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int E>
+__device__ __forceinline__ double row_bcast_t(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = row_bcast<E>((uint32_t)u), hi = row_bcast<E>((uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, lo | (hi << 32));
+}
+// f(integral_constant<int, E>) for E = B .. N - 1, in order.
+template <int B, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < N) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, N>(f);
+  }
+}
+
 template <typename T>
 struct PanelDev {
   const int* u_off;        // npan + 1 offsets into u
@@ -776,6 +803,7 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
   constexpr int EM = (EV + kThreads - 1) / kThreads;
   constexpr int H = kWave * VEC;                 // SELL slice height
   static_assert(BW > 0 && UM % NS == 0 && KR % 8 == 0 && RM * KR == 4 * kThreads, "panel shape");
+  static_assert(KR == LN, "one table entry per lane of a row slot");
   static_assert(W * sizeof(T) == kPanelRowBytes && UM * kPanelRowBytes <= 65536, "offset table");
   __shared__ __align__(16) T su[UM * W];
   __shared__ __align__(16) T shl[RM * PAD];
@@ -922,7 +950,9 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
           if (kk + 2 < np) load_idx(kk + 2);
         }
       }
-      if (ok) {
+      {
+        // every lane takes part (lanes past n compute on zeros and store
+        // nothing), so the row broadcasts below always read active lanes
         const char* sub = reinterpret_cast<const char*>(su) + ls * VEC * sizeof(T);
         for (int j = rs; j < nr; j += NS) {
           const int4 mt = smeta[j];
@@ -951,33 +981,22 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
             accc[v] = T(0);
             mx[v] = (mri & mcv[v]) ? xv[v] : T(0);
           }
-          // local byte offsets and weights are read from LDS 8 entries at
-          // a time, so only one chunk of them is live in registers
+          // lane ls of the row slot holds entry ls of the row's offset and
+          // weight tables (one small LDS read per lane); entry e reaches the
+          // 16 lanes of the slot, which form one DPP row, by a row broadcast
+          const uint32_t il = sidx[j * KR + ls];
+          const T wl = swt[j * KR + ls];
+          static_for<0, KR>([&](auto ec) {
+            constexpr int e = decltype(ec)::value;
+            if (e < cnt) {
+              const uint32_t off = row_bcast<e>(il);
+              const T w = row_bcast_t<e>(wl);
+              T u4[VEC];
+              vld<T, VEC>(reinterpret_cast<const T*>(sub + off), u4);
 #pragma unroll
-          for (int q = 0; q < KR; q += 8) {
-            if (q < cnt) {
-              const uint4 iv = *reinterpret_cast<const uint4*>(&sidx[j * KR + q]);
-              const uint32_t iw[4] = {iv.x, iv.y, iv.z, iv.w};
-              T wv[8];
-#pragma unroll
-              for (int h = 0; h < 8; h += VEC) {
-                T w4[VEC];
-                vld<T, VEC>(&swt[j * KR + q + h], w4);
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) wv[h + v] = w4[v];
-              }
-#pragma unroll
-              for (int e = 0; e < 8; ++e) {
-                if (q + e < cnt) {
-                  const uint32_t off = (e & 1) ? (iw[e >> 1] >> 16) : (iw[e >> 1] & 0xffffu);
-                  T u4[VEC];
-                  vld<T, VEC>(reinterpret_cast<const T*>(sub + off), u4);
-#pragma unroll
-                  for (int v = 0; v < VEC; ++v) accr[v] += wv[e] * u4[v];
-                }
-              }
+              for (int v = 0; v < VEC; ++v) accr[v] += w * u4[v];
             }
-          }
+          });
 #pragma unroll
           for (int d = 0; d <= 2 * BW; ++d)
 #pragma unroll
@@ -991,7 +1010,7 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
 #pragma unroll
             for (int v = 0; v < VEC; ++v) accc[v] += vv[v] * rowp[kk2[v]];
           }
-          epi.template apply<VEC>(row, (size_t)row * n + c0, xv, mx, accr, accc, acc);
+          if (ok) epi.template apply<VEC>(row, (size_t)row * n + c0, xv, mx, accr, accc, acc);
         }
       }
     }
