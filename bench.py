@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_apply_panel_video_fp32.md")
-KERNEL_SOURCES = ("paper_1602_02070_amd/csrc/kernels.hpp", "paper_1602_02070_amd/csrc/common.hpp")
+KERNEL_SOURCES = ("paper_1602_02070_amd/csrc/kernels.hpp", "paper_1602_02070_amd/csrc/common.hpp",
+                  "paper_1602_02070_amd/csrc/panels.hpp")
 
 
 def kernel_source_hash() -> str:

@@ -159,11 +159,6 @@ cpca_status sync_collect(cpca_handle h) {
 }
 
 // ------------------------------------------------------------- preparation
-struct HostCsr {
-  int64_t n = 0, nnz = 0;
-  std::vector<int32_t> rp, ci;
-  std::vector<double> v;
-};
 
 cpca_status fetch_csr(const char* name, const cpca_csr* A, HostCsr& out) {
   out.n = A->n;
@@ -216,117 +211,6 @@ struct GraphImage {
   int npan;                     // panels of L_r rows (0: no panel tables)
   size_t o_pu_off, o_pu, o_pr_off, o_prows, o_peidx, o_pew, o_pmeta, o_pdiag;
 };
-
-// ------------------------------------------------------------------ panels
-// Row panels of L_r for the row-panel gather kernel (k_apply_panel).
-struct HostPanels {
-  int npan = 0;
-  std::vector<int32_t> u_off, u, r_off, rows, meta;  // meta: 4 ints per row
-  std::vector<uint16_t> eidx;
-  std::vector<double> ew, diag;
-};
-
-// Greedy grouping of the rows of L_r: a panel starts at the lowest row not
-// yet assigned and repeatedly takes, among the unassigned rows already in its
-// union U (the rows its L_r entries reference, itself included), the one
-// whose entries add the fewest new rows to U (ties: lowest index), while the
-// panel holds at most rmax rows and U at most umax. Rows of a panel and their
-// neighbourhoods therefore overlap, which is what makes staging U once per
-// panel cheaper than one read per entry. Returns false when a row has more
-// than kPanelK off-diagonal entries (the kernel's table width).
-inline bool build_panels(const HostCsr& Lr, const std::vector<uint8_t>& mr, int rmax, int umax,
-                         HostPanels& P) {
-  P = HostPanels{};
-  const int64_t p64 = Lr.n;
-  if (p64 <= 0 || p64 >= INT_MAX) return false;
-  const int p = (int)p64;
-  for (int i = 0; i < p; ++i) {
-    int c = 0;
-    for (int32_t e = Lr.rp[i]; e < Lr.rp[i + 1]; ++e) c += Lr.ci[e] != i;
-    if (c > kPanelK) return false;
-  }
-  std::vector<char> assigned((size_t)p, 0);
-  std::vector<int> stamp((size_t)p, -1), loc((size_t)p, -1);
-  std::vector<int> U, R, cand;
-  P.u_off.push_back(0);
-  P.r_off.push_back(0);
-  int seed = 0, k = 0;
-  for (;;) {
-    while (seed < p && assigned[(size_t)seed]) ++seed;
-    if (seed == p) break;
-    U.clear();
-    R.clear();
-    cand.clear();
-    auto added_by = [&](int v) {  // rows v would add to U
-      int c = stamp[(size_t)v] != k;
-      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e) c += stamp[(size_t)Lr.ci[e]] != k;
-      return c;
-    };
-    auto take = [&](int v) {
-      R.push_back(v);
-      assigned[(size_t)v] = 1;
-      auto ins = [&](int w) {
-        if (stamp[(size_t)w] == k) return;
-        stamp[(size_t)w] = k;
-        U.push_back(w);
-        if (!assigned[(size_t)w]) cand.push_back(w);
-      };
-      ins(v);
-      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e) ins(Lr.ci[e]);
-    };
-    take(seed);
-    while ((int)R.size() < rmax) {
-      int best = -1, bc = INT_MAX;
-      for (int c : cand) {
-        if (assigned[(size_t)c]) continue;
-        const int nc = added_by(c);
-        if (nc < bc || (nc == bc && c < best)) {
-          bc = nc;
-          best = c;
-        }
-      }
-      if (best < 0 || (int)U.size() + bc > umax) break;
-      take(best);
-    }
-    std::sort(U.begin(), U.end());
-    for (size_t i = 0; i < U.size(); ++i) loc[(size_t)U[i]] = (int)i;
-    P.u.insert(P.u.end(), U.begin(), U.end());
-    for (int v : R) {
-      const size_t base = P.eidx.size();
-      P.eidx.resize(base + kPanelK, 0);
-      P.ew.resize(base + kPanelK, 0.0);
-      int c = 0;
-      double dg = 0.0;
-      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e) {
-        if (Lr.ci[e] == v) {
-          dg += Lr.v[e];
-          continue;
-        }
-        P.eidx[base + c] = (uint16_t)(loc[(size_t)Lr.ci[e]] * kPanelRowBytes);
-        P.ew[base + c] = Lr.v[e];
-        ++c;
-      }
-      P.rows.push_back(v);
-      P.diag.push_back(dg);
-      const int m4[4] = {v, loc[(size_t)v] | (c << 16), (int)mr[(size_t)v], c};
-      P.meta.insert(P.meta.end(), m4, m4 + 4);
-    }
-    // group count: the rows j of a panel are computed by waves in groups of
-    // 4 consecutive j (j = 16 pass + 4 wave + slot); each row carries the
-    // largest count of its group
-    const size_t r0 = P.rows.size() - R.size();
-    for (size_t g = 0; g < R.size(); g += 4) {
-      int mx = 0;
-      for (size_t j = g; j < std::min(R.size(), g + 4); ++j) mx = std::max(mx, P.meta[4 * (r0 + j) + 3]);
-      for (size_t j = g; j < std::min(R.size(), g + 4); ++j) P.meta[4 * (r0 + j) + 3] = mx;
-    }
-    ++k;
-    P.u_off.push_back((int)P.u.size());
-    P.r_off.push_back((int)P.rows.size());
-  }
-  P.npan = k;
-  return true;
-}
 
 // Half-bandwidth of the diagonal (band) part of L_c: the smallest of 6, 8
 // and 16 that holds at least 90% of the entries, else 0 (sliced ELL only).
@@ -474,21 +358,6 @@ struct ApplyCfg {
   int npan = 0;        // panels in the staged image
 };
 
-// Consecutive panels per workgroup of the panel kernels: the largest G <= 8
-// whose panel groups fill the 8 per-XCD ranges of a strip to within 4 % (an
-// empty range ends the launch early on its XCD), else 2. Fewer, longer
-// workgroups load the band diagonals into registers fewer times; on the
-// video-shaped operands (324 panels) G = 7 gives 0.322 ms against 0.334 ms
-// for G = 2 (FP32), while G = 5 and 8, which leave 10-15 % of the ranges
-// empty, gave 0.344 and 0.357 ms.
-inline int panel_group(int npan) {
-  for (int G = 8; G >= 2; --G) {
-    const int ng = (npan + G - 1) / G;
-    const int slots = 8 * ((ng + 7) / 8);
-    if (ng >= 8 && (slots - ng) * 25 <= slots) return G;
-  }
-  return 2;
-}
 
 constexpr int kStripRows = 16;  // rows per workgroup of the column-strip kernel
 

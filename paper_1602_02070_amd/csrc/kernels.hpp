@@ -29,6 +29,8 @@
 
 #include <type_traits>
 
+#include "panels.hpp"
+
 namespace cpca {
 
 constexpr int kWave = 64;
@@ -716,26 +718,23 @@ k_apply_strip(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc
 // rows whose L_r neighbourhoods overlap (greedy growth on the graph of L_r);
 // the union U of a panel's neighbour rows (itself included) has at most
 // PanelUnion<T> rows. A workgroup owns one column strip of W = 16 * VEC
-// columns and G consecutive panels. Per panel it copies the strip segment of
-// every row of U into LDS once (plus a halo of PAD columns on both sides of
-// the panel's own rows), so each row of X is read about |U| / |panel| times
-// instead of once per L_r entry, and computes the panel's rows entirely from
-// LDS: L_r X from the staged union rows (local indices precomputed on the
-// host), X L_c from the band diagonals held in registers and the row's
-// window. The next panel's global loads are issued into registers before the
-// current panel is computed, so HBM traffic overlaps the LDS work.
+// columns and G consecutive panels. Per panel it copies into LDS the strip
+// segment of every row of U that is not already there from an earlier panel
+// of the group (each row into the slot the host assigned it), plus a halo of
+// PAD columns on both sides of the panel's own rows, so each row of X is read
+// about (staged rows) / p times instead of once per L_r entry, and computes
+// the panel's rows entirely from LDS: L_r X from the staged union rows (slot
+// offsets precomputed on the host), X L_c from the band diagonals held in
+// registers and the row's window. In k_apply_panel the next panel's global
+// loads are issued into registers before the current panel is computed, so
+// HBM traffic overlaps the LDS work.
 // Thread t serves row slot t / 16 (16 rows in flight) and columns
 // c0 = s * W + (t % 16) * VEC of strip s.
 // Grid: 8 * gpx * nstrips workgroups, gpx = ceil(ceil(npan / G) / 8); XCD x
 // takes panel groups [x * gpx, (x + 1) * gpx) of every strip, so panels that
 // share union rows run on the same XCD (one L2).
 // ---------------------------------------------------------------------------
-constexpr int kPanelLanes = 16;   // lanes per row slot
-constexpr int kPanelRows = 64;    // rows per panel (max)
-constexpr int kPanelK = 16;       // off-diagonal L_r entries per row (max)
-constexpr int kPanelGroupMax = 16;
-constexpr int kPanelRowBytes = 256;  // LDS bytes of one staged union row (16 lanes x 16 bytes)
-template <typename T> struct PanelUnion { static constexpr int value = sizeof(T) == 4 ? 160 : 128; };
+// (layout constants kPanel*, PanelUnion: panels.hpp)
 
 // Lane E of every 16-lane row of the wave, broadcast to the whole row (DPP
 // row_newbcast): a register-only move.
@@ -765,13 +764,14 @@ __device__ __forceinline__ void static_for(F&& f) {
 template <typename T>
 struct PanelDev {
   const int* u_off;        // npan + 1 offsets into u
-  const int* u;            // union rows of each panel
+  const int* u;            // per panel and LDS slot: the union row to stage into the slot,
+                           // -1 where the slot keeps what it holds
   const int* r_off;        // npan + 1 offsets into the per-row arrays
   const int* rows;         // output rows, panel by panel
-  const uint16_t* eidx;    // [row][kPanelK] LDS byte offset (union-local index x 256) of each
-                           // off-diagonal entry; 0 with value 0 beyond the row's count
+  const uint16_t* eidx;    // [row][kPanelK] LDS byte offset (slot x 256) of each off-diagonal
+                           // entry; the row's own slot with value 0 beyond the row's count
   const T* ew;             // [row][kPanelK] its value
-  const int4* meta;        // [row] {row, local index | count << 16, row mask, group count}:
+  const int4* meta;        // [row] {row, own slot | count << 16, row mask, group count}:
                            // group count = the largest count of the 4 rows one wave computes
   const T* diag;           // [row] diagonal entry of L_r
   int npan;
@@ -802,7 +802,7 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
   constexpr int EV = RM * KR / VEC;              // weight vectors per panel
   constexpr int EM = (EV + kThreads - 1) / kThreads;
   constexpr int H = kWave * VEC;                 // SELL slice height
-  static_assert(BW > 0 && UM % NS == 0 && KR % 8 == 0 && RM * KR == 4 * kThreads, "panel shape");
+  static_assert(BW > 0 && UM % NS == 0 && UM / NS <= 32 && KR % 8 == 0 && RM * KR == 4 * kThreads, "panel shape");
   static_assert(KR == LN, "one table entry per lane of a row slot");
   static_assert(W * sizeof(T) == kPanelRowBytes && UM * kPanelRowBytes <= 65536, "offset table");
   __shared__ __align__(16) T su[UM * W];
@@ -852,6 +852,7 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
     // Prefetch state: union row indices (next panel but one), staged values
     // and panel tables (next panel).
     int ridx[SM], hrow[HM];
+    uint32_t pmask = 0;  // bit m: slot rs + NS * m is overwritten by the rows in flight
     auto load_idx = [&](int kk) {
       const int u0 = soff[0][kk], nu = soff[0][kk + 1] - u0;
       const int r0 = soff[1][kk], nr = soff[1][kk + 1] - r0;
@@ -873,6 +874,7 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
       const int r0 = soff[1][kk], nr = soff[1][kk + 1] - r0;
 #pragma unroll
       for (int m = 0; m < SM; ++m) {
+        pmask = (m == 0 ? 0u : pmask) | (ridx[m] >= 0 ? 1u << m : 0u);
         if (ridx[m] >= 0 && ok) {
           vld<T, VEC>(X + (size_t)ridx[m] * n + c0, px[m]);
         } else {
@@ -922,8 +924,11 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
         load_data(kk);
       }
       __syncthreads();  // the previous panel's LDS reads are done
+      // rows still resident from an earlier panel of the group keep their
+      // slots; the new ones overwrite slots that this panel does not read
 #pragma unroll
-      for (int m = 0; m < SM; ++m) vst<T, VEC>(&su[(rs + NS * m) * W + ls * VEC], px[m]);
+      for (int m = 0; m < SM; ++m)
+        if (pmask >> m & 1u) vst<T, VEC>(&su[(rs + NS * m) * W + ls * VEC], px[m]);
 #pragma unroll
       for (int m = 0; m < HM; ++m) {
         const int it = t + m * kThreads;
