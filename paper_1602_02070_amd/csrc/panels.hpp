@@ -81,15 +81,33 @@ struct HostPanels {
 // within the group), then the fewest rows to U, then the lowest index, among
 // the candidates that keep |U| <= umax; it stops at rmax rows or when no
 // candidate fits.
+// The two counts of every candidate are kept up to date as U grows: a row
+// entering U leaves the counts of the candidates in its closed neighbourhood,
+// which are exactly the candidates whose closed neighbourhood holds it when
+// the pattern of L_r is symmetric (as a Laplacian's is). The chosen row is
+// recounted exactly before it is taken, so |U| <= umax holds for any pattern.
 inline void grow_panels(const HostCsr& Lr, int rmax, int umax, int Gs,
                         std::vector<std::vector<int>>& Rs, std::vector<std::vector<int>>& Us) {
   const int p = (int)Lr.n;
   Rs.clear();
   Us.clear();
   std::vector<char> assigned((size_t)p, 0);
-  std::vector<int> stamp((size_t)p, -1);
-  std::vector<int> U, R, cand;
+  std::vector<int> stamp((size_t)p, -1);  // last panel whose union holds the row
+  // live candidates of the current panel with their two counts (compact, so
+  // the choice scans contiguous memory), and each candidate's position there
+  struct Cand {
+    int nl, nu, c;
+  };
+  std::vector<Cand> cand;
+  std::vector<int> pos((size_t)p, -1);
+  std::vector<int> U, R;
   int seed = 0;
+  // f(w) for w in the closed neighbourhood of v: v and its off-diagonal entries
+  auto each_nb = [&](int v, auto&& f) {
+    f(v);
+    for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e)
+      if (Lr.ci[e] != v) f(Lr.ci[e]);
+  };
   for (int k = 0;; ++k) {
     const bool first = k % Gs == 0;
     int s = -1;
@@ -102,51 +120,73 @@ inline void grow_panels(const HostCsr& Lr, int rmax, int umax, int Gs,
       if (seed == p) break;
       s = seed;
     }
+    for (const Cand& x : cand) pos[(size_t)x.c] = -1;
     U.clear();
     R.clear();
     cand.clear();
-    // rows v would add to U: all of them, and those not resident
-    auto added_by = [&](int v, int& nl) {
+    auto drop = [&](int c) {
+      const int i = pos[(size_t)c];
+      cand[(size_t)i] = cand.back();
+      pos[(size_t)cand[(size_t)i].c] = i;
+      cand.pop_back();
+      pos[(size_t)c] = -1;
+    };
+    // rows v would add to U (returned), and how many of them are not resident
+    auto count = [&](int v, int& nl) {
       int nu = 0;
       nl = 0;
-      auto count = [&](int w) {
+      each_nb(v, [&](int w) {
         const int st = stamp[(size_t)w];
         if (st == k) return;
         ++nu;
         nl += first || st != k - 1;
-      };
-      count(v);
-      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e)
-        if (Lr.ci[e] != v) count(Lr.ci[e]);
+      });
       return nu;
     };
+    auto ins = [&](int w) {
+      const int st = stamp[(size_t)w];
+      if (st == k) return;
+      const bool fresh = first || st != k - 1;
+      stamp[(size_t)w] = k;
+      U.push_back(w);
+      each_nb(w, [&](int c) {
+        const int i = pos[(size_t)c];
+        if (i < 0) return;
+        --cand[(size_t)i].nu;
+        cand[(size_t)i].nl -= fresh;
+      });
+      if (!assigned[(size_t)w]) {
+        Cand x;
+        x.c = w;
+        x.nu = count(w, x.nl);
+        pos[(size_t)w] = (int)cand.size();
+        cand.push_back(x);
+      }
+    };
     auto take = [&](int v) {
+      if (pos[(size_t)v] >= 0) drop(v);
       R.push_back(v);
       assigned[(size_t)v] = 1;
-      auto ins = [&](int w) {
-        if (stamp[(size_t)w] == k) return;
-        stamp[(size_t)w] = k;
-        U.push_back(w);
-        if (!assigned[(size_t)w]) cand.push_back(w);
-      };
-      ins(v);
-      for (int32_t e = Lr.rp[v]; e < Lr.rp[v + 1]; ++e) ins(Lr.ci[e]);
+      each_nb(v, ins);
     };
     take(s);
     while ((int)R.size() < rmax) {
       int best = -1, bl = INT_MAX, bu = INT_MAX;
-      for (int c : cand) {
-        if (assigned[(size_t)c]) continue;
-        int nl;
-        const int nu = added_by(c, nl);
-        if ((int)U.size() + nu > umax) continue;
-        if (nl < bl || (nl == bl && (nu < bu || (nu == bu && c < best)))) {
-          bl = nl;
-          bu = nu;
-          best = c;
+      const int room = umax - (int)U.size();
+      for (const Cand& x : cand) {
+        if (x.nu > room) continue;
+        if (x.nl < bl || (x.nl == bl && (x.nu < bu || (x.nu == bu && x.c < best)))) {
+          bl = x.nl;
+          bu = x.nu;
+          best = x.c;
         }
       }
       if (best < 0) break;
+      int nl;
+      if (count(best, nl) > room) {
+        drop(best);  // miscounted (pattern not symmetric): not a candidate
+        continue;
+      }
       take(best);
     }
     std::sort(U.begin(), U.end());
@@ -158,9 +198,9 @@ inline void grow_panels(const HostCsr& Lr, int rmax, int umax, int Gs,
 // Builds the panel tables of L_r (false, and no tables, when a row has more
 // than kPanelK off-diagonal entries or umax is not in [kPanelK + 1, 256];
 // row masks mr). Phase 1 runs with the group size that panel_group gives for
-// the panel count of the previous attempt (at most three attempts). Phase 2
-// assigns the LDS slots for G = panel_group(npan), the group size the launch
-// uses: per group, the slots start empty; for each panel, every row of U that
+// panels of rmax - 1 rows on average. Phase 2 assigns the LDS slots for
+// G = panel_group(npan), the group size the launch uses (phase 1's guess only
+// affects how much is reused): per group, the slots start empty; for each panel, every row of U that
 // is resident keeps its slot, and each new row takes a slot that holds no row
 // of U (empty slots first, then the one whose row was used longest ago, then
 // the lowest slot). |U| <= umax guarantees a slot for every new row.
@@ -177,13 +217,7 @@ inline bool build_panels(const HostCsr& Lr, const std::vector<uint8_t>& mr, int 
     if (c > kPanelK) return false;
   }
   std::vector<std::vector<int>> Rs, Us;
-  int Gs = panel_group((p + rmax - 1) / rmax);
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    grow_panels(Lr, rmax, umax, Gs, Rs, Us);
-    const int g = panel_group((int)Rs.size());
-    if (g == Gs) break;
-    Gs = g;
-  }
+  grow_panels(Lr, rmax, umax, panel_group((p + rmax - 2) / (rmax - 1)), Rs, Us);
   const int npan = (int)Rs.size();
   const int G = panel_group(npan);
   P.npan = npan;
@@ -191,7 +225,14 @@ inline bool build_panels(const HostCsr& Lr, const std::vector<uint8_t>& mr, int 
   P.u_off.push_back(0);
   P.r_off.push_back(0);
   std::vector<int> rslot((size_t)p, -1), inU((size_t)p, -1);
-  std::vector<int> slot_row((size_t)umax, -1), last_use((size_t)umax, -1), fr;
+  std::vector<int> slot_row((size_t)umax, -1), last_use((size_t)umax, -1), fr((size_t)umax);
+  std::vector<int> nb((size_t)kPanelGroupMax + 2);
+  P.u.reserve((size_t)npan * umax);
+  P.rows.reserve((size_t)p);
+  P.diag.reserve((size_t)p);
+  P.meta.reserve((size_t)4 * p);
+  P.eidx.reserve((size_t)kPanelK * p);
+  P.ew.reserve((size_t)kPanelK * p);
   for (int k0 = 0; k0 < npan; k0 += G) {
     for (int s = 0; s < umax; ++s) {
       if (slot_row[(size_t)s] >= 0) rslot[(size_t)slot_row[(size_t)s]] = -1;
@@ -202,12 +243,18 @@ inline bool build_panels(const HostCsr& Lr, const std::vector<uint8_t>& mr, int 
       const std::vector<int>& U = Us[(size_t)k];
       const std::vector<int>& R = Rs[(size_t)k];
       for (int w : U) inU[(size_t)w] = k;
-      fr.clear();
+      // free slots (holding no row of U) by last use (-1: empty, else a panel
+      // k0 .. k - 1 of this group), then by index: a counting sort
+      std::fill(nb.begin(), nb.end(), 0);
+      auto bucket = [&](int s) { return last_use[(size_t)s] < 0 ? 0 : last_use[(size_t)s] - k0 + 1; };
+      auto is_free = [&](int s) {
+        return slot_row[(size_t)s] < 0 || inU[(size_t)slot_row[(size_t)s]] != k;
+      };
       for (int s = 0; s < umax; ++s)
-        if (slot_row[(size_t)s] < 0 || inU[(size_t)slot_row[(size_t)s]] != k) fr.push_back(s);
-      std::stable_sort(fr.begin(), fr.end(), [&](int a, int b) {
-        return last_use[(size_t)a] < last_use[(size_t)b];
-      });
+        if (is_free(s)) ++nb[(size_t)bucket(s) + 1];
+      for (size_t b = 1; b < nb.size(); ++b) nb[b] += nb[b - 1];
+      for (int s = 0; s < umax; ++s)
+        if (is_free(s)) fr[(size_t)nb[(size_t)bucket(s)]++] = s;
       size_t f = 0;
       const size_t ub = P.u.size();
       P.u.resize(ub + (size_t)umax, -1);
