@@ -964,7 +964,7 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
           const int row = mt.x, ctr = mt.y & 0xffff;
           const uint8_t mri = (uint8_t)mt.z;
           // entries beyond a row's own count (up to its wave's largest) have
-          // value 0 and offset 0, so the loop bound is wave-uniform
+          // value 0 and the row's own slot, so the loop bound is wave-uniform
           const int cnt = __builtin_amdgcn_readfirstlane(mt.w);
           T win[2 * PAD + VEC];
 #pragma unroll
