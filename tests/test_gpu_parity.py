@@ -137,6 +137,41 @@ def test_apply_banded_many_panels(kernel, shape, n, K):
         cp.set_apply_config(0, -1)
 
 
+@pytest.mark.parametrize("kernel", ["panel", "panel_lo"])
+def test_apply_panels_on_unstructured_rows(kernel):
+    # An irregular L_r (5-NN graph of 1500 random points in 3-D, plus 37
+    # isolated rows and a two-row component) with a banded L_c of ragged
+    # width: the panels grow along irregular neighbourhoods, so rows stay
+    # resident in LDS in irregular slot patterns across each panel group
+    _announce(f"apply panels on unstructured rows kernel={kernel}")
+    rng = np.random.default_rng(23)
+    Lg, _ = synth.knn_laplacian(rng.standard_normal((1500, 3)), 5)
+    assert (np.diff(Lg.tocsr().indptr) - 1).max() <= 16  # panel tables apply
+    pair = sp.csr_matrix(np.array([[1.0, -1.0], [-1.0, 1.0]]))
+    Lr = sp.block_diag([Lg, sp.csr_matrix((37, 37)), pair], format="csr")
+    n = 777
+    Lc, _ = synth.knn_laplacian(np.arange(float(n))[:, None], 10)
+    p = Lr.shape[0]
+    om_r = np.sort(rng.choice(p, p // 5, replace=False)).astype(np.int32)
+    om_c = np.sort(rng.choice(n, n // 6, replace=False)).astype(np.int32)
+    m_r, m_c = OD.masks(p, n, om_r, om_c)
+    gr, gc = 1.3, 0.7
+    X = rng.standard_normal((p, n))
+    cp.set_apply_config(0, -1, kernel)
+    try:
+        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+            Xt = torch.from_numpy(X).to(dtype).cuda()
+            Q, pq = cp.apply_operator(Xt, cp.Graph.from_scipy(Lr), cp.Graph.from_scipy(Lc), gr,
+                                      gc, torch.from_numpy(om_r).cuda(),
+                                      torch.from_numpy(om_c).cuda())
+            Xh = host(Xt)
+            refd = OD.apply_A(Xh, m_r, m_c, Lr, Lc, gr, gc)
+            assert np.abs(host(Q) - refd).max() <= tol * np.abs(refd).max() * 10
+            assert np.isclose(pq, np.sum(Xh * refd), rtol=1e-12 if dtype == torch.float64 else 1e-5)
+    finally:
+        cp.set_apply_config(0, -1)
+
+
 def test_fista_trajectory_matches_oracle(cfg1):
     P = cfg1
     d = dev_problem(P)
