@@ -111,8 +111,13 @@ cpca_status cpca_set_stream(cpca_handle h, void* hip_stream);
  * Lr_til      rho_r x rho_r Laplacian; Lc_til rho_c x rho_c Laplacian.
  * gamma_r/_c  >= 0 and finite.
  * lmax_r/_c   spectral norms ||L~_r||_2, ||L~_c||_2 (largest eigenvalues),
- *             > 0 when the matching gamma is > 0. The step is 1/beta' with
+ *             finite. The step is 1/beta' with
  *             beta' = 2 gamma_c lmax_c + 2 gamma_r lmax_r; beta' = 0 returns Y~.
+ *             A value <= 0 where the matching gamma is > 0 makes the library
+ *             estimate that norm itself, as cpca_laplacian_lmax does with
+ *             tol 1e-9 and at most 50000 products (the paper leaves the
+ *             method open; such runs are outside the parity contract,
+ *             which passes the exact values).
  * max_iter    J >= 0. eps >= 0: stop after iteration j when
  *             ||Z_{j+1} - Z_j||_F^2 < eps ||Z_j||_F^2; eps = 0 runs exactly J
  *             iterations.
@@ -129,6 +134,24 @@ cpca_status cpca_frpcag(cpca_handle h, cpca_mode mode,
                         double lmax_r, double lmax_c,
                         int32_t max_iter, double eps,
                         void* Xtil_out, cpca_info* info);
+
+/*
+ * Largest eigenvalue of a symmetric positive semi-definite CSR matrix (a
+ * graph Laplacian), i.e. its spectral norm, which sets the FISTA step of
+ * Section IV.B. FP64 power iteration on the device from a fixed
+ * pseudo-random positive start vector: w = L v, theta = <v, w> with
+ * ||v|| = 1, stop when ||w - theta v|| <= tol * theta (an eigenvalue then
+ * lies within tol * theta of theta) or after max_iter products.
+ * L           square CSR in device memory (structure checked as everywhere).
+ * tol         in (0, 1); max_iter >= 1.
+ * lmax        host pointer, receives theta (also on ENOCONV).
+ * info        iters = products run, rel_residual = ||w - theta v|| / theta.
+ * The estimate approaches the largest eigenvalue from below; a start vector
+ * orthogonal to its eigenvector (probability zero) would give another one.
+ * Returns OK, ENOCONV (max_iter reached first), EINVAL, ENAN, EHIP, ENOMEM.
+ */
+cpca_status cpca_laplacian_lmax(cpca_handle h, const cpca_csr* L, double tol,
+                                int32_t max_iter, double* lmax, cpca_info* info);
 
 /*
  * Alternate decoder (Section V.B, eq. alternatedecoder) solved by conjugate
@@ -383,7 +406,8 @@ typedef struct {
   const cpca_csr* Lc;           /* n x n Laplacian                            */
   const cpca_csr* Lr_til;       /* rho_r x rho_r Laplacian of sampled rows    */
   const cpca_csr* Lc_til;       /* rho_c x rho_c Laplacian of sampled columns */
-  double lmax_r_til, lmax_c_til;/* their largest eigenvalues                  */
+  double lmax_r_til, lmax_c_til;/* their largest eigenvalues (finite; <= 0:    */
+                                /* estimated on the device, as in cpca_frpcag) */
   const void* Ytil;             /* rho_r x rho_c sampled data                 */
 } cpca_instance;
 

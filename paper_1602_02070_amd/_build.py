@@ -34,15 +34,23 @@ def build(verbose: bool = False) -> str:
     objs = []
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    cmds = []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(build_dir, os.path.splitext(s)[0] + ".o")
         lang = ["-x", "hip"] if s.endswith(".hip") else ["-x", "c++"]
-        cmd = [cc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, *lang, "-c", src, "-o", obj]
+        cmds.append([cc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, *lang, "-c", src, "-o", obj])
+        objs.append(obj)
+    # the translation units compile in parallel (one process each)
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        procs.append(subprocess.Popen(cmd))
+    codes = [p.wait() for p in procs]
+    for cmd, rc in zip(cmds, codes):
+        if rc != 0:
+            raise subprocess.CalledProcessError(rc, cmd)
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -16,7 +16,8 @@ EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
            "cpca_set_stream", "cpca_frpcag", "cpca_decode", "cpca_decode_backward",
            "cpca_apply", "cpca_check_csr_host", "cpca_check_index_set_host",
            "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config",
-           "cpca_solve_batched", "cpca_approx_decode", "cpca_cluster_decode"]
+           "cpca_solve_batched", "cpca_approx_decode", "cpca_cluster_decode",
+           "cpca_laplacian_lmax"]
 
 
 class CpcaCsr(ctypes.Structure):
@@ -80,6 +81,7 @@ def _declare(lib):
         "cpca_set_stream": (st, [P, P]),
         "cpca_frpcag": (st, [P, c_int32, P, c_int64, c_int64, csr, csr, c_double, c_double,
                              c_double, c_double, c_int32, c_double, P, info]),
+        "cpca_laplacian_lmax": (st, [P, csr, c_double, c_int32, POINTER(c_double), info]),
         "cpca_decode": (st, [P, c_int32, P, c_int64, c_int64, P, P, c_int64, c_int64, csr, csr,
                              c_double, c_double, c_double, c_int32, P, P, info]),
         "cpca_decode_backward": (st, [P, c_int32, P, P, c_int64, c_int64, P, P, c_int64, c_int64,

@@ -16,7 +16,7 @@ import torch
 from . import _lib
 from ._lib import CpcaApproxInfo, CpcaClusterInfo, CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
 
-__all__ = ["CpcaError", "Graph", "handle", "frpcag", "decode", "decode_backward",
+__all__ = ["CpcaError", "Graph", "handle", "frpcag", "laplacian_lmax", "decode", "decode_backward",
            "apply_operator", "Decode", "DecodeProblem", "profiling", "get_profile",
            "mode_for", "set_apply_config", "Instance", "solve_batched"]
 
@@ -168,6 +168,18 @@ def frpcag(Ytil: torch.Tensor, Lr_til: Graph, Lc_til: Graph, gamma_r: float, gam
                                  int(max_iter), float(eps), _ptr(out), ctypes.byref(info))
     _check(st, "cpca_frpcag")
     return out, info.as_dict()
+
+
+def laplacian_lmax(L: Graph, tol: float = 1e-9, max_iter: int = 50000, device=None):
+    """Largest eigenvalue of a PSD CSR matrix by FP64 power iteration on the
+    device (the FISTA step's norm, Section IV.B). Returns (lmax, info)."""
+    lmax = ctypes.c_double()
+    info = CpcaInfo()
+    st = _lib.load().cpca_laplacian_lmax(handle(device or L.rowptr.device), ctypes.byref(L.desc),
+                                         float(tol), int(max_iter), ctypes.byref(lmax),
+                                         ctypes.byref(info))
+    _check(st, "cpca_laplacian_lmax")
+    return lmax.value, info.as_dict()
 
 
 def decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tensor, p: int, n: int,

@@ -9,6 +9,8 @@
 // fused product comes from the autotuner (or the handle's override).
 #include "batched.hpp"
 #include "common.hpp"
+#define CPCA_SPECTRAL_HOST
+#include "spectral.hpp"
 
 namespace {
 
@@ -44,9 +46,9 @@ cpca_status check_batched_args(cpca_mode mode, const cpca_instance* inst, int32_
     if ((st = check_csr_shape("Lc_til", I.Lc_til, I.rho_c)))
       return fail(st, std::string(where) + ": " + last_error());
     if (!I.Ytil) return fail(CPCA_EINVAL, std::string(where) + ": null Ytil");
-    if (!std::isfinite(I.lmax_r_til) || !std::isfinite(I.lmax_c_til) || I.lmax_r_til < 0 ||
-        I.lmax_c_til < 0)
-      return fail(CPCA_EINVAL, std::string(where) + ": lmax must be finite and >= 0");
+    // lmax <= 0 asks the library to estimate the norm (device power iteration)
+    if (!std::isfinite(I.lmax_r_til) || !std::isfinite(I.lmax_c_til))
+      return fail(CPCA_EINVAL, std::string(where) + ": lmax must be finite");
   }
   for (int32_t t = 0; t < ntasks; ++t) {
     const cpca_task& T = tasks[t];
@@ -57,9 +59,6 @@ cpca_status check_batched_args(cpca_mode mode, const cpca_instance* inst, int32_
     cpca_status st;
     if ((st = check_gamma("gamma_r", T.gamma_r)) || (st = check_gamma("gamma_c", T.gamma_c)))
       return fail(st, std::string(where) + ": " + last_error());
-    const cpca_instance& I = inst[T.instance];
-    if ((T.gamma_r > 0 && !(I.lmax_r_til > 0)) || (T.gamma_c > 0 && !(I.lmax_c_til > 0)))
-      return fail(CPCA_EINVAL, std::string(where) + ": lmax must be > 0 where gamma > 0");
     if (!T.X_out) return fail(CPCA_EINVAL, std::string(where) + ": null X_out");
   }
   return CPCA_OK;
@@ -155,6 +154,20 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
     std::vector<uint8_t> zr((size_t)I.rho_r, 0), zc((size_t)H.ldt, 0);
     H.gt = stage_graph<double>(stg, H.Lrt, H.Lct, zr, zc, kWave * 2);
   }
+  // norms of the sampled graphs: the caller's, or estimated on the device
+  // where the caller passed lmax <= 0 and some task turns that term on
+  std::vector<double> lmr((size_t)ninst), lmc((size_t)ninst);
+  for (int32_t k = 0; k < ninst; ++k) {
+    lmr[(size_t)k] = inst[k].lmax_r_til;
+    lmc[(size_t)k] = inst[k].lmax_c_til;
+  }
+  for (int32_t t = 0; t < ntasks; ++t) {
+    const size_t k = (size_t)tasks[t].instance;
+    if (tasks[t].gamma_r > 0 && !(lmr[k] > 0))
+      STCHK(device_lmax(h, inst[k].Lr_til, kLmaxTol, kLmaxMaxIt, &lmr[k], nullptr, nullptr));
+    if (tasks[t].gamma_c > 0 && !(lmc[k] > 0))
+      STCHK(device_lmax(h, inst[k].Lc_til, kLmaxTol, kLmaxMaxIt, &lmc[k], nullptr, nullptr));
+  }
   // ---- launch shape
   BatchCfg bc;
   bc.R = h->force_R > 0 ? h->force_R : 1;
@@ -183,7 +196,8 @@ cpca_status run_batched(cpca_handle h, cpca_mode mode, const cpca_instance* inst
     k.ldt = (int)H.ldt;
     k.gr = tasks[t].gamma_r;
     k.gc = tasks[t].gamma_c;
-    const double beta = 2.0 * k.gc * I.lmax_c_til + 2.0 * k.gr * I.lmax_r_til;
+    const double beta = 2.0 * k.gc * lmc[(size_t)tasks[t].instance] +
+                        2.0 * k.gr * lmr[(size_t)tasks[t].instance];
     k.lam = beta > 0.0 ? 1.0 / beta : 0.0;
     k.om_r = I.omega_r;
     k.om_c = I.omega_c;

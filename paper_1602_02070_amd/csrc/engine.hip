@@ -11,6 +11,8 @@
 // then runs entirely on the handle's stream. Convergence scalars stay on
 // the device; the host polls them at geometrically growing intervals.
 #include "common.hpp"
+#define CPCA_SPECTRAL_HOST
+#include "spectral.hpp"
 
 namespace {
 
@@ -421,6 +423,9 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
   HIPCHK(hipStreamSynchronize(h->stream));
   STCHK(fetch_csr("Lr_til", Lr_t, Lr));
   STCHK(fetch_csr("Lc_til", Lc_t, Lc));
+  // lmax <= 0 where the graph term is on: estimate it on the device
+  if (gr > 0 && !(lmax_r > 0)) STCHK(device_lmax(h, Lr_t, kLmaxTol, kLmaxMaxIt, &lmax_r, nullptr, nullptr));
+  if (gc > 0 && !(lmax_c > 0)) STCHK(device_lmax(h, Lc_t, kLmaxTol, kLmaxMaxIt, &lmax_c, nullptr, nullptr));
   const size_t N = (size_t)rho_r * rho_c;
   std::vector<uint8_t> mr((size_t)rho_r, 0), mc((size_t)rho_c, 0);
   ApplyCfg cfg = choose_cfg(h, rho_r, rho_c, sizeof(double), choose_band(Lc));
@@ -628,6 +633,28 @@ extern "C" cpca_status cpca_frpcag(cpca_handle h, cpca_mode mode, const void* Yt
   const cpca_status st = run_frpcag(h, mode, Ytil, rho_r, rho_c, Lr_til, Lc_til, gamma_r, gamma_c,
                                     lmax_r, lmax_c, max_iter, eps, Xtil_out, &iters, &obj, &ratio);
   fill_info(info, st, iters, 0, ratio, obj, t0);
+  return st;
+}
+
+extern "C" cpca_status cpca_laplacian_lmax(cpca_handle h, const cpca_csr* L, double tol,
+                                           int32_t max_iter, double* lmax, cpca_info* info) {
+  clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!L || !lmax) return fail(CPCA_EINVAL, "lmax: null argument");
+  if (L->n < 1 || L->n > INT32_MAX) return fail(CPCA_EINVAL, "lmax: order out of range");
+  STCHK(check_csr_shape("L", L, L->n));
+  if (!std::isfinite(tol) || !(tol > 0) || !(tol < 1)) return fail(CPCA_EINVAL, "lmax: tol must be in (0, 1)");
+  if (max_iter < 1) return fail(CPCA_EINVAL, "lmax: max_iter < 1");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  HostCsr Lh;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  STCHK(fetch_csr("L", L, Lh));
+  double res = 0.0;
+  int its = 0;
+  cpca_status st = device_lmax(h, L, tol, max_iter, lmax, &res, &its);
+  const double rel = *lmax > 0 ? res / *lmax : 0.0;
+  if (st == CPCA_OK && res > tol * *lmax) st = fail(CPCA_ENOCONV, "lmax: max_iter reached");
+  fill_info(info, st, its, 0, rel, 0.0, t0);
   return st;
 }
 

@@ -150,10 +150,9 @@ cpca_status check_frpcag_args(cpca_mode mode, const void* Ytil, int64_t rho_r, i
   if ((st = check_csr_shape("Lc_til", Lc, rho_c))) return st;
   if ((st = check_gamma("gamma_r", gr))) return st;
   if ((st = check_gamma("gamma_c", gc))) return st;
-  if (!std::isfinite(lmax_r) || !std::isfinite(lmax_c) || lmax_r < 0 || lmax_c < 0)
-    return fail(CPCA_EINVAL, "frpcag: lmax must be finite and >= 0");
-  if ((gr > 0 && !(lmax_r > 0)) || (gc > 0 && !(lmax_c > 0)))
-    return fail(CPCA_EINVAL, "frpcag: lmax must be > 0 where gamma > 0");
+  // lmax <= 0 asks the library to estimate the norm (device power iteration)
+  if (!std::isfinite(lmax_r) || !std::isfinite(lmax_c))
+    return fail(CPCA_EINVAL, "frpcag: lmax must be finite");
   if (max_iter < 0) return fail(CPCA_EINVAL, "frpcag: max_iter < 0");
   if (!std::isfinite(eps) || eps < 0) return fail(CPCA_EINVAL, "frpcag: eps must be finite and >= 0");
   return CPCA_OK;

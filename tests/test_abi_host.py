@@ -114,11 +114,22 @@ def test_entry_points_reject_bad_scalars_before_device_work(lib):
                                a["gr"], a["gc"], a["lr"], a["lc"], a["it"], a["eps"], dummy,
                                ctypes.byref(info))
 
-    for kw, word in [(dict(lr=0.0), "lmax"), (dict(it=-1), "max_iter"), (dict(eps=-1.0), "eps"),
+    for kw, word in [(dict(lr=float("nan")), "lmax"), (dict(it=-1), "max_iter"), (dict(eps=-1.0), "eps"),
                      (dict(rr=11), "Lr_til"), (dict(gc=float("inf")), "gamma_c")]:
         assert fr(**kw) == _lib.EINVAL, kw
         assert word in _lib.last_error(), (kw, _lib.last_error())
     assert fr(gr=0.0, lr=0.0) == _lib.EINVAL and "null handle" in _lib.last_error()
+    # lmax <= 0 asks for the device estimate: it passes the argument checks
+    assert fr(lr=0.0, lc=-1.0) == _lib.EINVAL and "null handle" in _lib.last_error()
+    lm = ctypes.c_double()
+    for kw, word in [(dict(tol=0.0), "tol"), (dict(tol=1.0), "tol"), (dict(it=0), "max_iter")]:
+        a = dict(dict(tol=1e-9, it=100), **kw)
+        assert lib.cpca_laplacian_lmax(None, ctypes.byref(Lr), a["tol"], a["it"], ctypes.byref(lm),
+                                       ctypes.byref(info)) == _lib.EINVAL, kw
+        assert word in _lib.last_error(), (kw, _lib.last_error())
+    assert lib.cpca_laplacian_lmax(None, ctypes.byref(Lr), 1e-9, 100, None, None) == _lib.EINVAL
+    assert lib.cpca_laplacian_lmax(None, ctypes.byref(Lr), 1e-9, 100, ctypes.byref(lm),
+                                   None) == _lib.EINVAL and "null handle" in _lib.last_error()
     assert lib.cpca_create(None, None) == _lib.EINVAL
     assert lib.cpca_destroy(None) == _lib.OK
 

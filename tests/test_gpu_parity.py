@@ -3,12 +3,15 @@
 Sizes are chosen so the oracle finishes in seconds while the GPU launches
 still span several row blocks, several 64-column SELL slices and ragged
 tails in both dimensions."""
+import warnings
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
 import torch
 
 import paper_1602_02070_amd as cp
+from paper_1602_02070_amd import _lib
 import synth
 from oracle import decoder as OD
 from oracle import frpcag as OF
@@ -498,3 +501,163 @@ def test_full_sampling_without_regularisation_returns_samples():
     assert i64["status"] == 0 and i64["iters"] <= 1
     assert np.array_equal(X64, Xtil)
     assert rel(X32, Xtil) <= 1e-7
+
+
+def test_cfg4_fp32_gradient_at_config1_shapes():
+    # differentiation workload at the tiny shapes (p = 100, n = 200, 50 x 100
+    # samples): loss ||decode(Y~) - X_true||_F^2 with the gradient for Y~ in
+    # FP32 and for both gammas in FP64, through the autograd Function, against
+    # the oracle's adjoint and central finite differences (h = 1e-4) of the
+    # oracle's loss; and the FP32 adjoint at p = 60, n = 80 against the dense
+    # Kronecker gradient
+    P = synth.cfg1_tiny(0)
+    _announce("cfg4 fp32 gradient 100x200")
+    d = dev_problem(P, torch.float32)
+    Xtrue = P.X_true
+    prob = cp.DecodeProblem(d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], tol=1e-10,
+                            mode="fp32_ir")
+    Y = d["Ytil"].clone().requires_grad_(True)
+    gr = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    gc = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    X = cp.Decode.apply(Y, gr, gc, prob)
+    assert X.dtype == torch.float32
+    loss = ((X.double() - torch.from_numpy(Xtrue).cuda()) ** 2).sum()
+    loss.backward()
+    assert Y.grad.dtype == torch.float32
+
+    Yr = P.Ytil.astype(np.float32).astype(np.float64)
+    X_ref = OD.decode(Yr, P.p, P.n, P.omega_r, P.omega_c, P.Lr, P.Lc, 1.0, 1.0)
+    dY_ref, dgr_ref, dgc_ref = OD.decode_backward(2 * (X_ref - Xtrue), X_ref, P.p, P.n,
+                                                  P.omega_r, P.omega_c, P.Lr, P.Lc, 1.0, 1.0)
+    e = rel(host(Y.grad), dY_ref)
+    print(f"[cfg4] dY~ rel.err {e:.2e}, dgr {gr.grad.item():.8e} vs {dgr_ref:.8e}, "
+          f"dgc {gc.grad.item():.8e} vs {dgc_ref:.8e}", flush=True)
+    assert e <= 1e-5
+    assert np.isclose(gr.grad.item(), dgr_ref, rtol=1e-5)
+    assert np.isclose(gc.grad.item(), dgc_ref, rtol=1e-5)
+
+    def L(Yt, a, b):
+        Xd = OD.decode(Yt, P.p, P.n, P.omega_r, P.omega_c, P.Lr, P.Lc, a, b)
+        return float(np.sum((Xd - Xtrue) ** 2))
+
+    h = 1e-4
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        V = rng.standard_normal(P.Ytil.shape)
+        fd = (L(Yr + h * V, 1, 1) - L(Yr - h * V, 1, 1)) / (2 * h)
+        assert np.isclose(float((host(Y.grad) * V).sum()), fd, rtol=1e-5)
+    fd_r = (L(Yr, 1 + h, 1) - L(Yr, 1 - h, 1)) / (2 * h)
+    fd_c = (L(Yr, 1, 1 + h) - L(Yr, 1, 1 - h)) / (2 * h)
+    assert np.isclose(gr.grad.item(), fd_r, rtol=1e-5)
+    assert np.isclose(gc.grad.item(), fd_c, rtol=1e-5)
+
+    # dense Kronecker adjoint at p = 60, n = 80, FP32 tensors
+    P2 = synth.small_problem(18, p_shape=(6, 10), n=80, rank=3, frac=0.5, gamma=(1.0, 1.0))
+    d2 = dev_problem(P2, torch.float32)
+    rng = np.random.default_rng(10)
+    Xt2 = rng.standard_normal((P2.rho_r, P2.rho_c)).astype(np.float32).astype(np.float64)
+    X2 = OD.decode(Xt2, P2.p, P2.n, P2.omega_r, P2.omega_c, P2.Lr, P2.Lc, 1.0, 1.0,
+                   method="dense")
+    G2 = 2 * (X2 - rng.standard_normal((P2.p, P2.n)))
+    ref2 = OD.decode_backward(G2, X2, P2.p, P2.n, P2.omega_r, P2.omega_c, P2.Lr, P2.Lc, 1.0, 1.0,
+                              method="dense")
+    dX, dgr, dgc, _ = cp.decode_backward(torch.from_numpy(G2).float().cuda(),
+                                         torch.from_numpy(X2).float().cuda(), d2["om_r"],
+                                         d2["om_c"], P2.p, P2.n, d2["Lr"], d2["Lc"], 1.0, 1.0,
+                                         tol=1e-10, mode="fp32_ir")
+    assert rel(host(dX), ref2[0]) <= 1e-5
+    assert np.isclose(dgr, ref2[1], rtol=1e-5) and np.isclose(dgc, ref2[2], rtol=1e-5)
+
+
+# ------------------------------------------------------------------ norm estimate, error paths
+
+def _graph(L):
+    return cp.Graph.from_scipy(sp.csr_matrix(L))
+
+
+def test_laplacian_lmax_matches_dense_spectrum():
+    # device power iteration (outside the parity contract) against the dense
+    # spectrum: normalised and combinatorial Laplacians, a sampled video-size
+    # pixel graph, a path graph (clustered top of the spectrum)
+    _announce("laplacian lmax")
+    P1 = synth.cfg1_tiny(0)
+    Pc = synth.small_problem(12, p_shape=(9, 11), n=120, kind="combinatorial")
+    rng = np.random.default_rng(2)
+    Lv, _ = synth.knn_laplacian(synth.grid_coords(128, 160)[np.sort(rng.choice(20480, 1024, replace=False))], 10)
+    m = 300
+    W = sp.diags([np.ones(m - 1), np.ones(m - 1)], [-1, 1])
+    Lpath = sp.diags(np.asarray(W.sum(axis=1)).ravel()) - W
+    for name, L in [("cfg1 rows", P1.Lr_til), ("cfg1 cols", P1.Lc_til), ("comb rows", Pc.Lr),
+                    ("comb cols", Pc.Lc), ("video sampled rows", Lv), ("path", Lpath)]:
+        ref = np.linalg.eigvalsh(sp.csr_matrix(L).toarray())[-1]
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            lm, info = cp.laplacian_lmax(_graph(L))
+        print(f"[lmax] {name}: {lm:.12f} vs {ref:.12f} ({info['iters']} products, "
+              f"status {info['status']})", flush=True)
+        if info["status"] == 0:
+            assert abs(lm - ref) <= 1e-8 * ref, name
+        assert lm <= ref * (1 + 1e-12)
+        assert abs(lm - ref) <= 1e-4 * ref, name
+
+
+def test_frpcag_with_estimated_norms_stays_at_parity(cfg1):
+    # lmax <= 0 asks the library for the norms; 500 FISTA iterations with the
+    # estimates stay close to the run with the exact values and to the oracle
+    P = cfg1
+    _announce("frpcag estimated lmax")
+    d = dev_problem(P)
+    exact, _ = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], 1.0, 1.0, P.lmax_r_til,
+                         P.lmax_c_til, max_iter=500)
+    est, info = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], 1.0, 1.0, 0.0, -1.0, max_iter=500)
+    ref, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, 1.0, 1.0, P.lmax_r_til, P.lmax_c_til, 500)
+    e1, e2 = rel(host(est), host(exact)), rel(host(est), ref)
+    print(f"[lmax] FISTA with estimated norms: rel.diff {e1:.2e} vs exact-norm run, "
+          f"{e2:.2e} vs oracle", flush=True)
+    assert info["status"] == 0 and e1 <= 1e-6 and e2 <= 1e-6
+    # gamma = 0 on one side: that norm is not needed and not estimated
+    a, _ = cp.frpcag(d["Ytil"], d["Lr_til"], d["Lc_til"], 0.0, 1.0, 0.0, P.lmax_c_til, 50)
+    b, _ = OF.fista(P.Ytil, P.Lr_til, P.Lc_til, 0.0, 1.0, 0.0, P.lmax_c_til, 50)
+    assert rel(host(a), b) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "fp32_ir"])
+def test_indefinite_operator_reports_enotspd(cfg1, mode):
+    # L_r = -5 I makes <B, A B> < 0 at the first CG step: the breakdown is
+    # reported as CPCA_ENOTSPD, every kernel returns, and the handle works on
+    P = cfg1
+    _announce(f"enotspd {mode}")
+    d = dev_problem(P)
+    dt = torch.float64 if mode == "fp64" else torch.float32
+    neg = _graph(-5.0 * sp.identity(P.p))
+    Xt = torch.from_numpy(P.Ytil).to(dt).cuda()
+    with pytest.raises(cp.CpcaError) as e:
+        cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, neg, d["Lc"], 1.0, 1.0, mode=mode)
+    assert e.value.status == _lib.ENOTSPD, str(e.value)
+    X, info = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                        tol=1e-10, mode=mode)
+    ref = _decode_ref(P, P.Ytil.astype(np.float32).astype(np.float64) if mode != "fp64"
+                      else P.Ytil, 1.0, 1.0)
+    assert info["status"] == 0 and rel(host(X), ref) <= (1e-9 if mode == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "fp32_ir"])
+def test_nan_input_reports_enan(cfg1, mode):
+    # a NaN in X~ (decoder) or in Y~ (FISTA) ends the iteration with CPCA_ENAN
+    P = cfg1
+    _announce(f"enan {mode}")
+    d = dev_problem(P)
+    dt = torch.float64 if mode == "fp64" else torch.float32
+    Xt = torch.from_numpy(P.Ytil).to(dt).cuda()
+    Xt[3, 7] = float("nan")
+    with pytest.raises(cp.CpcaError) as e:
+        cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0, mode=mode)
+    assert e.value.status == _lib.ENAN, str(e.value)
+    Xt[3, 7] = float("inf")
+    with pytest.raises(cp.CpcaError) as e:
+        cp.frpcag(Xt, d["Lr_til"], d["Lc_til"], 1.0, 1.0, P.lmax_r_til, P.lmax_c_til, 20,
+                  mode=mode)
+    assert e.value.status == _lib.ENAN, str(e.value)
+    X, info = cp.decode(torch.from_numpy(P.Ytil).to(dt).cuda(), d["om_r"], d["om_c"], P.p, P.n,
+                        d["Lr"], d["Lc"], 1.0, 1.0, tol=1e-10, mode=mode)
+    assert info["status"] == 0

@@ -118,3 +118,25 @@ def test_upsampled_indicators_form_a_partition_of_unity():
         if np.any(lab == j):
             assert np.allclose(cen[j], pts[lab == j].mean(axis=0), atol=1e-14)
     assert np.array_equal(lab, np.argmin(((pts[:, None] - cen[None]) ** 2).sum(2), axis=1))
+
+
+def test_kmeans_update_cap_by_hand():
+    # 1-D points 0, 2, 3, 7, 10 with seeds 0 and 2, worked by hand:
+    #   assignment to (0, 2)        -> 0 1 1 1 1, means (0, 5.5)
+    #   assignment to (0, 5.5)      -> 0 0 1 1 1, means (1, 20/3)
+    #   assignment to (1, 20/3)     -> 0 0 0 1 1, means (5/3, 8.5)
+    #   assignment to (5/3, 8.5)    -> unchanged: converged after 3 updates
+    pts = np.array([[0.0], [2.0], [3.0], [7.0], [10.0]])
+    seeds = pts[[0, 1]]
+    want = {
+        0: ([0, 1, 1, 1, 1], [0.0, 2.0]),
+        1: ([0, 0, 1, 1, 1], [0.0, 5.5]),
+        2: ([0, 0, 0, 1, 1], [1.0, 20.0 / 3.0]),
+        3: ([0, 0, 0, 1, 1], [5.0 / 3.0, 8.5]),
+        100: ([0, 0, 0, 1, 1], [5.0 / 3.0, 8.5]),
+    }
+    for cap, (lab_w, cen_w) in want.items():
+        lab, cen, it = OC.kmeans(pts, seeds, max_iter=cap)
+        assert list(lab) == lab_w, cap
+        assert np.allclose(cen[:, 0], cen_w, rtol=0, atol=1e-15), cap
+        assert it == min(cap, 3)

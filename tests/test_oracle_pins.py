@@ -423,3 +423,66 @@ def _lyapunov_check(P, gr, gc):
         E.append(2 / beta * tk ** 2 * (F.objective(rec[k], Y, Lr, Lc, gr, gc) - Fstar) + np.sum(u * u))
     E = np.array(E)
     assert np.all(np.diff(E) <= 1e-9 * E[0])
+
+
+# ---------------------------------------------------------------- FISTA early stop
+
+def test_fista_eps_stop_on_nullspace_data_after_one_iteration():
+    # nullspace data: grad g = 0, so S_1 = Y and Z_2 = S_1 = Z_1; the relative
+    # change is 0 < eps at the first test, the output is S_1 = Y
+    P = _tiny(kind="normalized")
+    zr = np.linalg.eigh(P.Lr_til.toarray())[1][:, 0]
+    zc = np.linalg.eigh(P.Lc_til.toarray())[1][:, 0]
+    Y = -1.5 * np.outer(zr, zc)
+    S, it = F.fista(Y, P.Lr_til, P.Lc_til, 1.0, 2.0, P.lmax_r_til, P.lmax_c_til, 50, eps=1e-30)
+    assert it == 1
+    assert np.allclose(S, Y, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed,gamma", [(5, (1.0, 3.0)), (8, (0.4, 0.9))])
+def test_fista_eps_stop_rule_index_and_output(seed, gamma):
+    # Algorithm 1 stops at the first j with ||Z_{j+1} - Z_j||^2 < eps ||Z_j||^2
+    # and returns S_j. The Z sequence is rebuilt from the recorded prox
+    # iterates S_j with the momentum step Z_{j+1} = S_j + ((t_j - 1)/t_{j+1})
+    # (S_j - S_{j-1}), S_0 = Z_1 = Y, and the t_j of the pinned momentum
+    # sequence; every eps placed just above / just below a recorded ratio
+    # must stop exactly there / one iteration later (strict inequality).
+    P = _tiny(seed=seed)
+    gr, gc = gamma
+    args = (P.Lr_til, P.Lc_til, gr, gc, P.lmax_r_til, P.lmax_c_til)
+    J = 80
+    rec = {j: None for j in range(1, J + 1)}
+    F.fista(P.Ytil, *args, J, record=rec)
+    t = F.momentum_sequence(J)               # t[j-1] = t_j
+    S = [P.Ytil] + [rec[j] for j in range(1, J + 1)]
+    Z = [None, P.Ytil]                       # Z[j] = Z_j
+    for j in range(1, J + 1):
+        Z.append(S[j] + ((t[j - 1] - 1.0) / t[j]) * (S[j] - S[j - 1]))
+    ratio = np.array([np.sum((Z[j + 1] - Z[j]) ** 2) / np.sum(Z[j] ** 2)
+                      for j in range(1, J + 1)])
+    assert np.all(np.isfinite(ratio)) and ratio.max() > 0
+
+    def first_stop(eps):
+        hit = np.nonzero(ratio < eps)[0]
+        return int(hit[0]) + 1 if hit.size else J
+
+    checked = 0
+    for j in (2, 5, 11, 23, 40, 67):
+        for eps in (ratio[j - 1] * (1 + 1e-9), ratio[j - 1] * (1 - 1e-9)):
+            want = first_stop(eps)
+            S_out, it = F.fista(P.Ytil, *args, J, eps=eps)
+            assert it == want, (j, eps, it, want)
+            assert np.array_equal(S_out, S[want])
+            checked += 1
+    # the stop index really moves with eps (the pin is not vacuous)
+    assert len({first_stop(r * (1 + 1e-9)) for r in ratio}) > 5
+    assert checked == 12
+
+
+def test_fista_eps_stop_is_strict_on_zero_data():
+    # Y = 0: every iterate is 0, so the test compares 0 < eps * 0, which is
+    # false for the strict rule; all J iterations run
+    P = _tiny()
+    Y = np.zeros_like(P.Ytil)
+    S, it = F.fista(Y, P.Lr_til, P.Lc_til, 1.0, 1.0, P.lmax_r_til, P.lmax_c_til, 7, eps=0.5)
+    assert it == 7 and not S.any()
