@@ -15,7 +15,8 @@ import types
 import pytest
 
 import oracle
-from tests import test_oracle_approx_pins, test_oracle_cluster_pins, test_oracle_pins
+from tests import (test_oracle_approx_pins, test_oracle_cluster_pins, test_oracle_knn_pins,
+                   test_oracle_pins)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -86,9 +87,26 @@ MUTANTS = [
     ("cluster", "        if it >= max_iter:", "        if it > max_iter:", "k-means cap off by one"),
     ("cluster", "return np.argmax(np.asarray(C), axis=1)", "return np.argmin(np.asarray(C), axis=1)",
      "min pooling"),
+    # K-NN graphs (Section II)
+    ("knn", "order = np.lexsort((cand, d2[a, cand]))[:K]", "order = np.lexsort((-cand, d2[a, cand]))[:K]",
+     "ties to the higher index"),
+    ("knn", "d2[np.arange(q.size), q] = np.inf", "d2[np.arange(q.size), q] = d2[np.arange(q.size), q]",
+     "a point its own neighbour"),
+    ("knn", "return float(np.mean(np.sqrt(np.asarray(d2, dtype=np.float64))))",
+     "return float(np.sqrt(np.mean(np.sqrt(np.asarray(d2, dtype=np.float64)))))",
+     "sigma^2 = mean distance"),
+    ("knn", "w = np.exp(-np.asarray(d2, dtype=np.float64).ravel() / (sigma * sigma))",
+     "w = np.exp(-np.sqrt(np.asarray(d2, dtype=np.float64).ravel()) / (sigma * sigma))",
+     "kernel of the distance instead of its square"),
+    ("knn", "    r = np.concatenate([rows, idx.ravel()])\n    c = np.concatenate([idx.ravel(), rows])",
+     "    r = np.concatenate([rows, rows])\n    c = np.concatenate([idx.ravel(), idx.ravel()])",
+     "directed graph (no union)"),
+    ("knn", "vals = -Wc.data / np.sqrt(deg[Wc.row] * deg[Wc.col])", "vals = -Wc.data / deg[Wc.row]",
+     "random-walk instead of symmetric normalisation"),
 ]
 
-PIN_MODULES = (test_oracle_pins, test_oracle_approx_pins, test_oracle_cluster_pins)
+PIN_MODULES = (test_oracle_pins, test_oracle_approx_pins, test_oracle_cluster_pins,
+               test_oracle_knn_pins)
 
 
 def _pin_cases():
