@@ -321,6 +321,31 @@ cpca_status cpca_apply(cpca_handle h, cpca_mode mode, const void* P, void* Q,
                        double gamma_r, double gamma_c, double* pq);
 
 /*
+ * cpca_apply without device memory allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, result and kernels as cpca_apply; the
+ * staged operator image (L_r, L_c in the kernel layouts, masks, row-panel
+ * tables) and the partial sums go to a static device array of 32 MiB per
+ * GPU (held from the first cpca_create on that GPU until the process ends)
+ * instead of the handle's workspace, which is neither used nor grown.
+ * Nothing in the array has to start at zero: each call overwrites the image
+ * and every partial it reads. All handles on one GPU share the array, so
+ * calls that overlap on one GPU (several host threads or streams) race and
+ * must be serialised by the caller. Host memory for the staging is still
+ * taken from the C++ heap; no device or pinned allocation is made, and
+ * profiling events are not recorded for this call.
+ * Errors as cpca_apply, plus EINVAL when the operator image and partial sums
+ * need more than 32 MiB (for example about 2.5 M non-zeros of L_r in FP64);
+ * the message states both sizes.
+ */
+cpca_status cpca_apply_noalloc(cpca_handle h, cpca_mode mode, const void* P, void* Q,
+                               int64_t p, int64_t n,
+                               const int32_t* omega_r, int64_t rho_r,
+                               const int32_t* omega_c, int64_t rho_c,
+                               const cpca_csr* Lr, const cpca_csr* Lc,
+                               double gamma_r, double gamma_c, double* pq);
+
+/*
  * Host-side structural checks, exposed so that they can be exercised
  * without a GPU. Pointers are HOST memory here.
  *   cpca_check_csr_host: rowptr monotone with rowptr[0] = 0 and

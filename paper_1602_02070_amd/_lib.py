@@ -17,7 +17,7 @@ EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
            "cpca_apply", "cpca_check_csr_host", "cpca_check_index_set_host",
            "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config",
            "cpca_solve_batched", "cpca_approx_decode", "cpca_cluster_decode",
-           "cpca_laplacian_lmax"]
+           "cpca_laplacian_lmax", "cpca_apply_noalloc"]
 
 
 class CpcaCsr(ctypes.Structure):
@@ -89,6 +89,8 @@ def _declare(lib):
                                       POINTER(c_double), POINTER(c_double), info]),
         "cpca_apply": (st, [P, c_int32, P, P, c_int64, c_int64, P, c_int64, P, c_int64, csr, csr,
                             c_double, c_double, POINTER(c_double)]),
+        "cpca_apply_noalloc": (st, [P, c_int32, P, P, c_int64, c_int64, P, c_int64, P, c_int64,
+                                    csr, csr, c_double, c_double, POINTER(c_double)]),
         "cpca_check_csr_host": (st, [c_int64, c_int64, P, P, P]),
         "cpca_check_index_set_host": (st, [c_int64, c_int64, P]),
         "cpca_set_profiling": (st, [P, c_int32]),

@@ -11,8 +11,44 @@
 // then runs entirely on the handle's stream. Convergence scalars stay on
 // the device; the host polls them at geometrically growing intervals.
 #include "common.hpp"
+#include <mutex>
 #define CPCA_SPECTRAL_HOST
 #include "spectral.hpp"
+
+// ------------------------------------------------------- no-allocation apply
+// Scratch of cpca_apply_noalloc: the staged operator image and the partial
+// sums live in this file-scope device array (one copy per GPU, held until the
+// process ends) instead of the handle's workspace. In host code the name is
+// only a stand-in: kernels and copies use the address that
+// hipGetSymbolAddress returns for the current device (scratch_device()).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Resolves (once per device, with that device current) the device address
+// of `scratch`. Called by cpca_create on the handle's device.
+cpca_status scratch_resolve(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(CPCA_EHIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return CPCA_OK;
+  void* ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(CPCA_EHIP, "hipGetSymbolAddress returned null for the scratch array");
+  g_scratch[device] = static_cast<char*>(ptr);
+  return CPCA_OK;
+}
+
+char* scratch_device(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
+}
+
+}  // namespace
 
 namespace {
 
@@ -555,6 +591,16 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
                 std::string("cpca_create: ") + hipGetErrorString(e));
   }
   h->stream = static_cast<hipStream_t>(stream);
+  {
+    // device address of the no-allocation scratch array (once per device)
+    const cpca_status sst = scratch_resolve(h->device);
+    if (sst != CPCA_OK) {
+      (void)hipFree(h->fixed);
+      (void)hipHostFree(h->pinned);
+      delete h;
+      return sst;
+    }
+  }
   tune_load_file(h);
   if (const char* s = std::getenv("CPCA_APPLY_R")) h->force_R = std::atoi(s);
   if (const char* s = std::getenv("CPCA_APPLY_LDS")) h->force_lds = std::atoi(s);
@@ -741,10 +787,14 @@ extern "C" cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode, const
   return st;
 }
 
+
 namespace {
+// The operator image and the partial sums go to `fixed_buf` (of `fixed_cap`
+// bytes) when it is given, else to the handle's workspace.
 template <typename T>
 cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_t p, int64_t n,
-                      double gr, double gc, double* pq) {
+                      double gr, double gc, double* pq, char* fixed_buf = nullptr,
+                      size_t fixed_cap = 0) {
   ApplyCfg cfg = choose_cfg(h, p, n, sizeof(T), choose_band(P.Lc), true);
   // user buffers: fall back to scalar columns if they are not 16-byte aligned
   if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Q)) % 16 != 0) {
@@ -767,10 +817,20 @@ cpca_status run_apply(cpca_handle h, const Prepared& P, const T* X, T* Q, int64_
   {
     Arena a;
     layout(a);
-    STCHK(ensure_ws(h, a.off));
+    if (fixed_buf) {
+      if (a.off > fixed_cap) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "apply_noalloc: operator image and partials need %zu bytes, scratch holds %zu",
+                      a.off, fixed_cap);
+        return fail(CPCA_EINVAL, buf);
+      }
+    } else {
+      STCHK(ensure_ws(h, a.off));
+    }
   }
   Arena a;
-  a.base = h->ws;
+  a.base = fixed_buf ? fixed_buf : h->ws;
   layout(a);
   HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
   const DevGraph<T> g = bind_graph<T>(gi, img);
@@ -809,6 +869,42 @@ extern "C" cpca_status cpca_apply(cpca_handle h, cpca_mode mode, const void* P, 
                              gamma_r, gamma_c, pq);
   return run_apply<float>(h, Pp, static_cast<const float*>(P), static_cast<float*>(Q), p, n,
                           gamma_r, gamma_c, pq);
+}
+
+extern "C" cpca_status cpca_apply_noalloc(cpca_handle h, cpca_mode mode, const void* P, void* Q,
+                                          int64_t p, int64_t n, const int32_t* omega_r,
+                                          int64_t rho_r, const int32_t* omega_c, int64_t rho_c,
+                                          const cpca_csr* Lr, const cpca_csr* Lc, double gamma_r,
+                                          double gamma_c, double* pq) {
+  clear_error();
+  STCHK(check_mode(mode));
+  STCHK(check_dims("P", p, n));
+  if (!P || !Q) return fail(CPCA_EINVAL, "apply_noalloc: null data pointer");
+  if (rho_r < 0 || rho_c < 0 || rho_r > p || rho_c > n)
+    return fail(CPCA_EINVAL, "apply_noalloc: sample counts out of range");
+  if ((rho_r > 0 && !omega_r) || (rho_c > 0 && !omega_c))
+    return fail(CPCA_EINVAL, "apply_noalloc: null index set");
+  STCHK(check_csr_shape("Lr", Lr, p));
+  STCHK(check_csr_shape("Lc", Lc, n));
+  STCHK(check_gamma("gamma_r", gamma_r));
+  STCHK(check_gamma("gamma_c", gamma_c));
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  char* buf = scratch_device(h->device);
+  if (!buf) return fail(CPCA_EHIP, "apply_noalloc: scratch address not resolved for this device");
+  Prepared Pp;
+  STCHK(prepare(h, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n, Pp));
+  // no event objects are created: profiling is paused for this call
+  const bool prof = h->prof;
+  h->prof = false;
+  cpca_status st;
+  if (mode == CPCA_FP64)
+    st = run_apply<double>(h, Pp, static_cast<const double*>(P), static_cast<double*>(Q), p, n,
+                           gamma_r, gamma_c, pq, buf, kScratchBytes);
+  else
+    st = run_apply<float>(h, Pp, static_cast<const float*>(P), static_cast<float*>(Q), p, n,
+                          gamma_r, gamma_c, pq, buf, kScratchBytes);
+  h->prof = prof;
+  return st;
 }
 
 extern "C" cpca_status cpca_set_apply_config(cpca_handle h, int32_t rows_per_block, int32_t use_lds,
