@@ -28,11 +28,19 @@ reaches).
 X is invariant under the sign of each singular pair; it is unique when the
 kept singular values are distinct.
 
+The appendix's approximate decoders 2 and 3 (approx_decode_rows /
+approx_decode_cols) upsample one side only and project the full data Y onto
+it: X = U U^T Y or X = Y V V^T, with U (V) the upsampled and normalised
+singular vectors of Algorithm 2; the scale constant cancels.
+
 Parity status: pinned (the upsampled vectors against a constrained quadratic
 minimisation solved through a null-space basis; exact recovery of a
 piecewise-constant subspace on a graph with several components; full
 sampling reduces the decoder to the rank-k truncation of X~; the rank
-selection on prescribed singular values; the scale constant).
+selection on prescribed singular values; the scale constant; decoders 2 and 3:
+full sampling gives the rank-k truncation of Y with the Eckart-Young error,
+one kept vector gives the orthogonal projection onto the upsampled vector,
+and each decoder on the transposed problem is the other one).
 """
 from __future__ import annotations
 
@@ -41,7 +49,8 @@ import scipy.sparse as sp
 import scipy.sparse.csgraph as csg
 import scipy.sparse.linalg as spla
 
-__all__ = ["thin_svd", "select_rank", "upsample", "rip_scale", "approx_decode"]
+__all__ = ["thin_svd", "select_rank", "upsample", "rip_scale", "approx_decode",
+           "approx_decode_rows", "approx_decode_cols"]
 
 
 def thin_svd(Xt):
@@ -110,3 +119,35 @@ def approx_decode(Xt, p, n, omega_r, omega_c, Lr, Lc, delta: float = 0.0,
     scale = rip_scale(p, n, rho_r, rho_c, delta)
     X = (U * (scale * s[:k])) @ V.T
     return X, dict(k=k, sigma=s, U=U, V=V, scale=scale)
+
+
+def _unit_columns(S):
+    return S / np.linalg.norm(S, axis=0, keepdims=True) if S.shape[1] else S
+
+
+def approx_decode_rows(Xt, Y, omega_r, Lr, ratio: float = 0.1, k_max: int | None = None):
+    """Approximate decoder 2 (appendix, other approximate decoders): only the
+    left singular vectors of X~ are upsampled, over the row graph, and
+    normalised as in Algorithm 2; with the full data Y (p x n) available,
+    V = Y^T U S~^-1 / scale makes X = U S~ scale V^T equal to U U^T Y, which
+    is what is returned. Returns (X, info) with info = dict(k, sigma, U)."""
+    Xt = np.asarray(Xt, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    Ut, s, _ = thin_svd(Xt)
+    k = select_rank(s, ratio, k_max)
+    U = _unit_columns(upsample(Lr, omega_r, Ut[:, :k]))
+    X = U @ (U.T @ Y)
+    return X, dict(k=k, sigma=s, U=U)
+
+
+def approx_decode_cols(Xt, Y, omega_c, Lc, ratio: float = 0.1, k_max: int | None = None):
+    """Approximate decoder 3 (appendix): only the right singular vectors of
+    X~ are upsampled, over the column graph, and normalised; then
+    X = Y V V^T. Returns (X, info) with info = dict(k, sigma, V)."""
+    Xt = np.asarray(Xt, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    _, s, Vt = thin_svd(Xt)
+    k = select_rank(s, ratio, k_max)
+    V = _unit_columns(upsample(Lc, omega_c, Vt[:, :k]))
+    X = (Y @ V) @ V.T
+    return X, dict(k=k, sigma=s, V=V)

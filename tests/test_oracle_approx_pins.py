@@ -138,3 +138,61 @@ def test_block_constant_matrix_is_recovered_exactly():
     Lr_bad = _random_laplacian(20, rng, comps=[np.arange(0, 5), np.arange(5, 20)])
     Xbad, _ = OA.approx_decode(Xt, 20, 16, om_r, om_c, Lr_bad, Lc)
     assert np.abs(Xbad - X).max() > 1e-3
+
+
+# ---------------------------------------------------------- decoders 2 and 3
+
+def test_one_side_decoders_full_sampling_give_the_rank_k_truncation_of_Y():
+    # omega = everything and X~ = Y: U = U~ (orthonormal), so U U^T Y and
+    # Y V V^T are the best rank-k approximation of Y (Eckart-Young)
+    rng = np.random.default_rng(11)
+    p, n = 13, 9
+    Lr = _random_laplacian(p, rng)
+    Lc = _random_laplacian(n, rng)
+    sig = np.array([9.0, 5.0, 3.0, 2.5, 0.5, 0.2, 0.1, 0.05, 0.02])
+    Q1, _ = np.linalg.qr(rng.standard_normal((p, n)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Y = (Q1 * sig) @ Q2.T
+    for fn, L, om in ((OA.approx_decode_rows, Lr, np.arange(p)),
+                      (OA.approx_decode_cols, Lc, np.arange(n))):
+        X, info = fn(Y, Y, om, L, ratio=0.25)
+        assert info["k"] == 4                      # threshold 2.25 keeps 9, 5, 3, 2.5
+        assert np.linalg.matrix_rank(X, tol=1e-9) == 4
+        assert abs(np.linalg.norm(Y - X) ** 2 - np.sum(sig[4:] ** 2)) <= 1e-12
+
+
+def test_one_kept_vector_gives_the_orthogonal_projection():
+    # k = 1: X = u u^T Y / ||u||^2 with u the upsampled leading vector: the
+    # residual Y - X is orthogonal to u and X has rank one along u
+    rng = np.random.default_rng(12)
+    p, n = 30, 17
+    Lr = _random_laplacian(p, rng)
+    Lc = _random_laplacian(n, rng)
+    om_r = np.sort(rng.choice(p, 9, replace=False))
+    om_c = np.sort(rng.choice(n, 6, replace=False))
+    Y = rng.standard_normal((p, n))
+    Xt = np.outer(rng.standard_normal(9), rng.standard_normal(6)) + 1e-3 * rng.standard_normal((9, 6))
+    X, info = OA.approx_decode_rows(Xt, Y, om_r, Lr, ratio=0.5)
+    assert info["k"] == 1
+    u = OA.upsample(Lr, om_r, np.linalg.svd(Xt)[0][:, :1])[:, 0]
+    assert np.abs(u @ (Y - X)).max() <= 1e-12 * np.abs(Y).max() * np.linalg.norm(u)
+    assert np.linalg.matrix_rank(X, tol=1e-10) == 1
+    assert np.abs(X - np.outer(u, u @ Y) / (u @ u)).max() <= 1e-12
+    X3, info3 = OA.approx_decode_cols(Xt, Y, om_c, Lc, ratio=0.5)
+    v = OA.upsample(Lc, om_c, np.linalg.svd(Xt)[2][:1].T)[:, 0]
+    assert info3["k"] == 1 and np.abs((Y - X3) @ v).max() <= 1e-12 * np.abs(Y).max() * np.linalg.norm(v)
+
+
+def test_decoder_3_is_decoder_2_of_the_transposed_problem():
+    rng = np.random.default_rng(13)
+    p, n = 25, 19
+    Lr = _random_laplacian(p, rng)
+    Lc = _random_laplacian(n, rng)
+    om_r = np.sort(rng.choice(p, 8, replace=False))
+    om_c = np.sort(rng.choice(n, 7, replace=False))
+    Y = rng.standard_normal((p, n))
+    Xt = Y[np.ix_(om_r, om_c)] + 0.1 * rng.standard_normal((8, 7))
+    X3, i3 = OA.approx_decode_cols(Xt, Y, om_c, Lc, ratio=0.2)
+    X2t, i2 = OA.approx_decode_rows(Xt.T, Y.T, om_c, Lc, ratio=0.2)
+    assert i3["k"] == i2["k"] >= 2
+    assert np.abs(X3 - X2t.T).max() <= 1e-12 * np.abs(X3).max()

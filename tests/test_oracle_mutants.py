@@ -81,6 +81,12 @@ MUTANTS = [
      "return float(np.sqrt(n * p / (rho_r * rho_c * (1.0 + delta))))", "delta with the wrong sign"),
     ("approx", "U = U / np.linalg.norm(U, axis=0, keepdims=True) if k else U",
      "U = U if k else U", "left vectors not normalised"),
+    ("approx", "    U = _unit_columns(upsample(Lr, omega_r, Ut[:, :k]))",
+     "    U = upsample(Lr, omega_r, Ut[:, :k])", "decoder 2 without normalisation"),
+    ("approx", "    V = _unit_columns(upsample(Lc, omega_c, Vt[:, :k]))",
+     "    V = upsample(Lc, omega_c, Vt[:, :k])", "decoder 3 without normalisation"),
+    ("approx", "    V = _unit_columns(upsample(Lc, omega_c, Vt[:, :k]))",
+     "    V = _unit_columns(upsample(Lc, omega_c, Vt[:, :max(k - 1, 1)]))", "decoder 3 one vector short"),
     # Algorithm 3 (Section VI)
     ("cluster", "new = np.argmin(D, axis=1)", "new = np.argmax(D, axis=1)", "k-means to the farthest centroid"),
     ("cluster", "C[j] = P[members].mean(axis=0)", "C[j] = P[members].sum(axis=0)", "centroid as a sum"),
