@@ -154,6 +154,38 @@ cpca_status cpca_laplacian_lmax(cpca_handle h, const cpca_csr* L, double tol,
                                 int32_t max_iter, double* lmax, cpca_info* info);
 
 /*
+ * K-nearest-neighbour graph Laplacian of a point set (Section II: each point
+ * is joined to its K nearest neighbours in Euclidean distance; the
+ * symmetric adjacency carries W_ij = exp(-||y_i - y_j||^2 / sigma^2) on every
+ * pair related in either direction; L = D - W, or D^{-1/2} (D - W) D^{-1/2}
+ * when normalized; Section VII-A takes K = 10 and sets sigma from the mean
+ * K-NN distance).
+ * points      N x d row-major FP64 (device): row i is y_i (a row or column
+ *             of the data matrix, or any feature vector).
+ * K           1 <= K <= min(28, N - 1).
+ * normalized  1: L_n (unit diagonal), 0: combinatorial L.
+ * rowptr_out  N + 1 int32 (device); colind_out / vals_out hold at least
+ *             nnz_cap >= N (2K + 1) entries (device); the CSR rows are sorted
+ *             by column and store the diagonal; *nnz_out (host) receives the
+ *             number used (N + N K + the entries added by the union).
+ * sigma_out   host: the mean Euclidean distance over the N K neighbour pairs.
+ * knn_out     optional N x K int32 (device): the neighbours of each point by
+ *             (squared distance, index), or NULL.
+ * Readings: a point is not its own neighbour; equal distances are ordered by
+ * index; sigma is the mean K-NN distance itself. Candidates are selected with
+ * squared distances from FP64 MFMA Gram tiles (||y_i||^2 + ||y_j||^2 -
+ * 2 <y_i, y_j>); the K kept ones are re-ranked with squared distances summed
+ * directly over coordinates in FP64, which are also the ones weighted.
+ * Returns OK, EINVAL (also when sigma = 0: every neighbour distance is zero;
+ * nothing is written then), ENAN (NaN or Inf in the points), EHIP, ENOMEM.
+ */
+cpca_status cpca_knn_graph(cpca_handle h, const double* points, int64_t N, int64_t d,
+                           int32_t K, int32_t normalized, int32_t* rowptr_out,
+                           int32_t* colind_out, double* vals_out, int64_t nnz_cap,
+                           int64_t* nnz_out, double* sigma_out, int32_t* knn_out,
+                           cpca_info* info);
+
+/*
  * Alternate decoder (Section V.B, eq. alternatedecoder) solved by conjugate
  * gradient on its normal equations
  *

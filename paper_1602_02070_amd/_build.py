@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcpca.so")
 
-SOURCES = ["engine.hip", "batched.hip", "approx.hip", "validate.cpp"]
+SOURCES = ["engine.hip", "batched.hip", "approx.hip", "knn.hip", "validate.cpp"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from emitting packed FP32 arithmetic

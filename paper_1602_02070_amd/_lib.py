@@ -17,7 +17,7 @@ EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
            "cpca_apply", "cpca_check_csr_host", "cpca_check_index_set_host",
            "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config",
            "cpca_solve_batched", "cpca_approx_decode", "cpca_cluster_decode",
-           "cpca_laplacian_lmax", "cpca_apply_noalloc"]
+           "cpca_laplacian_lmax", "cpca_apply_noalloc", "cpca_knn_graph"]
 
 
 class CpcaCsr(ctypes.Structure):
@@ -82,6 +82,8 @@ def _declare(lib):
         "cpca_frpcag": (st, [P, c_int32, P, c_int64, c_int64, csr, csr, c_double, c_double,
                              c_double, c_double, c_int32, c_double, P, info]),
         "cpca_laplacian_lmax": (st, [P, csr, c_double, c_int32, POINTER(c_double), info]),
+        "cpca_knn_graph": (st, [P, P, c_int64, c_int64, c_int32, c_int32, P, P, P, c_int64,
+                                POINTER(c_int64), POINTER(c_double), P, info]),
         "cpca_decode": (st, [P, c_int32, P, c_int64, c_int64, P, P, c_int64, c_int64, csr, csr,
                              c_double, c_double, c_double, c_int32, P, P, info]),
         "cpca_decode_backward": (st, [P, c_int32, P, P, c_int64, c_int64, P, P, c_int64, c_int64,

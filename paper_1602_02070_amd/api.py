@@ -16,7 +16,8 @@ import torch
 from . import _lib
 from ._lib import CpcaApproxInfo, CpcaClusterInfo, CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
 
-__all__ = ["CpcaError", "Graph", "handle", "frpcag", "laplacian_lmax", "decode", "decode_backward",
+__all__ = ["CpcaError", "Graph", "handle", "frpcag", "laplacian_lmax", "knn_graph", "decode",
+           "decode_backward",
            "apply_operator", "Decode", "DecodeProblem", "profiling", "get_profile",
            "mode_for", "set_apply_config", "Instance", "solve_batched"]
 
@@ -115,6 +116,12 @@ class Graph:
     def desc(self) -> CpcaCsr:
         return self._desc
 
+    def to_scipy(self):
+        """Host copy as a scipy.sparse CSR matrix."""
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.vals.cpu().numpy(), self.colind.cpu().numpy(),
+                              self.rowptr.cpu().numpy()), shape=(self.n, self.n))
+
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
@@ -180,6 +187,39 @@ def laplacian_lmax(L: Graph, tol: float = 1e-9, max_iter: int = 50000, device=No
                                          ctypes.byref(info))
     _check(st, "cpca_laplacian_lmax")
     return lmax.value, info.as_dict()
+
+
+def knn_graph(points: torch.Tensor, K: int = 10, kind: str = "normalized",
+              want_knn: bool = False):
+    """Laplacian of the K-NN Gaussian-kernel graph of the rows of `points`
+    (N x d, FP64, on the GPU): Section II. kind: "normalized" or
+    "combinatorial". Returns (Graph, info) with info = dict(sigma, nnz, ms,
+    knn (N x K int32 neighbour indices, if want_knn))."""
+    Y = _need(points, "points", torch.float64)
+    if Y.dim() != 2:
+        raise ValueError("points must be N x d")
+    N, d = Y.shape
+    if kind not in ("normalized", "combinatorial"):
+        raise ValueError(f"unknown kind {kind!r}")
+    cap = N * (2 * int(K) + 1)
+    rowptr = torch.empty(N + 1, dtype=torch.int32, device=Y.device)
+    colind = torch.empty(cap, dtype=torch.int32, device=Y.device)
+    vals = torch.empty(cap, dtype=torch.float64, device=Y.device)
+    knn = torch.empty((N, int(K)), dtype=torch.int32, device=Y.device) if want_knn else None
+    nnz = ctypes.c_int64()
+    sigma = ctypes.c_double()
+    info = CpcaInfo()
+    st = _lib.load().cpca_knn_graph(handle(Y.device), _ptr(Y), N, d, int(K),
+                                    int(kind == "normalized"), _ptr(rowptr), _ptr(colind),
+                                    _ptr(vals), cap, ctypes.byref(nnz), ctypes.byref(sigma),
+                                    _ptr(knn), ctypes.byref(info))
+    _check(st, "cpca_knn_graph", allow_noconv=False)
+    m = nnz.value
+    G = Graph(rowptr, colind[:m].clone(), vals[:m].clone(), N)
+    out = dict(sigma=sigma.value, nnz=m, ms=info.ms)
+    if want_knn:
+        out["knn"] = knn
+    return G, out
 
 
 def decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tensor, p: int, n: int,

@@ -23,7 +23,7 @@ from .graphs import knn_laplacian, laplacian_lmax, low_eigvecs
 
 __all__ = ["Problem", "round_count", "make_problem", "cfg1_tiny", "cfg2_face",
            "cfg3_video", "cfg5_batch", "small_problem", "grid_coords",
-           "circle_coords", "helix_coords", "cluster_digits"]
+           "circle_coords", "helix_coords", "cluster_digits", "digits_points"]
 
 
 @dataclasses.dataclass
@@ -271,6 +271,7 @@ def cluster_digits(seed: int = 0, n: int = 70000, side: int = 28, k: int = 10,
     centres = rng.uniform(0.0, 12.0, size=(k, 3))
     labels = rng.integers(0, k, size=n)
     lat = centres[labels] + spread * rng.standard_normal((n, 3))
+    lat_all = lat
     rows = grid_coords(side, side)
     p = side * side
     Lr, _ = knn_laplacian(rows, K)
@@ -292,4 +293,25 @@ def cluster_digits(seed: int = 0, n: int = 70000, side: int = 28, k: int = 10,
     return Problem(name="cluster_digits", p=p, n=n, Lr=Lr, Lc=Lc, omega_r=om_r, omega_c=om_c,
                    Ytil=Ytil, Lr_til=Lr, Lc_til=Lc_t, lmax_r_til=laplacian_lmax(Lr),
                    lmax_c_til=laplacian_lmax(Lc_t), gamma_r=1.0, gamma_c=1.0,
-                   fista_iters=500, tol=1e-10, meta=dict(labels=labels, init=init, k=k))
+                   fista_iters=500, tol=1e-10,
+                   meta=dict(labels=labels, init=init, k=k, latent=lat_all))
+
+
+def digits_points(seed: int = 0, n: int = 70000, side: int = 28, k: int = 10,
+                  dtype=np.float64) -> tuple[np.ndarray, np.ndarray]:
+    """Digit-shaped point set for graph construction between samples: n
+    points of dimension side^2 in k classes. A point is its class template (a
+    smooth random image, unit standard deviation) plus a rank-3 smooth
+    within-class variation (std 0.3 per factor) and Gaussian noise (std 0.1).
+    Returns (points n x side^2, labels)."""
+    rng = np.random.default_rng(seed)
+    templates = _smooth_fields(rng, side, side, k, 2.0)
+    var = _smooth_fields(rng, side, side, 3, 2.0)
+    labels = rng.integers(0, k, size=n)
+    pts = np.empty((n, side * side), dtype=dtype)
+    for s0 in range(0, n, 10000):
+        s1 = min(n, s0 + 10000)
+        m = s1 - s0
+        pts[s0:s1] = (templates[labels[s0:s1]] + 0.3 * rng.standard_normal((m, 3)) @ var
+                      + 0.1 * rng.standard_normal((m, side * side)))
+    return pts, labels

@@ -181,3 +181,25 @@ def test_cluster_decode_rejects_bad_arguments_before_device_work(lib):
         assert call(**kw) == _lib.EINVAL, kw
         assert word in _lib.last_error(), (kw, _lib.last_error())
     assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
+
+
+def test_knn_graph_rejects_bad_arguments_before_device_work(lib):
+    info = _lib.CpcaInfo()
+    dummy = ctypes.c_void_p(16)
+    nnz = ctypes.c_int64()
+    sig = ctypes.c_double()
+    base = dict(N=100, d=3, K=10, norm=1, cap=100 * 21)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return lib.cpca_knn_graph(None, dummy, a["N"], a["d"], a["K"], a["norm"], dummy, dummy,
+                                  dummy, a["cap"], ctypes.byref(nnz), ctypes.byref(sig), None,
+                                  ctypes.byref(info))
+
+    cases = [(dict(N=1), "N must"), (dict(d=0), "d must"), (dict(K=0), "K must"),
+             (dict(K=29), "K must"), (dict(N=10, K=10, cap=210), "K must"),
+             (dict(norm=2), "normalized"), (dict(cap=100 * 21 - 1), "nnz_cap")]
+    for kw, word in cases:
+        assert call(**kw) == _lib.EINVAL, kw
+        assert word in _lib.last_error(), (kw, _lib.last_error())
+    assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
