@@ -10,7 +10,8 @@ the HBM traffic of that kernel from the committed counter summary (null when
 the kernel sources changed since the counters were taken), and the FP64 CPU
 oracle timed on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--workload video|face|tiny|batch|video-approx|cluster]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload video|face|tiny|batch|video-approx|cluster|knn]
                     [--copy-probe]   (device copies of known size, for counter calibration)
 """
 from __future__ import annotations
@@ -72,6 +73,10 @@ WORKLOADS = {
                 "latent 3-D 10-NN graph, 5% of the samples (all features), FISTA 500 it, then the "
                 "clustering decoder (Algorithm 3: k-means from 10 seeded samples, FP64 PCG "
                 "upsampling of the indicators, max pooling)", 1e-10),
+    "knn": ("digits_points", "K-NN graph of 70000 digit-shaped points of dimension 784 (10 "
+            "classes, smooth templates + rank-3 variation + noise), K = 10, Gaussian weights "
+            "with sigma = mean K-NN distance, normalised Laplacian; FP64 MFMA Gram tiles select "
+            "candidates, direct FP64 distances rank them", None),
     "batch": ("cfg5_batch", "64 instances, p log-uniform in [500, 4000] x n log-uniform in "
               "[200, 2000], rank 3-10, helix rows / circle columns, 5% outliers, 10% sampling, "
               "each swept over a 4 x 4 (gamma_r, gamma_c) grid in {0.1, 1, 10, 100}: 1024 tasks "
@@ -91,6 +96,27 @@ def algorithmic_apply_bytes(P, elem: int) -> int:
     lr = P.Lr.nnz * (4 + elem) + (P.p + 1) * 4
     lc = P.Lc.nnz * (4 + elem) + (P.n + 1) * 4
     return 2 * elem * pn + lr + lc + P.p + P.n
+
+
+# FP64 oracle values of X at fixed positions, written by the committed
+# scripts in tests/golden/ (they call only the input generators and the oracle)
+ORACLE_SAMPLES = {"video": "tests/golden/video_oracle_samples.npz",
+                  "face": "tests/golden/face_oracle_samples.npz"}
+ERR_BAR = 1e-5
+
+
+def oracle_sample_error(workload, X):
+    """Relative error of the decoded X against the stored FP64 oracle samples
+    (None when the workload has none)."""
+    import numpy as np
+    import torch
+    path = ORACLE_SAMPLES.get(workload)
+    if path is None or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    g = np.load(os.path.join(ROOT, path))
+    idx = torch.from_numpy(g["idx"]).to(X.device)
+    got = X.reshape(-1)[idx].double().cpu().numpy()
+    return float(np.linalg.norm(got - g["vals"]) / np.linalg.norm(g["vals"]))
 
 
 def cpu_baseline(P, J, tol, gpu_fp64_iters, max_seconds=25.0):
@@ -388,6 +414,98 @@ def run_cluster(args, desc, tol):
     return 0
 
 
+MFMA_F64_PEAK_TFLOPS = 78.6
+
+
+def knn_cpu_baseline(pts, K, max_seconds=20.0):
+    """The oracle's brute-force K-NN (oracle/knn.py) on one core for a
+    bounded number of query rows, extrapolated to all N rows."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import knn as OK
+    limiter = threadpool_limits(limits=1)
+    N = pts.shape[0]
+    rng = np.random.default_rng(3)
+    t0 = time.perf_counter()
+    OK.query_knn(pts, rng.choice(N, 2, replace=False), K)
+    t1 = (time.perf_counter() - t0) / 2
+    q = max(2, min(400, int(max_seconds / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    OK.query_knn(pts, rng.choice(N, q, replace=False), K)
+    per = (time.perf_counter() - t0) / q
+    limiter.unregister()
+    total = per * N
+    return {"value": N / total, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle brute-force K-NN (oracle/knn.py) for {q} query rows against "
+                       f"all {N} points ({per * 1e3:.1f} ms per row), extrapolated to {N} rows "
+                       f"(est. {total:.0f} s); the union, weights and Laplacian assembly are not "
+                       f"timed")}
+
+
+def run_knn(args, desc):
+    """K-NN graph construction on the digit-shaped point set. The roofline is
+    that of the candidate kernel's FP64 MFMA Gram tiles: 2 N^2 ceil4(d) flops
+    per launch over its HIP-event time, against the FP64 matrix peak."""
+    import numpy as np
+    import torch
+
+    import paper_1602_02070_amd as cp
+    import synth
+    log("[bench] building inputs: knn (70000 x 784)")
+    pts, _ = synth.digits_points(0)
+    N, d = pts.shape
+    K = 10
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    P = torch.from_numpy(pts).to(dev)
+    out = {}
+
+    def step():
+        L, info = cp.knn_graph(P, K, kind="normalized")
+        out["L"], out["info"] = L, info
+
+    for w in range(args.warmup):
+        step()
+        log(f"[bench] warmup {w + 1}/{args.warmup}: {out['info']['ms']:.1f} ms, "
+            f"nnz {out['info']['nnz']}")
+    cp.profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_t, ms_t = cp.get_profile("other")
+    cp.profiling(False)
+    flops = 2.0 * N * N * ((d + 3) // 4 * 4)
+    avg = ms_t / max(n_t, 1)
+    achieved = flops / (avg * 1e-3) / 1e12
+    # the graph itself: symmetric, unit diagonal
+    L = out["L"].to_scipy()
+    sym = float(abs(L - L.T).max())
+    line = {
+        "metric": "K-NN graph points/s (K-NN search + Gaussian weights + normalised Laplacian)",
+        "value": N * args.steps / elapsed, "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"knn: {desc}", "N": N, "d": d, "K": K,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "K-NN candidate kernel (FP64 MFMA 16x16x4 Gram tiles + selection)",
+                     "algorithmic_flops_per_launch": flops},
+        "extra": {"candidate_kernel_ms": avg, "nnz": out["info"]["nnz"],
+                  "sigma": out["info"]["sigma"], "max_asymmetry": sym},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = knn_cpu_baseline(pts, K)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def run_batch(args, desc, tol):
     """The batched workload: every task's FISTA + decode in one cpca_solve_batched
     call. The roofline line is a whole-solve rate: the algorithmic bytes of all
@@ -524,6 +642,8 @@ def main(argv=None):
         return run_approx(args, desc, tol)
     if args.workload == "cluster":
         return run_cluster(args, desc, tol)
+    if args.workload == "knn":
+        return run_knn(args, desc)
     log(f"[bench] building inputs: {args.workload}")
     P = getattr(synth, builder)(0)
     dt = torch.float64 if args.mode == "fp64" else torch.float32
@@ -583,7 +703,14 @@ def main(argv=None):
     avg_apply = ms_apply / max(n_work, 1)
     achieved = bytes_apply / (avg_apply * 1e-3) / 1e9 if n_work else None
 
-    extra = {"decode_iters": infos["decode"]["iters"],
+    # the result counts only at parity with the FP64 oracle (stored samples)
+    err_orc = oracle_sample_error(args.workload, X_out)
+    status = infos["decode"]["status"]
+    failed = status != 0 or (err_orc is not None and not err_orc <= ERR_BAR)
+    if failed:
+        log(f"[bench] RESULT INVALID: decode status {status}, rel.err vs oracle samples {err_orc}")
+    extra = {"rel_err_vs_oracle_samples": err_orc, "decode_status": status,
+             "decode_iters": infos["decode"]["iters"],
              "refinements": infos["decode"]["outer_iters"],
              "rel_residual_fp64": infos["decode"]["rel_residual"],
              "fista_iters": infos["fista"]["iters"],
@@ -607,7 +734,7 @@ def main(argv=None):
     line = {
         "metric": "recovered entries/s (FRPCAG FISTA + alternate decoder CG), rel.err<=1e-5 "
                   "vs FP64 oracle",
-        "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "value": None if failed else value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32_ir": "f32+f64-refine", "fp64": "f64", "fp32": "f32"}[args.mode],
@@ -629,7 +756,7 @@ def main(argv=None):
         log("[bench] timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(P, J, tol, fp64_iters)
     print(json.dumps(line), flush=True)
-    return 0
+    return 1 if failed else 0
 
 
 if __name__ == "__main__":
