@@ -294,6 +294,43 @@ cpca_status cpca_approx_decode(cpca_handle h, cpca_mode mode,
                                cpca_approx_info* info);
 
 /*
+ * Approximate decoders 2 and 3 (appendix, other approximate decoders): with
+ * the full data matrix Y available, only one subspace is upsampled.
+ *   decoder 2 (cpca_approx_decode2): the kept left singular vectors of X~
+ *     (k as in cpca_approx_decode) are upsampled over L_r and normalised to
+ *     unit columns U; X = U U^T Y.
+ *   decoder 3 (cpca_approx_decode3): the kept right singular vectors are
+ *     upsampled over L_c and normalised to V; X = Y V V^T.
+ * The paper writes these as X = U S~ s V^T with V = Y^T U S~^-1 / s (and the
+ * mirror image); the RIP scale s cancels, so delta is not an argument.
+ * Xtil        rho_r x rho_c (mode type), min(rho_r, rho_c) <= 4096.
+ * omega_r/_c  the sampled rows (decoder 2) or columns (decoder 3), distinct.
+ * Lr / Lc     the p x p or n x n Laplacian of that side (device, FP64 values).
+ * Y           p x n full data (mode type, device).
+ * sigma_ratio in [0, 1]; k_max in [1, 16].
+ * tol, max_iter, X_out, sigma_out as in cpca_approx_decode; info reports the
+ * upsampled side's CG iterations and residuals (the other side's are 0) and
+ * scale = 1.
+ * The SVD, the CG and the projections accumulate in FP64; Y is read once and
+ * X written once (two streaming passes plus partial sums of p x k or k x n).
+ * Returns OK, EINVAL, ENOCONV, ENOTSPD, ENAN, EHIP, ENOMEM.
+ */
+cpca_status cpca_approx_decode2(cpca_handle h, cpca_mode mode,
+                                const void* Xtil, int64_t rho_r, int64_t rho_c,
+                                const int32_t* omega_r, int64_t p, int64_t n,
+                                const cpca_csr* Lr, const void* Y,
+                                double sigma_ratio, int32_t k_max, double tol,
+                                int32_t max_iter, void* X_out, double* sigma_out,
+                                cpca_approx_info* info);
+cpca_status cpca_approx_decode3(cpca_handle h, cpca_mode mode,
+                                const void* Xtil, int64_t rho_r, int64_t rho_c,
+                                const int32_t* omega_c, int64_t p, int64_t n,
+                                const cpca_csr* Lc, const void* Y,
+                                double sigma_ratio, int32_t k_max, double tol,
+                                int32_t max_iter, void* X_out, double* sigma_out,
+                                cpca_approx_info* info);
+
+/*
  * Approximate decoder for clustering (Section VI, Algorithm 3). The rho_c
  * columns of X~ are the sampled points (dimension rho_r):
  *   1. k-means (Lloyd) from the k seed points init[0..k): assign each point

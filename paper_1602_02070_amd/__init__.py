@@ -8,6 +8,7 @@ binding. The library is loaded on first use; a missing build raises.
 from .api import (CpcaError, Decode, DecodeProblem, Graph, apply_operator,  # noqa: F401
                   decode, decode_backward, frpcag, get_profile, handle, mode_for,
                   profiling, set_apply_config, Instance, solve_batched, approx_decode,
-                  cluster_decode, laplacian_lmax, knn_graph)
+                  cluster_decode, laplacian_lmax, knn_graph,
+                  approx_decode_one_side)
 
 __version__ = "0.1.0"

@@ -17,7 +17,8 @@ EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
            "cpca_apply", "cpca_check_csr_host", "cpca_check_index_set_host",
            "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config",
            "cpca_solve_batched", "cpca_approx_decode", "cpca_cluster_decode",
-           "cpca_laplacian_lmax", "cpca_apply_noalloc", "cpca_knn_graph"]
+           "cpca_laplacian_lmax", "cpca_apply_noalloc", "cpca_knn_graph",
+           "cpca_approx_decode2", "cpca_approx_decode3"]
 
 
 class CpcaCsr(ctypes.Structure):
@@ -103,6 +104,12 @@ def _declare(lib):
         "cpca_approx_decode": (st, [P, c_int32, P, c_int64, c_int64, P, P, c_int64, c_int64, csr,
                                     csr, c_double, c_double, c_int32, c_double, c_int32, P,
                                     POINTER(c_double), POINTER(CpcaApproxInfo)]),
+        "cpca_approx_decode2": (st, [P, c_int32, P, c_int64, c_int64, P, c_int64, c_int64, csr, P,
+                                     c_double, c_int32, c_double, c_int32, P, POINTER(c_double),
+                                     POINTER(CpcaApproxInfo)]),
+        "cpca_approx_decode3": (st, [P, c_int32, P, c_int64, c_int64, P, c_int64, c_int64, csr, P,
+                                     c_double, c_int32, c_double, c_int32, P, POINTER(c_double),
+                                     POINTER(CpcaApproxInfo)]),
         "cpca_cluster_decode": (st, [P, c_int32, P, c_int64, c_int64, P, c_int64, csr, c_int32, P,
                                      c_int32, c_double, c_int32, P, P, P,
                                      POINTER(CpcaClusterInfo)]),

@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import CpcaApproxInfo, CpcaClusterInfo, CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
 
 __all__ = ["CpcaError", "Graph", "handle", "frpcag", "laplacian_lmax", "knn_graph", "decode",
-           "decode_backward",
+           "decode_backward", "approx_decode_one_side",
            "apply_operator", "Decode", "DecodeProblem", "profiling", "get_profile",
            "mode_for", "set_apply_config", "Instance", "solve_batched"]
 
@@ -276,6 +276,35 @@ def approx_decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tens
                                         float(delta), float(sigma_ratio), int(k_max), float(tol),
                                         int(max_iter), _ptr(out), sigma, ctypes.byref(info))
     _check(st, "cpca_approx_decode")
+    return out, [sigma[i] for i in range(min(Xt.shape))], info.as_dict()
+
+
+def approx_decode_one_side(side: str, Xtil: torch.Tensor, omega: torch.Tensor, p: int, n: int,
+                           L: Graph, Y: torch.Tensor, sigma_ratio: float = 0.1, k_max: int = 16,
+                           tol: float = 1e-10, max_iter: int = 20000, mode: str | None = None,
+                           out: torch.Tensor | None = None, h=None):
+    """Approximate decoders 2 and 3 of the appendix: side "rows" upsamples
+    the left singular vectors of X~ over L_r and returns X = U U^T Y; side
+    "cols" upsamples the right ones over L_c and returns X = Y V V^T. Y is
+    the full p x n data. Returns (X, sigma, info) as approx_decode."""
+    if side not in ("rows", "cols"):
+        raise ValueError("side must be 'rows' or 'cols'")
+    mode = mode_for(Xtil.dtype, mode)
+    dt = _dtype_of(mode)
+    Xt = _need(Xtil, "Xtil", dt)
+    Yd = _need(Y, "Y", dt, (p, n))
+    om = _index(omega, "omega")
+    if out is None:
+        out = torch.empty((p, n), dtype=dt, device=Xt.device)
+    else:
+        out = _need(out, "out", dt, (p, n))
+    sigma = (ctypes.c_double * max(1, min(Xt.shape)))()
+    info = CpcaApproxInfo()
+    fn = _lib.load().cpca_approx_decode2 if side == "rows" else _lib.load().cpca_approx_decode3
+    st = fn(h or handle(Xt.device), _lib.MODES[mode], _ptr(Xt), Xt.shape[0], Xt.shape[1], _ptr(om),
+            int(p), int(n), ctypes.byref(L.desc), _ptr(Yd), float(sigma_ratio), int(k_max),
+            float(tol), int(max_iter), _ptr(out), sigma, ctypes.byref(info))
+    _check(st, "cpca_approx_decode2" if side == "rows" else "cpca_approx_decode3")
     return out, [sigma[i] for i in range(min(Xt.shape))], info.as_dict()
 
 

@@ -599,6 +599,138 @@ __global__ void __launch_bounds__(kThreads) k_fill_zero(TO* __restrict__ X, size
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) X[e] = TO(0);
 }
 
+// --------------------------------- one-side decoders (appendix: decoders 2, 3)
+// One workgroup: w_c = 1 / ||S_c||^2 for c < k (0 past k), so that
+// S diag(w) S^T = U U^T for the unit columns U = S / ||S||; rel = the final
+// recursive CG residuals of the side.
+__global__ void __launch_bounds__(kThreads)
+k_up_unitw(UpSide a, int KP, int k, double* __restrict__ w, double* __restrict__ rel) {
+  __shared__ double red[kThreads];
+  const double n2 = col_total(a.pa, a.nb, KP, 0, red);
+  const int c = threadIdx.x;
+  if (c >= KP) return;
+  w[c] = (c < k && n2 > 0.0) ? 1.0 / n2 : 0.0;
+  const double bb = s_bb(a)[c];
+  rel[c] = c < k && bb > 0.0 ? sqrt(s_rr(a)[c] / bb) : 0.0;
+}
+
+// Decoder 2, G = S^T Y (KP x n), first pass: workgroup (strip, chunk) sums
+// rows [chunk * rows_per, ...) of S[i, c] Y[i, j] for its kThreads * VEC
+// columns; partials Gp[chunk][c][j]. Each S row (KP values) is the same for
+// the whole workgroup.
+template <typename T, int KPT, int VEC>
+__global__ void __launch_bounds__(kThreads)
+k_proj_left(const T* __restrict__ Y, const double* __restrict__ S, int p, int n, int KP,
+            int rows_per, int nstrips, double* __restrict__ Gp) {
+  const int strip = blockIdx.x % nstrips;
+  const int chunk = blockIdx.x / nstrips;
+  const int j0 = (strip * kThreads + (int)threadIdx.x) * VEC;
+  const int i0 = chunk * rows_per, i1 = min(p, i0 + rows_per);
+  double acc[KPT][VEC];
+#pragma unroll
+  for (int c = 0; c < KPT; ++c)
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) acc[c][q] = 0.0;
+  if (j0 < n) {
+    const bool full = j0 + VEC <= n;
+    for (int i = i0; i < i1; ++i) {
+      T y[VEC];
+      const T* src = Y + (size_t)i * n + j0;
+      if (VEC > 1 && full) {
+        vld<T, VEC>(src, y);
+      } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) y[q] = j0 + q < n ? src[q] : T(0);
+      }
+      const double* srow = S + (size_t)i * KP;
+#pragma unroll
+      for (int c = 0; c < KPT; ++c) {
+        const double sc = c < KP ? srow[c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[c][q] += sc * (double)y[q];
+      }
+    }
+  }
+  double* dst = Gp + (size_t)chunk * KP * n;
+#pragma unroll
+  for (int c = 0; c < KPT; ++c)
+    if (c < KP)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q)
+        if (j0 + q < n) dst[(size_t)c * n + j0 + q] = acc[c][q];
+}
+
+// Decoder 2, second pass: Gt[j][c] = sum over chunks of Gp[chunk][c][j]
+// (fixed order), written n x KP for the rank-k output kernel.
+__global__ void __launch_bounds__(kThreads)
+k_proj_left_sum(const double* __restrict__ Gp, int nchunks, int n, int KP, double* __restrict__ Gt) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * KP) return;
+  const int j = (int)(e / KP), c = (int)(e % KP);
+  double s = 0.0;
+  for (int b = 0; b < nchunks; ++b) s += Gp[((size_t)b * KP + c) * n + j];
+  Gt[e] = s;
+}
+
+// Decoder 3, G = Y S (p x KP), first pass: each wave owns a strip of
+// 64 * VEC columns (its S rows in registers) and walks the rows of its
+// workgroup's row range; per row the KP sums over the strip are reduced
+// across the wave and written as partials Gp[i][wstrip][c].
+template <typename T, int KPT, int VEC>
+__global__ void __launch_bounds__(kThreads)
+k_proj_right(const T* __restrict__ Y, const double* __restrict__ S, int p, int n, int KP,
+             int rows_per, int nwg_strips, int nwstrips, double* __restrict__ Gp) {
+  const int wg_strip = blockIdx.x % nwg_strips;
+  const int rg = blockIdx.x / nwg_strips;
+  const int lane = threadIdx.x & 63;
+  const int wstrip = wg_strip * kMaxWaves + (int)threadIdx.x / 64;
+  const int j0 = (wstrip * 64 + lane) * VEC;
+  const int i0 = rg * rows_per, i1 = min(p, i0 + rows_per);
+  if (wstrip >= nwstrips) return;  // whole wave
+  double sv[VEC][KPT];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q)
+#pragma unroll
+    for (int c = 0; c < KPT; ++c)
+      sv[q][c] = (j0 + q < n && c < KP) ? S[(size_t)(j0 + q) * KP + c] : 0.0;
+  const bool full = j0 + VEC <= n;
+  for (int i = i0; i < i1; ++i) {
+    T y[VEC];
+    const T* src = Y + (size_t)i * n + j0;
+    if (VEC > 1 && full) {
+      vld<T, VEC>(src, y);
+    } else {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) y[q] = j0 + q < n ? src[q] : T(0);
+    }
+    double acc[KPT];
+#pragma unroll
+    for (int c = 0; c < KPT; ++c) {
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) a += (double)y[q] * sv[q][c];
+      acc[c] = wave_sum(a);
+    }
+    if (lane == 0) {
+      double* dst = Gp + ((size_t)i * nwstrips + wstrip) * KP;
+#pragma unroll
+      for (int c = 0; c < KPT; ++c)
+        if (c < KP) dst[c] = acc[c];
+    }
+  }
+}
+
+// Decoder 3, second pass: G[i][c] = sum over wave strips of Gp[i][s][c].
+__global__ void __launch_bounds__(kThreads)
+k_proj_right_sum(const double* __restrict__ Gp, int nwstrips, int p, int KP, double* __restrict__ G) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)p * KP) return;
+  const int i = (int)(e / KP), c = (int)(e % KP);
+  double s = 0.0;
+  for (int b = 0; b < nwstrips; ++b) s += Gp[((size_t)i * nwstrips + b) * KP + c];
+  G[e] = s;
+}
+
 // ---------------------------------------------- clustering (Algorithm 3)
 // Points (rho_c x rho_r, FP64): point j is column j of X~ (rho_r x rho_c).
 template <typename TI>
@@ -765,6 +897,71 @@ hipError_t launch_rank_k(hipStream_t st, TO* X, const double* U, const double* V
   }
 }
 
+// One-side projections of decoders 2 and 3: side 0: Gt = (S^T Y)^T (n x KP),
+// side 1: G = Y S (p x KP), each as a partial-sum pass plus a fixed-order sum.
+// Gp must hold proj_partials(...) doubles.
+inline int proj_vec(size_t elem, int n) {
+  const int v = (int)(16 / elem);
+  return n % v == 0 ? v : 1;
+}
+inline size_t proj_partials(int side, size_t elem, int p, int n, int KP) {
+  const int vec = proj_vec(elem, n);
+  if (side == 0) {
+    const int nstrips = (n + kThreads * vec - 1) / (kThreads * vec);
+    const int nchunks = std::min(std::max(1, (1024 + nstrips - 1) / nstrips), std::min(p, 128));
+    return (size_t)nchunks * KP * n;
+  }
+  const int nwstrips = (n + 64 * vec - 1) / (64 * vec);
+  return (size_t)p * nwstrips * KP;
+}
+
+template <int KPT, int VEC, typename T>
+hipError_t launch_proj_v(hipStream_t st, int side, const T* Y, const double* S, int p, int n,
+                         int KP, double* Gp, double* G) {
+  if (side == 0) {
+    const int nstrips = (n + kThreads * VEC - 1) / (kThreads * VEC);
+    int nchunks = std::min(std::max(1, (1024 + nstrips - 1) / nstrips), std::min(p, 128));
+    const int rows_per = (p + nchunks - 1) / nchunks;
+    nchunks = (p + rows_per - 1) / rows_per;
+    k_proj_left<T, KPT, VEC><<<nstrips * nchunks, kThreads, 0, st>>>(Y, S, p, n, KP, rows_per,
+                                                                    nstrips, Gp);
+    k_proj_left_sum<<<(int)(((size_t)n * KP + kThreads - 1) / kThreads), kThreads, 0, st>>>(
+        Gp, nchunks, n, KP, G);
+  } else {
+    const int nwstrips = (n + 64 * VEC - 1) / (64 * VEC);
+    const int nwg = (nwstrips + kMaxWaves - 1) / kMaxWaves;
+    const int ngroups = std::min(std::max(1, (1024 + nwg - 1) / nwg), p);
+    const int rows_per = (p + ngroups - 1) / ngroups;
+    const int ng = (p + rows_per - 1) / rows_per;
+    k_proj_right<T, KPT, VEC><<<nwg * ng, kThreads, 0, st>>>(Y, S, p, n, KP, rows_per, nwg,
+                                                            nwstrips, Gp);
+    k_proj_right_sum<<<(int)(((size_t)p * KP + kThreads - 1) / kThreads), kThreads, 0, st>>>(
+        Gp, nwstrips, p, KP, G);
+  }
+  return hipGetLastError();
+}
+
+template <int KPT, typename T>
+hipError_t launch_proj_t(hipStream_t st, int side, const T* Y, const double* S, int p, int n,
+                         int KP, double* Gp, double* G) {
+  constexpr int VW = (int)(16 / sizeof(T));
+  if (proj_vec(sizeof(T), n) == VW) return launch_proj_v<KPT, VW, T>(st, side, Y, S, p, n, KP, Gp, G);
+  return launch_proj_v<KPT, 1, T>(st, side, Y, S, p, n, KP, Gp, G);
+}
+
+template <typename T>
+hipError_t launch_proj(hipStream_t st, int side, const T* Y, const double* S, int p, int n, int KP,
+                       double* Gp, double* G) {
+  switch (KP) {
+    case 1: return launch_proj_t<1, T>(st, side, Y, S, p, n, KP, Gp, G);
+    case 2: return launch_proj_t<2, T>(st, side, Y, S, p, n, KP, Gp, G);
+    case 4: return launch_proj_t<4, T>(st, side, Y, S, p, n, KP, Gp, G);
+    case 8: return launch_proj_t<8, T>(st, side, Y, S, p, n, KP, Gp, G);
+    case 16: return launch_proj_t<16, T>(st, side, Y, S, p, n, KP, Gp, G);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 struct SideHost {
   std::vector<int32_t> inv;
   std::vector<double> dinv;
@@ -882,21 +1079,32 @@ cpca_status upsample_solve(cpca_handle h, const UpSide& A, const UpSide& B, int 
   return CPCA_OK;
 }
 
+// variant 0: Algorithm 2 (both graphs); 1: decoder 2 (row graph only,
+// X = U U^T Y); 2: decoder 3 (column graph only, X = Y V V^T). The one-side
+// variants take the full data Y (p x n) and ignore the absent side's
+// arguments (omega, L, delta).
 template <typename T>
 cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
                        const int32_t* om_r, const int32_t* om_c, int64_t p, int64_t n,
                        const cpca_csr* Lr, const cpca_csr* Lc, double delta, double ratio,
                        int32_t k_max, double tol, int32_t max_iter, T* X_out, double* sigma_out,
-                       cpca_approx_info* info) {
+                       cpca_approx_info* info, int variant = 0, const T* Y = nullptr) {
   const auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipStreamSynchronize(h->stream));  // inputs may still be in flight
+  const bool use_r = variant != 2, use_c = variant != 1;
   HostCsr hLr, hLc;
-  STCHK(fetch_csr("Lr", Lr, hLr));
-  STCHK(fetch_csr("Lc", Lc, hLc));
   std::vector<int32_t> wr, wc;
-  STCHK(fetch_indices("omega_r", om_r, rho_r, p, wr));
-  STCHK(fetch_indices("omega_c", om_c, rho_c, n, wc));
-  const SideHost sr = side_tables(hLr, wr), sc = side_tables(hLc, wc);
+  SideHost sr, sc;
+  if (use_r) {
+    STCHK(fetch_csr("Lr", Lr, hLr));
+    STCHK(fetch_indices("omega_r", om_r, rho_r, p, wr));
+    sr = side_tables(hLr, wr);
+  }
+  if (use_c) {
+    STCHK(fetch_csr("Lc", Lc, hLc));
+    STCHK(fetch_indices("omega_c", om_c, rho_c, n, wc));
+    sc = side_tables(hLc, wc);
+  }
 
   const int trans = rho_r >= rho_c ? 1 : 0;
   const int m = (int)std::min(rho_r, rho_c);
@@ -916,7 +1124,7 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
          *rel = nullptr, *fro2 = nullptr;
   int2* pairs = nullptr;
   int *cnt = nullptr, *perm = nullptr, *kdev = nullptr, *inv_r = nullptr, *inv_c = nullptr;
-  double *dinv_r = nullptr, *dinv_c = nullptr;
+  double *dinv_r = nullptr, *dinv_c = nullptr, *gproj = nullptr, *gpart = nullptr;
   UpSide A, B;  // A: rows (L_r), B: columns (L_c)
   auto grid_for = [&](int64_t) { return kUpMaxBlocks; };  // partial buffers: the largest grid
   auto layout = [&](Arena& a) {
@@ -936,6 +1144,10 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
     inv_c = a.take<int>((size_t)n);
     dinv_r = a.take<double>((size_t)p);
     dinv_c = a.take<double>((size_t)n);
+    if (variant != 0) {
+      gproj = a.take<double>((size_t)std::max(p, n) * KPmax);
+      gpart = a.take<double>(proj_partials(variant - 1, sizeof(T), (int)p, (int)n, KPmax));
+    }
     for (int side = 0; side < 2; ++side) {
       UpSide& s = side == 0 ? A : B;
       const int64_t c = side == 0 ? p : n;
@@ -965,10 +1177,14 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
   hipStream_t st = h->stream;
   if (!rr_tab.empty())
     HIPCHK(hipMemcpyAsync(pairs, rr_tab.data(), sizeof(int2) * rr_tab.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(inv_r, sr.inv.data(), sizeof(int) * p, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(inv_c, sc.inv.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(dinv_r, sr.dinv.data(), sizeof(double) * p, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(dinv_c, sc.dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  if (use_r) {
+    HIPCHK(hipMemcpyAsync(inv_r, sr.inv.data(), sizeof(int) * p, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dinv_r, sr.dinv.data(), sizeof(double) * p, hipMemcpyHostToDevice, st));
+  }
+  if (use_c) {
+    HIPCHK(hipMemcpyAsync(inv_c, sc.inv.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dinv_c, sc.dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  }
 
   // ---- 1. one-sided Jacobi SVD
   k_jac_load<T><<<vec_grid((size_t)rho_r * rho_c), kThreads, 0, st>>>(W, Q, Xt, (int)rho_r,
@@ -1053,7 +1269,9 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
     info->reserved = 0;
     info->rel_residual_r = rel_r;
     info->rel_residual_c = rel_c;
-    info->scale = std::sqrt((double)n * (double)p / ((double)rho_r * (double)rho_c * (1.0 - delta)));
+    info->scale = variant != 0 ? 1.0
+                               : std::sqrt((double)n * (double)p /
+                                           ((double)rho_r * (double)rho_c * (1.0 - delta)));
     info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   };
   const size_t NX = (size_t)p * n;
@@ -1072,6 +1290,7 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
     UpSide& s = side == 0 ? A : B;
     s.nb = (int)std::max<int64_t>(1, std::min<int64_t>(kUpMaxBlocks, ((int64_t)s.c * KP + kThreads - 1) / kThreads));
     const cpca_csr* L = side == 0 ? Lr : Lc;
+    if (!L) continue;  // the absent side of a one-side decoder (never launched)
     s.rp = L->rowptr;
     s.ci = L->colind;
     s.v = L->vals;
@@ -1085,22 +1304,50 @@ cpca_status run_approx(cpca_handle h, const T* Xt, int64_t rho_r, int64_t rho_c,
                                                                        lv, sv);
   LAUNCHCHK();
 
-  // ---- 3. upsampling, both graphs in the same launches
   std::vector<int> hstate;
-  STCHK(upsample_solve(h, A, B, 2, KP, k, tol, max_iter, hstate));
-  // ---- 4.-6. norms, weights, X = U diag(w) V^T
-  const double scale = std::sqrt((double)n * (double)p / ((double)rho_r * (double)rho_c * (1.0 - delta)));
-  k_up_weights<<<1, kThreads, 0, st>>>(A, B, KP, k, sig, scale, wts, rel);
-  LAUNCHCHK();
-  STCHK(prof_begin(h, FAM_RANKK));
-  HIPCHK(launch_rank_k<T>(st, X_out, A.S, B.S, wts, (int)p, (int)n, KP));
-  STCHK(prof_end(h));
-  std::vector<double> hrel(2 * (size_t)KP);
-  HIPCHK(hipMemcpyAsync(hrel.data(), rel, sizeof(double) * 2 * KP, hipMemcpyDeviceToHost, st));
-  STCHK(read_states(h, A, B, 2, hstate));
-  STCHK(prof_collect(h));
+  std::vector<double> hrel(2 * (size_t)KP, 0.0);
   int it_r = 0, it_c = 0, worst = 0;
   double rel_r = 0.0, rel_c = 0.0;
+  if (variant == 0) {
+    // ---- 3. upsampling, both graphs in the same launches
+    STCHK(upsample_solve(h, A, B, 2, KP, k, tol, max_iter, hstate));
+    // ---- 4.-6. norms, weights, X = U diag(w) V^T
+    const double scale = std::sqrt((double)n * (double)p / ((double)rho_r * (double)rho_c * (1.0 - delta)));
+    k_up_weights<<<1, kThreads, 0, st>>>(A, B, KP, k, sig, scale, wts, rel);
+    LAUNCHCHK();
+    STCHK(prof_begin(h, FAM_RANKK));
+    HIPCHK(launch_rank_k<T>(st, X_out, A.S, B.S, wts, (int)p, (int)n, KP));
+    STCHK(prof_end(h));
+    HIPCHK(hipMemcpyAsync(hrel.data(), rel, sizeof(double) * 2 * KP, hipMemcpyDeviceToHost, st));
+    STCHK(read_states(h, A, B, 2, hstate));
+  } else {
+    // ---- one graph side: upsample, unit columns, project the full data
+    UpSide& U1 = variant == 1 ? A : B;
+    UpSide& U2 = variant == 1 ? B : A;
+    STCHK(upsample_solve(h, U1, U2, 1, KP, k, tol, max_iter, hstate));
+    k_up_unitw<<<1, kThreads, 0, st>>>(U1, KP, k, wts, rel);
+    LAUNCHCHK();
+    HIPCHK(launch_proj<T>(st, variant - 1, Y, U1.S, (int)p, (int)n, KP, gpart, gproj));
+    STCHK(prof_begin(h, FAM_RANKK));
+    if (variant == 1)   // X = S diag(w) (S^T Y)
+      HIPCHK(launch_rank_k<T>(st, X_out, U1.S, gproj, wts, (int)p, (int)n, KP));
+    else                // X = (Y S) diag(w) S^T
+      HIPCHK(launch_rank_k<T>(st, X_out, gproj, U1.S, wts, (int)p, (int)n, KP));
+    STCHK(prof_end(h));
+    HIPCHK(hipMemcpyAsync(hrel.data() + (variant == 1 ? 0 : KP), rel, sizeof(double) * KP,
+                          hipMemcpyDeviceToHost, st));
+    std::vector<int> hs1;
+    STCHK(read_states(h, U1, U2, 1, hs1));
+    // side states in the (rows, columns) order of the report
+    hstate.assign(2 * 2 * kApproxKMax, 1);
+    std::copy(hs1.begin(), hs1.begin() + 2 * kApproxKMax,
+              hstate.begin() + (variant == 1 ? 0 : 2 * kApproxKMax));
+    if (variant == 1)
+      std::fill(hstate.begin() + 3 * kApproxKMax, hstate.end(), 0);   // no column iterations
+    else
+      std::fill(hstate.begin() + kApproxKMax, hstate.begin() + 2 * kApproxKMax, 0);
+  }
+  STCHK(prof_collect(h));
   for (int c = 0; c < k; ++c) {
     const int dr = hstate[(size_t)c], dc = hstate[(size_t)2 * kApproxKMax + c];
     it_r = std::max(it_r, hstate[(size_t)kApproxKMax + c]);
@@ -1289,4 +1536,75 @@ extern "C" cpca_status cpca_approx_decode(cpca_handle h, cpca_mode mode, const v
   return run_approx<float>(h, static_cast<const float*>(Xtil), rho_r, rho_c, omega_r, omega_c, p,
                            n, Lr, Lc, delta, sigma_ratio, k_max, tol, max_iter,
                            static_cast<float*>(X_out), sigma_out, info);
+}
+
+// Approximate decoders 2 and 3 (appendix): one graph side, full data Y.
+namespace {
+cpca_status check_one_side_args(const char* who, cpca_mode mode, int64_t rho_r, int64_t rho_c,
+                                const int32_t* omega, int64_t rho, int64_t dim, int64_t p,
+                                int64_t n, const cpca_csr* L, const void* Y, double ratio,
+                                int32_t k_max, double tol, int32_t max_iter) {
+  cpca_status st;
+  const std::string w(who);
+  if ((st = check_mode(mode))) return st;
+  if ((st = check_dims("X", p, n))) return st;
+  if ((unsigned long long)p * (unsigned long long)n > (1ull << 40))
+    return fail(CPCA_EINVAL, w + ": p * n too large");
+  if ((st = check_dims("Xtil", rho_r, rho_c))) return st;
+  if (rho_r > p || rho_c > n) return fail(CPCA_EINVAL, w + ": more samples than rows/columns");
+  if (rho > dim) return fail(CPCA_EINVAL, w + ": more samples than graph nodes");
+  if (!omega) return fail(CPCA_EINVAL, w + ": null index set");
+  if ((st = check_csr_shape("L", L, dim))) return st;
+  if (!Y) return fail(CPCA_EINVAL, w + ": null Y");
+  if (!std::isfinite(ratio) || ratio < 0 || ratio > 1)
+    return fail(CPCA_EINVAL, w + ": sigma_ratio must be in [0, 1]");
+  if (k_max < 1 || k_max > 16) return fail(CPCA_EINVAL, w + ": k_max must be in [1, 16]");
+  if (!std::isfinite(tol) || !(tol > 0)) return fail(CPCA_EINVAL, w + ": tol must be > 0");
+  if (max_iter < 0) return fail(CPCA_EINVAL, w + ": max_iter < 0");
+  return CPCA_OK;
+}
+}  // namespace
+
+extern "C" cpca_status cpca_approx_decode2(cpca_handle h, cpca_mode mode, const void* Xtil,
+                                           int64_t rho_r, int64_t rho_c, const int32_t* omega_r,
+                                           int64_t p, int64_t n, const cpca_csr* Lr,
+                                           const void* Y, double sigma_ratio, int32_t k_max,
+                                           double tol, int32_t max_iter, void* X_out,
+                                           double* sigma_out, cpca_approx_info* info) {
+  clear_error();
+  STCHK(check_one_side_args("approx_decode2", mode, rho_r, rho_c, omega_r, rho_r, p, p, n, Lr, Y,
+                            sigma_ratio, k_max, tol, max_iter));
+  if (!Xtil || !X_out) return fail(CPCA_EINVAL, "approx_decode2: null data pointer");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  if (mode == CPCA_FP64)
+    return run_approx<double>(h, static_cast<const double*>(Xtil), rho_r, rho_c, omega_r, nullptr,
+                              p, n, Lr, nullptr, 0.0, sigma_ratio, k_max, tol, max_iter,
+                              static_cast<double*>(X_out), sigma_out, info, 1,
+                              static_cast<const double*>(Y));
+  return run_approx<float>(h, static_cast<const float*>(Xtil), rho_r, rho_c, omega_r, nullptr, p,
+                           n, Lr, nullptr, 0.0, sigma_ratio, k_max, tol, max_iter,
+                           static_cast<float*>(X_out), sigma_out, info, 1,
+                           static_cast<const float*>(Y));
+}
+
+extern "C" cpca_status cpca_approx_decode3(cpca_handle h, cpca_mode mode, const void* Xtil,
+                                           int64_t rho_r, int64_t rho_c, const int32_t* omega_c,
+                                           int64_t p, int64_t n, const cpca_csr* Lc,
+                                           const void* Y, double sigma_ratio, int32_t k_max,
+                                           double tol, int32_t max_iter, void* X_out,
+                                           double* sigma_out, cpca_approx_info* info) {
+  clear_error();
+  STCHK(check_one_side_args("approx_decode3", mode, rho_r, rho_c, omega_c, rho_c, n, p, n, Lc, Y,
+                            sigma_ratio, k_max, tol, max_iter));
+  if (!Xtil || !X_out) return fail(CPCA_EINVAL, "approx_decode3: null data pointer");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  if (mode == CPCA_FP64)
+    return run_approx<double>(h, static_cast<const double*>(Xtil), rho_r, rho_c, nullptr, omega_c,
+                              p, n, nullptr, Lc, 0.0, sigma_ratio, k_max, tol, max_iter,
+                              static_cast<double*>(X_out), sigma_out, info, 2,
+                              static_cast<const double*>(Y));
+  return run_approx<float>(h, static_cast<const float*>(Xtil), rho_r, rho_c, nullptr, omega_c, p,
+                           n, nullptr, Lc, 0.0, sigma_ratio, k_max, tol, max_iter,
+                           static_cast<float*>(X_out), sigma_out, info, 2,
+                           static_cast<const float*>(Y));
 }

@@ -192,7 +192,7 @@ def _blobs(h, w, nframes, frac, rng):
 
 
 def cfg3_video(seed: int = 0, shape=(128, 160), nframes: int = 4096,
-               frac: float = 0.05) -> Problem:
+               frac: float = 0.05, keep_full: bool = False) -> Problem:
     """Video-shaped stand-in: p = 128*160 pixels, n = 4096 frames (10-NN on the
     frame-time coordinate: a band graph), rank-5 background plus moving 8x8
     blobs on 2% of entries with values U(0.5, 1), 5% row/column sampling."""
@@ -204,13 +204,14 @@ def cfg3_video(seed: int = 0, shape=(128, 160), nframes: int = 4096,
     sv = _scaled_sv(rng, 5, p, nframes)
     return make_problem("cfg3_video", rows, cols, 5, rng, sv=sv,
                         extra=_blobs(h, w, nframes, 0.02, rng),
-                        frac_r=frac, frac_c=frac, fista_iters=500, tol=1e-10)
+                        frac_r=frac, frac_c=frac, fista_iters=500, tol=1e-10,
+                        keep_full=keep_full)
 
 
 def small_problem(seed: int, p_shape=(12, 10), n: int = 150, rank: int = 4,
                   frac: float = 0.3, gamma=(1.0, 1.0), kind="normalized",
                   K: int = 10, fista_iters: int = 100, tol: float = 1e-10,
-                  col_kind: str = "circle") -> Problem:
+                  col_kind: str = "circle", keep_full: bool = False) -> Problem:
     """Scaled-down instance for parity tests: pixel-grid rows, circle or band
     columns. Sizes are free so that tests can span tiles and ragged tails."""
     rng = np.random.default_rng(seed)
@@ -225,7 +226,7 @@ def small_problem(seed: int, p_shape=(12, 10), n: int = 150, rank: int = 4,
                         noise_std=0.05, outlier_frac=0.05, frac_r=frac,
                         frac_c=frac, min_rho=K + 2, K=K, kind=kind,
                         gamma_r=gamma[0], gamma_c=gamma[1],
-                        fista_iters=fista_iters, tol=tol)
+                        fista_iters=fista_iters, tol=tol, keep_full=keep_full)
 
 
 def cfg5_batch(seed: int = 0, count: int = 64, scale: float = 1.0):

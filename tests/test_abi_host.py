@@ -24,7 +24,7 @@ def lib():
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "cpca.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(cpca_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(cpca_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_every_declared_function_is_exported(lib):
@@ -203,3 +203,27 @@ def test_knn_graph_rejects_bad_arguments_before_device_work(lib):
         assert call(**kw) == _lib.EINVAL, kw
         assert word in _lib.last_error(), (kw, _lib.last_error())
     assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
+
+
+def test_one_side_decoders_reject_bad_arguments_before_device_work(lib):
+    info = _lib.CpcaApproxInfo()
+    dummy = ctypes.c_void_p(16)
+    Lr, k1 = _csr(10)
+    Lc, k2 = _csr(20)
+    base = dict(mode=1, rho_r=5, rho_c=6, p=10, n=20, ratio=0.1, kmax=16, tol=1e-10, it=100,
+                Y=dummy)
+    for fn, L, dimkey in ((lib.cpca_approx_decode2, Lr, "p"), (lib.cpca_approx_decode3, Lc, "n")):
+        def call(**kw):
+            a = dict(base, **kw)
+            return fn(None, a["mode"], dummy, a["rho_r"], a["rho_c"], dummy, a["p"], a["n"],
+                      ctypes.byref(L), a["Y"], a["ratio"], a["kmax"], a["tol"], a["it"], dummy,
+                      None, ctypes.byref(info))
+
+        cases = [(dict(mode=5), "mode"), (dict(n=0), "size"), (dict(rho_c=21), "samples"),
+                 (dict(ratio=1.5), "sigma_ratio"), (dict(kmax=0), "k_max"),
+                 (dict(kmax=17), "k_max"), (dict(tol=-1.0), "tol"), (dict(it=-1), "max_iter"),
+                 (dict(Y=None), "null Y"), ({dimkey: 11}, "L")]
+        for kw, word in cases:
+            assert call(**kw) == _lib.EINVAL, kw
+            assert word in _lib.last_error(), (kw, _lib.last_error())
+        assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
