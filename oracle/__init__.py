@@ -19,6 +19,8 @@ Contents (each function cites the passage it follows):
   cluster -- the approximate decoder for clustering (Algorithm 3, Section
              VI): Lloyd's k-means from given seeds, upsampling of the cluster
              indicators over the column graph, max pooling.
+  kron    -- Kron reduction of a Laplacian onto the sampled nodes (Section
+             IV-A): the Schur complement, written out.
   knn     -- K-nearest-neighbour Gaussian-kernel graphs and their
              combinatorial / normalised Laplacians (Section II, graph
              construction in Section VII-A), by brute force.
@@ -27,4 +29,4 @@ Every floating-point computation is FP64. Parity status of each function is
 stated in its docstring; all functions here are pinned by tests that check
 them against closed forms, brute force or invariants fixed by the paper.
 """
-from . import frpcag, decoder, approx, cluster, knn  # noqa: F401
+from . import frpcag, decoder, approx, cluster, knn, kron  # noqa: F401

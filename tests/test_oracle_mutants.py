@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 from tests import (test_oracle_approx_pins, test_oracle_cluster_pins, test_oracle_knn_pins,
-                   test_oracle_pins)
+                   test_oracle_kron_pins, test_oracle_pins)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -93,6 +93,14 @@ MUTANTS = [
     ("cluster", "        if it >= max_iter:", "        if it > max_iter:", "k-means cap off by one"),
     ("cluster", "return np.argmax(np.asarray(C), axis=1)", "return np.argmin(np.asarray(C), axis=1)",
      "min pooling"),
+    # Kron reduction (Section IV-A)
+    ("kron", "    return L_oo - L_or[:, keep] @ Xs", "    return L_oo + L_or[:, keep] @ Xs",
+     "Schur complement with the wrong sign"),
+    ("kron", "    rhs = B[keep].toarray()", "    rhs = B[keep].toarray() * 0.5", "half of the coupling"),
+    ("kron", "    keep = np.flatnonzero(touches[lab])", "    keep = np.arange(rest.size)",
+     "unsampled components without samples kept in the solve"),
+    ("kron", "    L_oo = L[omega][:, omega].toarray()", "    L_oo = np.diag(L[omega][:, omega].diagonal())",
+     "sampled-block off-diagonal dropped"),
     # K-NN graphs (Section II)
     ("knn", "order = np.lexsort((cand, d2[a, cand]))[:K]", "order = np.lexsort((-cand, d2[a, cand]))[:K]",
      "ties to the higher index"),
@@ -112,7 +120,7 @@ MUTANTS = [
 ]
 
 PIN_MODULES = (test_oracle_pins, test_oracle_approx_pins, test_oracle_cluster_pins,
-               test_oracle_knn_pins)
+               test_oracle_knn_pins, test_oracle_kron_pins)
 
 
 def _pin_cases():
