@@ -186,6 +186,31 @@ cpca_status cpca_knn_graph(cpca_handle h, const double* points, int64_t N, int64
                            cpca_info* info);
 
 /*
+ * Kron reduction of a graph Laplacian onto sampled nodes (Section IV-A,
+ * graphs for compressed data):
+ *   L~ = L(Omega, Omega) - L(Omega, Omega-bar) L(Omega-bar, Omega-bar)^-1 L(Omega-bar, Omega).
+ * It equals the sampled rows of L S, where S upsamples the unit vectors on
+ * Omega (S = I there, -L(bar, bar)^-1 L(bar, Omega) elsewhere); S is solved
+ * by the upsampling PCG of cpca_approx_decode, 64 columns at a time, each
+ * column to ||r|| <= tol ||b||. A component of the unsampled subgraph with no
+ * edge to Omega contributes nothing. The result is symmetrised,
+ * (L~ + L~^T) / 2, and is generally dense (the paper notes the fill-in).
+ * L           n x n symmetric PSD Laplacian (device CSR, FP64 values).
+ * omega       rho distinct int32 node indices (device); rows and columns of
+ *             the output follow this order.
+ * rho         1 <= rho <= min(n, 65536).
+ * tol > 0, max_iter >= 0: per-column CG stop and cap.
+ * Lred_out    rho x rho row-major FP64 (device).
+ * info        iters = largest CG iteration count, rel_residual = largest
+ *             final per-column recursive residual.
+ * Returns OK, EINVAL, ENOCONV (cap reached; the output is written), ENOTSPD,
+ * ENAN, EHIP, ENOMEM.
+ */
+cpca_status cpca_kron_reduce(cpca_handle h, const cpca_csr* L, const int32_t* omega,
+                             int64_t rho, double tol, int32_t max_iter,
+                             double* Lred_out, cpca_info* info);
+
+/*
  * Alternate decoder (Section V.B, eq. alternatedecoder) solved by conjugate
  * gradient on its normal equations
  *

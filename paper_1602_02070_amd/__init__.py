@@ -9,6 +9,6 @@ from .api import (CpcaError, Decode, DecodeProblem, Graph, apply_operator,  # no
                   decode, decode_backward, frpcag, get_profile, handle, mode_for,
                   profiling, set_apply_config, Instance, solve_batched, approx_decode,
                   cluster_decode, laplacian_lmax, knn_graph,
-                  approx_decode_one_side)
+                  approx_decode_one_side, kron_reduce)
 
 __version__ = "0.1.0"

@@ -18,7 +18,7 @@ EXPORTS = ["cpca_version", "cpca_last_error", "cpca_create", "cpca_destroy",
            "cpca_set_profiling", "cpca_get_profile", "cpca_set_apply_config",
            "cpca_solve_batched", "cpca_approx_decode", "cpca_cluster_decode",
            "cpca_laplacian_lmax", "cpca_apply_noalloc", "cpca_knn_graph",
-           "cpca_approx_decode2", "cpca_approx_decode3"]
+           "cpca_approx_decode2", "cpca_approx_decode3", "cpca_kron_reduce"]
 
 
 class CpcaCsr(ctypes.Structure):
@@ -83,6 +83,7 @@ def _declare(lib):
         "cpca_frpcag": (st, [P, c_int32, P, c_int64, c_int64, csr, csr, c_double, c_double,
                              c_double, c_double, c_int32, c_double, P, info]),
         "cpca_laplacian_lmax": (st, [P, csr, c_double, c_int32, POINTER(c_double), info]),
+        "cpca_kron_reduce": (st, [P, csr, P, c_int64, c_double, c_int32, P, info]),
         "cpca_knn_graph": (st, [P, P, c_int64, c_int64, c_int32, c_int32, P, P, P, c_int64,
                                 POINTER(c_int64), POINTER(c_double), P, info]),
         "cpca_decode": (st, [P, c_int32, P, c_int64, c_int64, P, P, c_int64, c_int64, csr, csr,

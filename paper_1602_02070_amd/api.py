@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import CpcaApproxInfo, CpcaClusterInfo, CpcaCsr, CpcaInfo, CpcaInstance, CpcaTask
 
 __all__ = ["CpcaError", "Graph", "handle", "frpcag", "laplacian_lmax", "knn_graph", "decode",
-           "decode_backward", "approx_decode_one_side",
+           "decode_backward", "approx_decode_one_side", "kron_reduce",
            "apply_operator", "Decode", "DecodeProblem", "profiling", "get_profile",
            "mode_for", "set_apply_config", "Instance", "solve_batched"]
 
@@ -220,6 +220,20 @@ def knn_graph(points: torch.Tensor, K: int = 10, kind: str = "normalized",
     if want_knn:
         out["knn"] = knn
     return G, out
+
+
+def kron_reduce(L: Graph, omega: torch.Tensor, tol: float = 1e-12, max_iter: int = 20000):
+    """Kron reduction of L onto the nodes omega (Section IV-A): the dense
+    rho x rho FP64 Schur complement, rows and columns in the order of omega.
+    Returns (L~, info)."""
+    om = _index(omega, "omega")
+    rho = om.numel()
+    out = torch.empty((rho, rho), dtype=torch.float64, device=om.device)
+    info = CpcaInfo()
+    st = _lib.load().cpca_kron_reduce(handle(om.device), ctypes.byref(L.desc), _ptr(om), rho,
+                                      float(tol), int(max_iter), _ptr(out), ctypes.byref(info))
+    _check(st, "cpca_kron_reduce")
+    return out, info.as_dict()
 
 
 def decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tensor, p: int, n: int,

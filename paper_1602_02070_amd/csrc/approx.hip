@@ -731,6 +731,42 @@ k_proj_right_sum(const double* __restrict__ Gp, int nwstrips, int p, int KP, dou
   G[e] = s;
 }
 
+// ------------------------------------------- Kron reduction (Section IV-A)
+// The Schur complement onto the sampled nodes equals the sampled rows of
+// L S, where S is the graph upsampling of the unit vectors: S = I on Omega
+// and S = -L(bar, bar)^-1 L(bar, Omega) elsewhere. Columns are processed KP
+// at a time: R holds unit vectors col0 .. col0 + kb - 1.
+__global__ void __launch_bounds__(kThreads)
+k_kron_rhs(double* __restrict__ R, int rho, int KP, int col0, int kb) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rho * KP) return;
+  const int a = (int)(e / KP), c = (int)(e % KP);
+  R[e] = (c < kb && a == col0 + c) ? 1.0 : 0.0;
+}
+
+// out[a][col0 + c] = (L S)[omega[a], c] for a < rho, c < kb (rho x rho row-major).
+__global__ void __launch_bounds__(kThreads)
+k_kron_rows(UpSide s, const int32_t* __restrict__ omega, int rho, int KP, int col0, int kb,
+            double* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rho * KP) return;
+  const int a = (int)(e / KP), c = (int)(e % KP);
+  if (c >= kb) return;
+  out[(size_t)a * rho + col0 + c] = lap_row(s, s.S, omega[a], c, KP);
+}
+
+// out = (out + out^T) / 2 (the two triangles agree to the CG tolerance).
+__global__ void __launch_bounds__(kThreads)
+k_kron_sym(double* __restrict__ out, int rho) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rho * rho) return;
+  const int i = (int)(e / rho), j = (int)(e % rho);
+  if (j <= i) return;
+  const double v = 0.5 * (out[(size_t)i * rho + j] + out[(size_t)j * rho + i]);
+  out[(size_t)i * rho + j] = v;
+  out[(size_t)j * rho + i] = v;
+}
+
 // ---------------------------------------------- clustering (Algorithm 3)
 // Points (rho_c x rho_r, FP64): point j is column j of X~ (rho_r x rho_c).
 template <typename TI>
@@ -1607,4 +1643,106 @@ extern "C" cpca_status cpca_approx_decode3(cpca_handle h, cpca_mode mode, const 
                            n, nullptr, Lc, 0.0, sigma_ratio, k_max, tol, max_iter,
                            static_cast<float*>(X_out), sigma_out, info, 2,
                            static_cast<const float*>(Y));
+}
+
+// Kron reduction of a Laplacian onto the sampled nodes (Section IV-A).
+namespace {
+cpca_status run_kron(cpca_handle h, const cpca_csr* L, const int32_t* omega, int64_t rho,
+                     double tol, int32_t max_iter, double* out, cpca_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HostCsr hL;
+  STCHK(fetch_csr("L", L, hL));
+  std::vector<int32_t> w;
+  STCHK(fetch_indices("omega", omega, rho, L->n, w));
+  const SideHost sh = side_tables(hL, w);
+  const int c = (int)L->n;
+  const int KP = std::min(kApproxKMax, pow2_at_least((int)rho));
+  int *inv = nullptr;
+  double *dinv = nullptr, *R = nullptr;
+  UpSide A;
+  A.c = c;
+  A.nb = (int)std::max<int64_t>(1, std::min<int64_t>(kUpMaxBlocks, ((int64_t)c * KP + kThreads - 1) / kThreads));
+  auto layout = [&](Arena& a) {
+    inv = a.take<int>((size_t)c);
+    dinv = a.take<double>((size_t)c);
+    R = a.take<double>((size_t)rho * KP);
+    const size_t N = (size_t)c * KP;
+    A.x = a.take<double>(N);
+    A.r = a.take<double>(N);
+    A.z = a.take<double>(N);
+    A.p = a.take<double>(N);
+    A.q = a.take<double>(N);
+    A.S = a.take<double>(N);
+    A.pa = a.take<double>((size_t)A.nb * KP);
+    A.pb = a.take<double>((size_t)A.nb * 2 * KP);
+    A.scal = a.take<double>(6 * kApproxKMax);
+    A.state = a.take<int>(2 * kApproxKMax);
+  };
+  {
+    Arena a;
+    layout(a);
+    STCHK(ensure_ws(h, a.off));
+  }
+  Arena ar;
+  ar.base = h->ws;
+  layout(ar);
+  hipStream_t st = h->stream;
+  HIPCHK(hipMemcpyAsync(inv, sh.inv.data(), sizeof(int) * c, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dinv, sh.dinv.data(), sizeof(double) * c, hipMemcpyHostToDevice, st));
+  A.rp = L->rowptr;
+  A.ci = L->colind;
+  A.v = L->vals;
+  A.inv = inv;
+  A.dinv = dinv;
+  A.R = R;
+  int it_max = 0, worst = 0;
+  double rel_max = 0.0;
+  std::vector<double> hscal(6 * kApproxKMax);
+  for (int col0 = 0; col0 < (int)rho; col0 += KP) {
+    const int kb = std::min(KP, (int)rho - col0);
+    k_kron_rhs<<<(int)(((size_t)rho * KP + kThreads - 1) / kThreads), kThreads, 0, st>>>(R, (int)rho, KP, col0, kb);
+    LAUNCHCHK();
+    std::vector<int> hs;
+    STCHK(upsample_solve(h, A, A, 1, KP, kb, tol, max_iter, hs));
+    k_kron_rows<<<(int)(((size_t)rho * KP + kThreads - 1) / kThreads), kThreads, 0, st>>>(
+        A, omega, (int)rho, KP, col0, kb, out);
+    LAUNCHCHK();
+    STCHK(read_states(h, A, A, 1, hs));
+    HIPCHK(hipMemcpyAsync(hscal.data(), A.scal, sizeof(double) * 6 * kApproxKMax,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = 0; j < kb; ++j) {
+      const int d = hs[(size_t)j];
+      it_max = std::max(it_max, hs[(size_t)kApproxKMax + j]);
+      const double bb = hscal[(size_t)2 * kApproxKMax + j], rr = hscal[(size_t)kApproxKMax + j];
+      if (bb > 0.0) rel_max = std::max(rel_max, std::sqrt(rr / bb));
+      if (d != 1) worst = std::max(worst, d == 0 ? 1 : d);
+    }
+  }
+  k_kron_sym<<<(int)(((size_t)rho * rho + kThreads - 1) / kThreads), kThreads, 0, st>>>(out, (int)rho);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));
+  cpca_status s = CPCA_OK;
+  if (worst == 3) s = fail(CPCA_ENAN, "kron_reduce: NaN/Inf in the CG");
+  else if (worst == 2) s = fail(CPCA_ENOTSPD, "kron_reduce: CG breakdown (p^T A p <= 0)");
+  else if (worst == 1) s = fail(CPCA_ENOCONV, "kron_reduce: CG reached max_iter");
+  fill_info(info, s, it_max, 0, rel_max, 0.0, t0);
+  return s;
+}
+}  // namespace
+
+extern "C" cpca_status cpca_kron_reduce(cpca_handle h, const cpca_csr* L, const int32_t* omega,
+                                        int64_t rho, double tol, int32_t max_iter,
+                                        double* Lred_out, cpca_info* info) {
+  clear_error();
+  if (!L || !omega || !Lred_out) return fail(CPCA_EINVAL, "kron_reduce: null argument");
+  if (L->n < 1 || L->n > INT32_MAX) return fail(CPCA_EINVAL, "kron_reduce: order out of range");
+  STCHK(check_csr_shape("L", L, L->n));
+  if (rho < 1 || rho > L->n) return fail(CPCA_EINVAL, "kron_reduce: rho must be in [1, n]");
+  if (rho > 65536) return fail(CPCA_EINVAL, "kron_reduce: rho above 65536 (dense output)");
+  if (!std::isfinite(tol) || !(tol > 0)) return fail(CPCA_EINVAL, "kron_reduce: tol must be > 0");
+  if (max_iter < 0) return fail(CPCA_EINVAL, "kron_reduce: max_iter < 0");
+  if (!h) return fail(CPCA_EINVAL, "null handle");
+  return run_kron(h, L, omega, rho, tol, max_iter, Lred_out, info);
 }

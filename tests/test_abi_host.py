@@ -227,3 +227,18 @@ def test_one_side_decoders_reject_bad_arguments_before_device_work(lib):
             assert call(**kw) == _lib.EINVAL, kw
             assert word in _lib.last_error(), (kw, _lib.last_error())
         assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
+
+
+def test_kron_reduce_rejects_bad_arguments_before_device_work(lib):
+    info = _lib.CpcaInfo()
+    dummy = ctypes.c_void_p(16)
+    L, keep = _csr(30)
+
+    def call(rho=5, tol=1e-12, it=100, om=dummy, out=dummy):
+        return lib.cpca_kron_reduce(None, ctypes.byref(L), om, rho, tol, it, out, ctypes.byref(info))
+
+    for kw, word in [(dict(rho=0), "rho"), (dict(rho=31), "rho"), (dict(tol=0.0), "tol"),
+                     (dict(it=-1), "max_iter"), (dict(om=None), "null"), (dict(out=None), "null")]:
+        assert call(**kw) == _lib.EINVAL, kw
+        assert word in _lib.last_error(), (kw, _lib.last_error())
+    assert call() == _lib.EINVAL and "null handle" in _lib.last_error()
