@@ -239,7 +239,7 @@ def kron_reduce(L: Graph, omega: torch.Tensor, tol: float = 1e-12, max_iter: int
 def decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tensor, p: int, n: int,
            Lr: Graph, Lc: Graph, gamma_r: float, gamma_c: float, tol: float = 1e-10,
            max_iter: int = 20000, mode: str | None = None, X0: torch.Tensor | None = None,
-           out: torch.Tensor | None = None):
+           out: torch.Tensor | None = None, h=None):
     """Alternate decoder by CG (Section V.B). Returns (X, info)."""
     mode = mode_for(Xtil.dtype, mode)
     dt = _dtype_of(mode)
@@ -254,7 +254,7 @@ def decode(Xtil: torch.Tensor, omega_r: torch.Tensor, omega_c: torch.Tensor, p: 
     else:
         out = _need(out, "out", dt, (p, n))
     info = CpcaInfo()
-    st = _lib.load().cpca_decode(handle(Xt.device), _lib.MODES[mode], _ptr(Xt), Xt.shape[0],
+    st = _lib.load().cpca_decode(h or handle(Xt.device), _lib.MODES[mode], _ptr(Xt), Xt.shape[0],
                                  Xt.shape[1], _ptr(om_r), _ptr(om_c), int(p), int(n),
                                  ctypes.byref(Lr.desc), ctypes.byref(Lc.desc), float(gamma_r),
                                  float(gamma_c), float(tol), int(max_iter), _ptr(X0c), _ptr(out),

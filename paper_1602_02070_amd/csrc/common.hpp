@@ -48,6 +48,10 @@ struct cpca_handle_s {
   size_t ev_used = 0;
   int64_t prof_n[FAM_COUNT] = {};
   double prof_ms[FAM_COUNT] = {};
+  // staged operator image of the last decode on this handle, kept in its own
+  // device buffer and reused while the operator's content key is unchanged
+  struct DecodeCache* dcache = nullptr;
+  bool dcache_on = true;       // CPCA_IMAGE_CACHE=0 turns the reuse off
 };
 
 namespace {

@@ -52,6 +52,13 @@ char* scratch_device(int device) {
 
 namespace {
 
+inline uint64_t mix_host(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
 // ---------------------------------------------------------------- CG core
 template <typename T>
 struct Operator {
@@ -125,6 +132,88 @@ cpca_status prepare(cpca_handle h, const cpca_csr* Lr, const cpca_csr* Lc, const
   return CPCA_OK;
 }
 
+// ------------------------------------------------- operator-image cache
+// The decoder's operator image (L_r and L_c in the kernel layouts of both
+// element types, masks, row-panel tables) costs host work on every call:
+// copying the CSR arrays and index sets back, validating them, building the
+// panel tables and uploading the image. The handle keeps the last image in a
+// device buffer of its own, keyed by a 64-bit content hash of every input
+// array computed on the device, and by the sizes, mode and launch settings;
+// a call whose key matches skips that work (the arrays were validated when
+// the image was built from the same content).
+
+// Sum over the words of mix(word, position, salt); partials per workgroup.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_hash_words(const uint32_t* __restrict__ w, size_t nw, uint64_t salt,
+             unsigned long long* __restrict__ out) {
+  uint64_t s = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+       i += (size_t)gridDim.x * blockDim.x)
+    s += mix64((uint64_t)w[i] ^ mix64((uint64_t)i ^ salt));
+  // the sum is order-independent modulo 2^64: atomics give the same total
+  atomicAdd(out, (unsigned long long)s);
+}
+
+}  // namespace
+
+// (global scope: the handle holds a pointer to it)
+struct DecodeCache {
+  uint64_t key = 0;
+  bool valid = false;
+  char* dev = nullptr;
+  size_t cap = 0, bytes = 0;
+  GraphImage<double> gi64{};
+  GraphImage<float> gi32{};
+  ApplyCfg cfg64{}, cfg32{};
+  int64_t nnz = 0;
+};
+
+namespace {
+
+void dcache_free(cpca_handle h) {
+  if (!h->dcache) return;
+  if (h->dcache->dev) (void)hipFree(h->dcache->dev);
+  delete h->dcache;
+  h->dcache = nullptr;
+}
+
+// Content key of a decode operator: the CSR arrays and index sets (device)
+// plus the sizes, the mode and the handle's launch settings.
+cpca_status decode_key(cpca_handle h, cpca_mode mode, const cpca_csr* Lr, const cpca_csr* Lc,
+                       const int32_t* om_r, int64_t rho_r, const int32_t* om_c, int64_t rho_c,
+                       int64_t p, int64_t n, uint64_t* key) {
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(results_ptr(h) + 20);
+  k_fill<int><<<1, kThreads, 0, h->stream>>>(reinterpret_cast<int*>(acc), 0, 2);
+  LAUNCHCHK();
+  struct Arr { const void* p; size_t words; };
+  const Arr arrs[] = {
+      {Lr->rowptr, (size_t)Lr->n + 1}, {Lr->colind, (size_t)Lr->nnz}, {Lr->vals, 2 * (size_t)Lr->nnz},
+      {Lc->rowptr, (size_t)Lc->n + 1}, {Lc->colind, (size_t)Lc->nnz}, {Lc->vals, 2 * (size_t)Lc->nnz},
+      {om_r, (size_t)rho_r}, {om_c, (size_t)rho_c}};
+  uint64_t salt = 0x51ed270b2f1f3a5dull;
+  for (const Arr& a : arrs) {
+    salt = mix_host(salt + 1);
+    if (a.words == 0) continue;
+    const int g = (int)std::min<size_t>(1024, (a.words + kThreads - 1) / kThreads);
+    k_hash_words<<<g, kThreads, 0, h->stream>>>(static_cast<const uint32_t*>(a.p), a.words, salt, acc);
+    LAUNCHCHK();
+  }
+  STCHK(read_fixed(h));
+  uint64_t k = *reinterpret_cast<const uint64_t*>(host_results(h) + 20);
+  const int64_t params[] = {(int64_t)mode, p, n, rho_r, rho_c, Lr->nnz, Lc->nnz, h->force_R,
+                            h->force_lds, h->force_band, h->force_kernel};
+  for (int64_t v : params) k = mix_host(k ^ mix_host((uint64_t)v));
+  *key = k;
+  return CPCA_OK;
+}
+
 // Right-hand side: the scattered samples (decode) or a dense p x n matrix
 // (backward), in the mode's element type.
 struct Rhs {
@@ -150,11 +239,11 @@ struct SolveOut {
 // With autotuning enabled (rows_per_block = -1), times the launch shapes of
 // the CG product on the current direction p and returns the fastest.
 template <typename T>
-cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, const Prepared& P, const T* pv, T* q,
+cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, int64_t nnz, const T* pv, T* q,
                       double* part, ApplyCfg* out) {
   *out = op.cfg;
   if (h->force_R != -1) return CPCA_OK;
-  const std::string key = tune_key("cg", sizeof(T), op.p, op.n, P.Lr.nnz + P.Lc.nnz);
+  const std::string key = tune_key("cg", sizeof(T), op.p, op.n, nnz);
   return autotune(h, key, op.n, sizeof(T), op.cfg,
                   [&](const ApplyCfg& c) -> cpca_status {
                     EpiApply<T> epi{q, op.gr, op.gc, part};
@@ -166,35 +255,83 @@ cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, const Prepared& P, c
 // Solves A(X) = B for the given mode. On return (OK or ENOCONV) the FP64
 // solution sits at so.x64 and, if `out` is given, the result is written to
 // it in the mode's element type.
-cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64_t p, int64_t n,
+// Builds the decoder's operator image from the validated host copies and
+// uploads it into the handle's image buffer (synchronous upload).
+cpca_status stage_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64_t p, int64_t n,
+                         uint64_t key) {
+  if (!h->dcache) h->dcache = new (std::nothrow) DecodeCache();
+  if (!h->dcache) return fail(CPCA_ENOMEM, "host allocation failed");
+  DecodeCache& dc = *h->dcache;
+  dc.valid = false;
+  const bool f32 = mode != CPCA_FP64;
+  const int band = choose_band(P.Lc);
+  dc.cfg64 = choose_cfg(h, p, n, sizeof(double), band, true);
+  dc.cfg32 = choose_cfg(h, p, n, sizeof(float), band, true);
+  Staging stg;
+  // panel tables when the panel kernel is chosen or may be tried by the tuner
+  const bool tables = h->force_R == -1;
+  dc.gi64 = stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(dc.cfg64), dc.cfg64.bw,
+                                dc.cfg64.panel || tables);
+  dc.gi32 = GraphImage<float>{};
+  if (f32)
+    dc.gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(dc.cfg32),
+                                 dc.cfg32.bw, dc.cfg32.panel || tables);
+  set_panels(dc.cfg64, dc.gi64.npan);
+  set_panels(dc.cfg32, dc.gi32.npan);
+  dc.nnz = P.Lr.nnz + P.Lc.nnz;
+  dc.bytes = stg.buf.size();
+  if (dc.bytes > dc.cap) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (dc.dev) HIPCHK(hipFree(dc.dev));
+    dc.dev = nullptr;
+    dc.cap = 0;
+    const size_t cap = align_up(dc.bytes + dc.bytes / 8, 1 << 20);
+    HIPCHK(hipMalloc(&dc.dev, cap));
+    dc.cap = cap;
+  }
+  // the host staging buffer is released on return: wait for the copy
+  HIPCHK(hipMemcpyAsync(dc.dev, stg.buf.data(), dc.bytes, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  dc.key = key;
+  dc.valid = true;
+  return CPCA_OK;
+}
+
+// The decoder's operator for these arguments: the cached image when the
+// content key matches, else host preparation (copies, checks) and staging.
+cpca_status decode_operator(cpca_handle h, cpca_mode mode, const cpca_csr* Lr, const cpca_csr* Lc,
+                            const int32_t* om_r, int64_t rho_r, const int32_t* om_c,
+                            int64_t rho_c, int64_t p, int64_t n) {
+  HIPCHK(hipStreamSynchronize(h->stream));  // inputs may still be in flight
+  uint64_t key = 0;
+  STCHK(decode_key(h, mode, Lr, Lc, om_r, rho_r, om_c, rho_c, p, n, &key));
+  if (h->dcache_on && h->dcache && h->dcache->valid && h->dcache->key == key) {
+    if (h->debug) std::fprintf(stderr, "[cpca] operator image reused (key %016llx)\n", (unsigned long long)key);
+    return CPCA_OK;
+  }
+  if (h->debug) std::fprintf(stderr, "[cpca] operator image staged (key %016llx)\n", (unsigned long long)key);
+  Prepared P;
+  STCHK(prepare(h, Lr, Lc, om_r, rho_r, om_c, rho_c, p, n, P));
+  return stage_decode(h, mode, P, p, n, key);
+}
+
+cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
                          double gr, double gc, double tol, int max_iter, const Rhs& rhs,
                          const void* X0, void* out, bool want_spare, SolveOut& so) {
   const size_t N = (size_t)p * n;
   const bool f32 = mode != CPCA_FP64;
-  const int band = choose_band(P.Lc);
-  ApplyCfg cfg64 = choose_cfg(h, p, n, sizeof(double), band, true);
-  ApplyCfg cfg32 = choose_cfg(h, p, n, sizeof(float), band, true);
-  Staging stg;
-  // panel tables when the panel kernel is chosen or may be tried by the tuner
-  const bool tables = h->force_R == -1;
-  const GraphImage<double> gi64 = stage_graph<double>(stg, P.Lr, P.Lc, P.mr, P.mc,
-                                                      slice_height(cfg64), cfg64.bw,
-                                                      cfg64.panel || tables);
-  GraphImage<float> gi32{};
-  if (f32)
-    gi32 = stage_graph<float>(stg, P.Lr, P.Lc, P.mr, P.mc, slice_height(cfg32), cfg32.bw,
-                              cfg32.panel || tables);
-  set_panels(cfg64, gi64.npan);
-  set_panels(cfg32, gi32.npan);
+  const DecodeCache& dc = *h->dcache;
+  const ApplyCfg cfg64 = dc.cfg64, cfg32 = dc.cfg32;
+  const GraphImage<double>& gi64 = dc.gi64;
+  const GraphImage<float>& gi32 = dc.gi32;
   const int maxgrid = std::max({max_apply_grid((int)p, (int)n), 2048,
                                 panel_grid(gi64.npan, (int)n, 2), panel_grid(gi32.npan, (int)n, 4)});
 
-  char* img = nullptr;
+  const char* img = dc.dev;
   double *pa = nullptr, *pb = nullptr, *B64 = nullptr, *X64 = nullptr, *r64 = nullptr,
          *p64 = nullptr, *q64 = nullptr, *spare = nullptr;
   float *B32 = nullptr, *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   auto layout = [&](Arena& a) {
-    img = a.take<char>(stg.buf.size());
     pa = a.take<double>((size_t)maxgrid * 2);
     pb = a.take<double>((size_t)maxgrid * 2);
     B64 = a.take<double>(N);
@@ -220,7 +357,6 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
   Arena a;
   a.base = h->ws;
   layout(a);
-  HIPCHK(hipMemcpyAsync(img, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, h->stream));
   const DevGraph<double> g64 = bind_graph<double>(gi64, img);
   DevGraph<float> g32{};
   if (f32) g32 = bind_graph<float>(gi32, img);
@@ -292,7 +428,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
       k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
     LAUNCHCHK();
-    STCHK(tuned_cfg<double>(h, op, P, p64, q64, pa, &op.cfg));
+    STCHK(tuned_cfg<double>(h, op, dc.nnz, p64, q64, pa, &op.cfg));
     STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, part));
     so.iters = host_cg(h).iter;
     done = host_cg(h).done ? host_cg(h).done : (host_cg(h).conv_it ? 1 : 0);
@@ -312,7 +448,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
       k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
     LAUNCHCHK();
-    STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
+    STCHK(tuned_cfg<float>(h, op, dc.nnz, p32, q32, pa, &op.cfg));
     STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
     so.iters = host_cg(h).iter;
     done = host_cg(h).done ? host_cg(h).done : (host_cg(h).conv_it ? 1 : 0);
@@ -405,7 +541,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
         k_cg_set_thr<<<1, 1, 0, h->stream>>>(sc, floor2);
         LAUNCHCHK();
       }
-      if (seg == 0) STCHK(tuned_cfg<float>(h, op, P, p32, q32, pa, &op.cfg));
+      if (seg == 0) STCHK(tuned_cfg<float>(h, op, dc.nnz, p32, q32, pa, &op.cfg));
       STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part));
       const CgScal ci = host_cg(h);
       if (h->debug)
@@ -612,6 +748,7 @@ extern "C" cpca_status cpca_create(cpca_handle* out, void* stream) {
     h->force_kernel = k == "rows" ? 0 : k == "strip" ? 1 : k == "panel" ? 2 : k == "panel_lo" ? 3 : -1;
   }
   if (const char* s = std::getenv("CPCA_DEBUG")) h->debug = std::atoi(s) != 0;
+  if (const char* s = std::getenv("CPCA_IMAGE_CACHE")) h->dcache_on = std::atoi(s) != 0;
   *out = h;
   return CPCA_OK;
 }
@@ -622,6 +759,7 @@ extern "C" cpca_status cpca_destroy(cpca_handle h) {
   (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
+  dcache_free(h);
   if (h->fixed) (void)hipFree(h->fixed);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
@@ -715,8 +853,7 @@ extern "C" cpca_status cpca_decode(cpca_handle h, cpca_mode mode, const void* Xt
                           tol, max_iter));
   if (!Xtil || !X_out) return fail(CPCA_EINVAL, "decode: null data pointer");
   if (!h) return fail(CPCA_EINVAL, "null handle");
-  Prepared P;
-  STCHK(prepare(h, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n, P));
+  STCHK(decode_operator(h, mode, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n));
   Rhs rhs;
   rhs.Xtil = Xtil;
   rhs.om_r = omega_r;
@@ -725,7 +862,7 @@ extern "C" cpca_status cpca_decode(cpca_handle h, cpca_mode mode, const void* Xt
   rhs.rho_c = (int)rho_c;
   SolveOut so;
   const cpca_status st =
-      solve_decode(h, mode, P, p, n, gamma_r, gamma_c, tol, max_iter, rhs, X0, X_out, false, so);
+      solve_decode(h, mode, p, n, gamma_r, gamma_c, tol, max_iter, rhs, X0, X_out, false, so);
   fill_info(info, st, so.iters, so.outer, so.rel, 0.0, t0);
   return st;
 }
@@ -744,14 +881,13 @@ extern "C" cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode, const
   if (!G || !X || !dXtil_out || !dgamma_r || !dgamma_c)
     return fail(CPCA_EINVAL, "decode_backward: null pointer");
   if (!h) return fail(CPCA_EINVAL, "null handle");
-  Prepared P;
-  STCHK(prepare(h, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n, P));
+  STCHK(decode_operator(h, mode, Lr, Lc, omega_r, rho_r, omega_c, rho_c, p, n));
   Rhs rhs;
   rhs.dense = G;
   SolveOut so;
   const bool f32 = mode != CPCA_FP64;
   cpca_status st =
-      solve_decode(h, mode, P, p, n, gamma_r, gamma_c, tol, max_iter, rhs, nullptr, nullptr, true, so);
+      solve_decode(h, mode, p, n, gamma_r, gamma_c, tol, max_iter, rhs, nullptr, nullptr, true, so);
   if (st != CPCA_OK && st != CPCA_ENOCONV) {
     fill_info(info, st, so.iters, so.outer, so.rel, 0.0, t0);
     return st;

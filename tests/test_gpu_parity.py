@@ -661,3 +661,84 @@ def test_nan_input_reports_enan(cfg1, mode):
     X, info = cp.decode(torch.from_numpy(P.Ytil).to(dt).cuda(), d["om_r"], d["om_c"], P.p, P.n,
                         d["Lr"], d["Lc"], 1.0, 1.0, tol=1e-10, mode=mode)
     assert info["status"] == 0
+
+
+# ------------------------------------------------------------------ operator-image cache
+
+def _debug_handle():
+    import ctypes
+    import os
+    lib = _lib.load()
+    hp = ctypes.c_void_p()
+    old = os.environ.get("CPCA_DEBUG")
+    os.environ["CPCA_DEBUG"] = "1"
+    try:
+        st = lib.cpca_create(ctypes.byref(hp),
+                             ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream)))
+    finally:
+        if old is None:
+            del os.environ["CPCA_DEBUG"]
+        else:
+            os.environ["CPCA_DEBUG"] = old
+    assert st == 0
+    return hp.value
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+def test_operator_image_cache_reuse_and_invalidation(mode, capfd):
+    # a second decode on the same operator reuses the staged image and gives
+    # the same bits; changing one value of L_r in place (same pointers), or
+    # one sampled index, is seen by the content key and restages the image
+    P = synth.small_problem(23, p_shape=(16, 20), n=300, rank=3, frac=0.3, col_kind="band")
+    _announce(f"image cache {mode}")
+    d = dev_problem(P)
+    dt = torch.float64 if mode == "fp64" else torch.float32
+    Xt = torch.from_numpy(P.Ytil).to(dt).cuda()
+    h = _debug_handle()
+    tol = 1e-12 if mode == "fp64" else 1e-10
+    bar = 1e-9 if mode == "fp64" else 1e-5
+    Xr = P.Ytil if mode == "fp64" else P.Ytil.astype(np.float32).astype(np.float64)
+    try:
+        capfd.readouterr()
+        X1, _ = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0, tol=tol,
+                          mode=mode, h=h)
+        X2, _ = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0, tol=tol,
+                          mode=mode, h=h)
+        torch.cuda.synchronize()
+        log = capfd.readouterr().err
+        assert log.count("operator image staged") == 1 and log.count("operator image reused") == 1
+        assert torch.equal(X1, X2)
+        # values of L_r changed in place (same pointers): a PSD rank-one
+        # increment on one edge, 0.05 (e_i + e_j)(e_i + e_j)^T
+        Lr2 = P.Lr.copy().tolil()
+        i, j = 5, int(P.Lr[5].indices[-1])
+        assert i != j
+        for a, b in ((i, i), (j, j), (i, j), (j, i)):
+            Lr2[a, b] = P.Lr[a, b] + 0.05
+        Lr2 = Lr2.tocsr()
+        Lr2.sort_indices()
+        assert np.array_equal(Lr2.indices, P.Lr.indices)
+        d["Lr"].vals.copy_(torch.from_numpy(Lr2.data))
+        X3, i3 = cp.decode(Xt, d["om_r"], d["om_c"], P.p, P.n, d["Lr"], d["Lc"], 1.0, 1.0,
+                           tol=tol, mode=mode, h=h)
+        torch.cuda.synchronize()
+        log = capfd.readouterr().err
+        assert "operator image staged" in log and "reused" not in log
+        ref3 = OD.decode(Xr, P.p, P.n, P.omega_r, P.omega_c, Lr2, P.Lc, 1.0, 1.0)
+        assert i3["status"] == 0 and rel(host(X3), ref3) <= bar
+        # one sampled column index changed: restaged, and the new operator used
+        om_c2 = P.omega_c.copy()
+        free = np.setdiff1d(np.arange(P.n), om_c2)
+        om_c2[-1] = free[-1]
+        order = np.argsort(om_c2)
+        om_c2 = om_c2[order]
+        Xt2 = Xt[:, torch.from_numpy(order).cuda()].contiguous()
+        X4, i4 = cp.decode(Xt2, d["om_r"], torch.from_numpy(om_c2).cuda(), P.p, P.n, d["Lr"],
+                           d["Lc"], 1.0, 1.0, tol=tol, mode=mode, h=h)
+        torch.cuda.synchronize()
+        log = capfd.readouterr().err
+        assert "operator image staged" in log
+        ref4 = OD.decode(Xr[:, order], P.p, P.n, P.omega_r, om_c2, Lr2, P.Lc, 1.0, 1.0)
+        assert i4["status"] == 0 and rel(host(X4), ref4) <= bar
+    finally:
+        _lib.load().cpca_destroy(h)
