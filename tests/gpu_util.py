@@ -24,3 +24,15 @@ def rel(a, b):
 
 def host(t):
     return t.detach().double().cpu().numpy()
+
+
+_VIDEO = {}
+
+
+def video_problem():
+    """The video-shaped workload (20480 x 4096, full data kept), generated once
+    per test session and shared by the modules that need it."""
+    if "P" not in _VIDEO:
+        import synth
+        _VIDEO["P"] = synth.cfg3_video(0, keep_full=True)
+    return _VIDEO["P"]

@@ -15,7 +15,7 @@ import torch
 import paper_1602_02070_amd as cp
 import synth
 from oracle import approx as OA
-from tests.gpu_util import dev_problem, host, rel
+from tests.gpu_util import dev_problem, host, rel, video_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -145,7 +145,7 @@ def test_approx_decode_recovers_block_constant_matrix_exactly():
 def test_approx_decode_video_shape_sampled_entries():
     # the full 20480 x 4096 video-shaped workload (FP32 output) against the
     # oracle's U, V and scale at 20000 random entries
-    P = synth.cfg3_video(0)
+    P = video_problem()
     print(f"[case] approx video {P.p}x{P.n}, Xtil {P.Ytil.shape}", flush=True)
     d = dev_problem(P, torch.float32)
     Xt_in = _input(P, "fp32")

@@ -12,7 +12,7 @@ import torch
 import paper_1602_02070_amd as cp
 import synth
 from oracle import approx as OA
-from tests.gpu_util import host, rel
+from tests.gpu_util import host, rel, video_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -84,7 +84,7 @@ def test_one_side_decoders_full_sampling_truncate_Y():
 
 @pytest.fixture(scope="module")
 def video_full():
-    return synth.cfg3_video(0, keep_full=True)
+    return video_problem()
 
 
 @pytest.mark.parametrize("side", ["rows", "cols"])

@@ -12,6 +12,7 @@ import torch
 
 import paper_1602_02070_amd as cp
 import synth
+from tests.gpu_util import video_problem
 from oracle import kron as OK
 
 pytestmark = pytest.mark.gpu
@@ -63,5 +64,5 @@ def test_kron_video_row_graph_full_size():
     # the 128 x 160 pixel graph of the video-shaped workload reduced onto its
     # 1024 sampled rows (16 column batches), as the compressed row graph
     print("[case] kron video rows", flush=True)
-    P = synth.cfg3_video(0)
+    P = video_problem()
     _check(P.Lr, P.omega_r, bar=1e-8)
