@@ -736,6 +736,9 @@ k_apply_strip(const T* __restrict__ X, int p, int n, CsrDev<T> Lr, SellDev<T> Lc
 // ---------------------------------------------------------------------------
 // (layout constants kPanel*, PanelUnion: panels.hpp)
 
+// Gather entries of a panel row handled under one loop-bound test.
+constexpr int kGatherChunk = 4;
+
 // Lane E of every 16-lane row of the wave, broadcast to the whole row (DPP
 // row_newbcast): a register-only move.
 template <int E>
@@ -988,18 +991,28 @@ __device__ __forceinline__ void panel_body(const T* __restrict__ X, int p, int n
           }
           // lane ls of the row slot holds entry ls of the row's offset and
           // weight tables (one small LDS read per lane); entry e reaches the
-          // 16 lanes of the slot, which form one DPP row, by a row broadcast
+          // 16 lanes of the slot, which form one DPP row, by a row broadcast.
+          // Entries go in chunks of kGatherChunk under one wave-uniform test:
+          // the chunk's LDS reads are all issued before the first is used,
+          // so their latencies overlap (entries past the row's count in the
+          // last chunk are padding: weight 0 on the row's own slot).
           const uint32_t il = sidx[j * KR + ls];
           const T wl = swt[j * KR + ls];
-          static_for<0, KR>([&](auto ec) {
-            constexpr int e = decltype(ec)::value;
-            if (e < cnt) {
-              const uint32_t off = row_bcast<e>(il);
-              const T w = row_bcast_t<e>(wl);
-              T u4[VEC];
-              vld<T, VEC>(reinterpret_cast<const T*>(sub + off), u4);
+          static_for<0, KR / kGatherChunk>([&](auto cc) {
+            constexpr int e0 = decltype(cc)::value * kGatherChunk;
+            if (e0 < cnt) {
+              T w[kGatherChunk];
+              T u4[kGatherChunk][VEC];
+              static_for<0, kGatherChunk>([&](auto ec) {
+                constexpr int e = e0 + decltype(ec)::value;
+                const uint32_t off = row_bcast<e>(il);
+                w[decltype(ec)::value] = row_bcast_t<e>(wl);
+                vld<T, VEC>(reinterpret_cast<const T*>(sub + off), u4[decltype(ec)::value]);
+              });
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) accr[v] += w * u4[v];
+              for (int q = 0; q < kGatherChunk; ++q)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) accr[v] += w[q] * u4[q][v];
             }
           });
 #pragma unroll
