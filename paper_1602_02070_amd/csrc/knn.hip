@@ -140,60 +140,80 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
     const int q = q0 + 16 * wid + (lane >> 4) + 4 * v;
     sqq[v] = q < N ? sq[q] : 0.0;
   }
-  for (int c0 = 0; c0 < N; c0 += kCT) {
-    d4 acc[4];
+  // (candidate tile, coordinate chunk) steps in order; the next step's
+  // coordinates are loaded into registers before the current step's MFMAs,
+  // so their global-memory latency overlaps the matrix work
+  const int r_st = tid >> 2, cc_st = (tid & 3) * 4;
+  double qr[4], cr[4];
+  auto load_chunk = [&](int c0, int k0) {
+    const int qg = q0 + r_st, cg = c0 + r_st;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < d4pad; k0 += kDK) {
-      // stage 64 x 16 coordinates of the queries and of the candidates
-      {
-        const int r = tid >> 2, cc = (tid & 3) * 4;
-        const int qg = q0 + r, cg = c0 + r;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + cc + u;
-          Qs[r * kDKP + cc + u] = (qg < N && k < d) ? Y[(size_t)qg * d + k] : 0.0;
-          Cs[r * kDKP + cc + u] = (cg < N && k < d) ? Y[(size_t)cg * d + k] : 0.0;
-        }
-      }
-      __syncthreads();
-      const int ksteps = min(kDK, d4pad - k0) >> 2;
-      for (int s = 0; s < ksteps; ++s) {
-        // A: row lane % 16, k = lane / 16 of the 16 x 4 block; B likewise
-        const double a = Qs[(16 * wid + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const double b = Cs[(16 * t + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-        }
-      }
-      __syncthreads();
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + cc_st + u;
+      qr[u] = (qg < N && k < d) ? Y[(size_t)qg * d + k] : 0.0;
+      cr[u] = (cg < N && k < d) ? Y[(size_t)cg * d + k] : 0.0;
     }
-    // approximate squared distances into the tile: output row (lane / 16) + 4 v,
-    // column lane % 16 of each 16 x 16 block
+  };
+  d4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int cl = 16 * t + (lane & 15);
-      const int c = c0 + cl;
-      const double sqc = c < N ? sq[c] : 0.0;
+  for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  int c0 = 0, k0 = 0;
+  load_chunk(0, 0);
+  while (c0 < N) {
+    // stage the 64 x 16 coordinates of the queries and of the candidates
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ql = 16 * wid + (lane >> 4) + 4 * v;
-        const int q = q0 + ql;
-        double dv = sqq[v] + sqc - 2.0 * acc[t][v];
-        if (c >= N || c == q) dv = __builtin_inf();
-        Ds[ql * kDTP + cl] = dv;
+    for (int u = 0; u < 4; ++u) {
+      Qs[r_st * kDKP + cc_st + u] = qr[u];
+      Cs[r_st * kDKP + cc_st + u] = cr[u];
+    }
+    __syncthreads();
+    int nk0 = k0 + kDK, nc0 = c0;
+    if (nk0 >= d4pad) {
+      nk0 = 0;
+      nc0 = c0 + kCT;
+    }
+    if (nc0 < N) load_chunk(nc0, nk0);
+    const int ksteps = min(kDK, d4pad - k0) >> 2;
+    for (int s = 0; s < ksteps; ++s) {
+      // A: row lane % 16, k = lane / 16 of the 16 x 4 block; B likewise
+      const double a = Qs[(16 * wid + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double b = Cs[(16 * t + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
-    // selection: this thread's 16 candidates, in increasing index
+    if (nk0 == 0) {
+      // tile complete: approximate squared distances into the tile, output
+      // row (lane / 16) + 4 v, column lane % 16 of each 16 x 16 block
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int cl = 16 * t + (lane & 15);
+        const int c = c0 + cl;
+        const double sqc = c < N ? sq[c] : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ql = 16 * wid + (lane >> 4) + 4 * v;
+          const int q = q0 + ql;
+          double dv = sqq[v] + sqc - 2.0 * acc[t][v];
+          if (c >= N || c == q) dv = __builtin_inf();
+          Ds[ql * kDTP + cl] = dv;
+        }
+        acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+      __syncthreads();
+      // selection: this thread's 16 candidates, in increasing index
 #pragma unroll 4
-    for (int m = 0; m < 16; ++m) {
-      const int cl = 16 * sub + m;
-      const double x = Ds[qs * kDTP + cl];
-      if (x < vd[CAP - 1]) list_insert<CAP>(vd, vi, x, c0 + cl);
+      for (int m = 0; m < 16; ++m) {
+        const int cl = 16 * sub + m;
+        const double x = Ds[qs * kDTP + cl];
+        if (x < vd[CAP - 1]) list_insert<CAP>(vd, vi, x, c0 + cl);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    c0 = nc0;
+    k0 = nk0;
   }
   // merge the four quarter lists of each query (lanes 4 qs .. 4 qs + 3 of
   // the wave) into the first one by (approximate distance, index)
