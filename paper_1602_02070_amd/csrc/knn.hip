@@ -8,8 +8,8 @@
 //
 // Stages, all on the handle's stream:
 //  1. k_sqnorm: ||y_i||^2.
-//  2. k_knn_tiles: every workgroup takes 64 queries and sweeps all points in
-//     tiles of 64. The 64 x 64 Gram tile <y_q, y_c> comes from FP64 MFMA
+//  2. k_knn_tiles: every workgroup takes 128 queries and sweeps all points in
+//     tiles of 64. The 128 x 64 Gram tile <y_q, y_c> comes from FP64 MFMA
 //     (v_mfma_f64_16x16x4f64, the coordinates staged through LDS in chunks of
 //     16), the squared distance is ||y_q||^2 + ||y_c||^2 - 2 <y_q, y_c>, and
 //     four threads per query keep the CAP smallest (distance, index) pairs of
@@ -32,7 +32,8 @@
 
 namespace {
 
-constexpr int kQT = 64;         // queries per workgroup
+constexpr int kQT = 128;        // queries per workgroup (16 per wave)
+constexpr int kKnnThreads = 512;
 constexpr int kCT = 64;         // candidates per tile
 constexpr int kDK = 16;         // coordinates per staged chunk
 constexpr int kDKP = kDK + 1;   // LDS row stride of the staged chunks (doubles)
@@ -111,7 +112,7 @@ __device__ __forceinline__ void lex_insert(double (&vd)[CAP], int (&vi)[CAP], do
 }
 
 template <int CAP>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kKnnThreads)
 k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, int d, int K,
             int* __restrict__ out_idx, double* __restrict__ out_d2) {
   __shared__ double Qs[kQT * kDKP];
@@ -151,7 +152,7 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + cc_st + u;
       qr[u] = (qg < N && k < d) ? Y[(size_t)qg * d + k] : 0.0;
-      cr[u] = (cg < N && k < d) ? Y[(size_t)cg * d + k] : 0.0;
+      cr[u] = (r_st < kCT && cg < N && k < d) ? Y[(size_t)cg * d + k] : 0.0;
     }
   };
   d4 acc[4];
@@ -164,7 +165,7 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       Qs[r_st * kDKP + cc_st + u] = qr[u];
-      Cs[r_st * kDKP + cc_st + u] = cr[u];
+      if (r_st < kCT) Cs[r_st * kDKP + cc_st + u] = cr[u];
     }
     __syncthreads();
     int nk0 = k0 + kDK, nc0 = c0;
@@ -398,7 +399,7 @@ k_knn_values(int N, const int* __restrict__ rowptr, const int* __restrict__ coli
 template <int CAP>
 hipError_t launch_tiles(hipStream_t s, const double* Y, const double* sq, int N, int d, int K,
                         int* idx, double* d2) {
-  k_knn_tiles<CAP><<<(N + kQT - 1) / kQT, kThreads, 0, s>>>(Y, sq, N, d, K, idx, d2);
+  k_knn_tiles<CAP><<<(N + kQT - 1) / kQT, kKnnThreads, 0, s>>>(Y, sq, N, d, K, idx, d2);
   return hipGetLastError();
 }
 
