@@ -10,6 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcpca.so")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 SOURCES = ["engine.hip", "batched.hip", "approx.hip", "knn.hip", "validate.cpp"]
 HIP_FLAGS = [
@@ -51,7 +52,8 @@ def build(verbose: bool = False) -> str:
     for cmd, rc in zip(cmds, codes):
         if rc != 0:
             raise subprocess.CalledProcessError(rc, cmd)
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
+           "-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + ROCM_LIB, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

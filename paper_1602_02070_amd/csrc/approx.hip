@@ -1049,6 +1049,7 @@ cpca_status read_states(cpca_handle h, const UpSide& A, const UpSide& B, int nsi
 // on a side stream; the host reads the done flags between chunks.
 cpca_status upsample_solve(cpca_handle h, const UpSide& A, const UpSide& B, int nsides, int KP,
                            int k, double tol, int max_iter, std::vector<int>& hstate) {
+  TraceRange trace_("upsampling PCG");
   hipStream_t st = h->stream;
   const int gup = A.nb + (nsides > 1 ? B.nb : 0);
   k_up_start<<<gup, kThreads, 0, st>>>(A, B, KP, 0);
@@ -1539,6 +1540,7 @@ extern "C" cpca_status cpca_cluster_decode(cpca_handle h, cpca_mode mode, const 
                                            double tol, int32_t max_iter, int32_t* labels_out,
                                            double* C_out, int32_t* sample_labels_out,
                                            cpca_cluster_info* info) {
+  TraceRange trace_("cpca_cluster_decode");
   clear_error();
   STCHK(check_cluster_args(mode, rho_r, rho_c, omega_c, n, Lc, k, init, kmeans_max_iter, tol,
                            max_iter));
@@ -1560,6 +1562,7 @@ extern "C" cpca_status cpca_approx_decode(cpca_handle h, cpca_mode mode, const v
                                           double sigma_ratio, int32_t k_max, double tol,
                                           int32_t max_iter, void* X_out, double* sigma_out,
                                           cpca_approx_info* info) {
+  TraceRange trace_("cpca_approx_decode");
   clear_error();
   STCHK(check_approx_args(mode, rho_r, rho_c, omega_r, omega_c, p, n, Lr, Lc, delta, sigma_ratio,
                           k_max, tol, max_iter));
@@ -1607,6 +1610,7 @@ extern "C" cpca_status cpca_approx_decode2(cpca_handle h, cpca_mode mode, const 
                                            const void* Y, double sigma_ratio, int32_t k_max,
                                            double tol, int32_t max_iter, void* X_out,
                                            double* sigma_out, cpca_approx_info* info) {
+  TraceRange trace_("cpca_approx_decode2");
   clear_error();
   STCHK(check_one_side_args("approx_decode2", mode, rho_r, rho_c, omega_r, rho_r, p, p, n, Lr, Y,
                             sigma_ratio, k_max, tol, max_iter));
@@ -1629,6 +1633,7 @@ extern "C" cpca_status cpca_approx_decode3(cpca_handle h, cpca_mode mode, const 
                                            const void* Y, double sigma_ratio, int32_t k_max,
                                            double tol, int32_t max_iter, void* X_out,
                                            double* sigma_out, cpca_approx_info* info) {
+  TraceRange trace_("cpca_approx_decode3");
   clear_error();
   STCHK(check_one_side_args("approx_decode3", mode, rho_r, rho_c, omega_c, rho_c, n, p, n, Lc, Y,
                             sigma_ratio, k_max, tol, max_iter));
@@ -1735,6 +1740,7 @@ cpca_status run_kron(cpca_handle h, const cpca_csr* L, const int32_t* omega, int
 extern "C" cpca_status cpca_kron_reduce(cpca_handle h, const cpca_csr* L, const int32_t* omega,
                                         int64_t rho, double tol, int32_t max_iter,
                                         double* Lred_out, cpca_info* info) {
+  TraceRange trace_("cpca_kron_reduce");
   clear_error();
   if (!L || !omega || !Lred_out) return fail(CPCA_EINVAL, "kron_reduce: null argument");
   if (L->n < 1 || L->n > INT32_MAX) return fail(CPCA_EINVAL, "kron_reduce: order out of range");

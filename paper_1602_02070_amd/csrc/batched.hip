@@ -764,6 +764,7 @@ extern "C" cpca_status cpca_solve_batched(cpca_handle h, cpca_mode mode,
                                           const cpca_task* tasks, int32_t n_tasks,
                                           int32_t fista_iters, double tol, int32_t max_iter,
                                           cpca_info* infos) {
+  TraceRange trace_("cpca_solve_batched");
   clear_error();
   STCHK(check_batched_args(mode, instances, n_instances, tasks, n_tasks, fista_iters, tol,
                            max_iter));

@@ -14,6 +14,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "cpca.h"
 #include "kernels.hpp"
 #include "validate.hpp"
@@ -26,6 +28,20 @@ namespace {
 enum Family { FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_RANKK = 4, FAM_COUNT = 5 };
 
 }  // namespace
+
+namespace cpca {
+
+// A named roctx range for the lifetime of the object: every entry point and
+// its host-side phases show up as ranges in a rocprofv3 --marker-trace
+// timeline (without a tool attached the calls return at once).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
+}  // namespace cpca
 
 struct cpca_handle_s {
   int device = 0;

@@ -259,6 +259,7 @@ cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, int64_t nnz, const T
 // uploads it into the handle's image buffer (synchronous upload).
 cpca_status stage_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64_t p, int64_t n,
                          uint64_t key) {
+  TraceRange trace_("decode: stage image");
   if (!h->dcache) h->dcache = new (std::nothrow) DecodeCache();
   if (!h->dcache) return fail(CPCA_ENOMEM, "host allocation failed");
   DecodeCache& dc = *h->dcache;
@@ -302,6 +303,7 @@ cpca_status stage_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
 cpca_status decode_operator(cpca_handle h, cpca_mode mode, const cpca_csr* Lr, const cpca_csr* Lc,
                             const int32_t* om_r, int64_t rho_r, const int32_t* om_c,
                             int64_t rho_c, int64_t p, int64_t n) {
+  TraceRange trace_("decode: operator image");
   HIPCHK(hipStreamSynchronize(h->stream));  // inputs may still be in flight
   uint64_t key = 0;
   STCHK(decode_key(h, mode, Lr, Lc, om_r, rho_r, om_c, rho_c, p, n, &key));
@@ -318,6 +320,7 @@ cpca_status decode_operator(cpca_handle h, cpca_mode mode, const cpca_csr* Lr, c
 cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
                          double gr, double gc, double tol, int max_iter, const Rhs& rhs,
                          const void* X0, void* out, bool want_spare, SolveOut& so) {
+  TraceRange trace_("decode: CG");
   const size_t N = (size_t)p * n;
   const bool f32 = mode != CPCA_FP64;
   const DecodeCache& dc = *h->dcache;
@@ -591,6 +594,7 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
                        int64_t rho_c, const cpca_csr* Lr_t, const cpca_csr* Lc_t, double gr,
                        double gc, double lmax_r, double lmax_c, int max_iter, double eps,
                        void* out, int* iters, double* objective, double* last_ratio) {
+  TraceRange trace_("frpcag: FISTA");
   HostCsr Lr, Lc;
   HIPCHK(hipStreamSynchronize(h->stream));
   STCHK(fetch_csr("Lr_til", Lr_t, Lr));
@@ -807,6 +811,7 @@ extern "C" cpca_status cpca_frpcag(cpca_handle h, cpca_mode mode, const void* Yt
                                    int64_t rho_c, const cpca_csr* Lr_til, const cpca_csr* Lc_til,
                                    double gamma_r, double gamma_c, double lmax_r, double lmax_c,
                                    int32_t max_iter, double eps, void* Xtil_out, cpca_info* info) {
+  TraceRange trace_("cpca_frpcag");
   clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   STCHK(check_frpcag_args(mode, Ytil, rho_r, rho_c, Lr_til, Lc_til, gamma_r, gamma_c, lmax_r,
@@ -822,6 +827,7 @@ extern "C" cpca_status cpca_frpcag(cpca_handle h, cpca_mode mode, const void* Yt
 
 extern "C" cpca_status cpca_laplacian_lmax(cpca_handle h, const cpca_csr* L, double tol,
                                            int32_t max_iter, double* lmax, cpca_info* info) {
+  TraceRange trace_("cpca_laplacian_lmax");
   clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   if (!L || !lmax) return fail(CPCA_EINVAL, "lmax: null argument");
@@ -847,6 +853,7 @@ extern "C" cpca_status cpca_decode(cpca_handle h, cpca_mode mode, const void* Xt
                                    int64_t p, int64_t n, const cpca_csr* Lr, const cpca_csr* Lc,
                                    double gamma_r, double gamma_c, double tol, int32_t max_iter,
                                    const void* X0, void* X_out, cpca_info* info) {
+  TraceRange trace_("cpca_decode");
   clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   STCHK(check_decode_args(mode, rho_r, rho_c, omega_r, omega_c, p, n, Lr, Lc, gamma_r, gamma_c,
@@ -874,6 +881,7 @@ extern "C" cpca_status cpca_decode_backward(cpca_handle h, cpca_mode mode, const
                                             const cpca_csr* Lc, double gamma_r, double gamma_c,
                                             double tol, int32_t max_iter, void* dXtil_out,
                                             double* dgamma_r, double* dgamma_c, cpca_info* info) {
+  TraceRange trace_("cpca_decode_backward");
   clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   STCHK(check_decode_args(mode, rho_r, rho_c, omega_r, omega_c, p, n, Lr, Lc, gamma_r, gamma_c,
@@ -985,6 +993,7 @@ extern "C" cpca_status cpca_apply(cpca_handle h, cpca_mode mode, const void* P, 
                                   int64_t n, const int32_t* omega_r, int64_t rho_r,
                                   const int32_t* omega_c, int64_t rho_c, const cpca_csr* Lr,
                                   const cpca_csr* Lc, double gamma_r, double gamma_c, double* pq) {
+  TraceRange trace_("cpca_apply");
   clear_error();
   STCHK(check_mode(mode));
   STCHK(check_dims("P", p, n));
@@ -1012,6 +1021,7 @@ extern "C" cpca_status cpca_apply_noalloc(cpca_handle h, cpca_mode mode, const v
                                           int64_t rho_r, const int32_t* omega_c, int64_t rho_c,
                                           const cpca_csr* Lr, const cpca_csr* Lc, double gamma_r,
                                           double gamma_c, double* pq) {
+  TraceRange trace_("cpca_apply_noalloc");
   clear_error();
   STCHK(check_mode(mode));
   STCHK(check_dims("P", p, n));

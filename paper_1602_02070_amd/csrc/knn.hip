@@ -410,6 +410,7 @@ extern "C" cpca_status cpca_knn_graph(cpca_handle h, const double* points, int64
                                       int32_t* colind_out, double* vals_out, int64_t nnz_cap,
                                       int64_t* nnz_out, double* sigma_out, int32_t* knn_out,
                                       cpca_info* info) {
+  TraceRange trace_("cpca_knn_graph");
   clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   if (!points || !rowptr_out || !colind_out || !vals_out || !nnz_out || !sigma_out)
