@@ -8,16 +8,23 @@
 //
 // Stages, all on the handle's stream:
 //  1. k_sqnorm: ||y_i||^2.
-//  2. k_knn_tiles: every workgroup takes 128 queries and sweeps all points in
-//     tiles of 64. The 128 x 64 Gram tile <y_q, y_c> comes from FP64 MFMA
-//     (v_mfma_f64_16x16x4f64, the coordinates staged through LDS in chunks of
-//     16), the squared distance is ||y_q||^2 + ||y_c||^2 - 2 <y_q, y_c>, and
-//     four threads per query keep the CAP smallest (distance, index) pairs of
-//     their quarter of each tile in registers. The four lists are merged, and
-//     the CAP >= K + 4 candidates are re-ranked by their squared distance
-//     recomputed directly (sum over coordinates of squared differences, in
-//     coordinate order, without contraction): the expanded form only selects
-//     candidates, the order and the distances are the direct ones.
+//  2. k_knn_tiles: every workgroup takes 128 queries and one segment of the
+//     points, which it sweeps in tiles of 256 (128 for K > 12). The Gram tile
+//     <y_q, y_c> comes from FP64 MFMA (v_mfma_f64_16x16x4f64, the coordinates
+//     staged through LDS in chunks of 16), the squared distance is
+//     ||y_q||^2 + ||y_c||^2 - 2 <y_q, y_c>, and four threads per query keep
+//     the CAP smallest (distance, index) pairs of their quarter of each
+//     64-wide slab in registers. The four lists are merged by (distance,
+//     index) and written per (query, segment). The segments exist only to
+//     give every compute unit the same number of workgroups; a workgroup's
+//     list is the exact CAP smallest of its segment, so the merged result
+//     does not depend on how many segments there are.
+//     k_knn_merge: per query, the segment lists are merged into the CAP
+//     smallest, and those CAP >= K + 4 candidates are re-ranked by their
+//     squared distance recomputed directly (sum over coordinates of squared
+//     differences, in coordinate order, without contraction): the expanded
+//     form only selects candidates, the order and the distances are the
+//     direct ones.
 //  3. k_knn_sigma: partial sums of the K-NN distances (deterministic order).
 //  4. k_knn_extra: each directed relation i -> j whose reverse j -> i is not
 //     a relation adds one entry to row j (the union); counted with integer
@@ -34,10 +41,11 @@ namespace {
 
 constexpr int kQT = 128;        // queries per workgroup (16 per wave)
 constexpr int kKnnThreads = 512;
-constexpr int kCT = 64;         // candidates per tile
+constexpr int kSlab = 64;       // candidates per selection slab
 constexpr int kDK = 16;         // coordinates per staged chunk
 constexpr int kDKP = kDK + 1;   // LDS row stride of the staged chunks (doubles)
-constexpr int kDTP = kCT + 1;   // LDS row stride of the distance tile
+constexpr int kDTP = kSlab + 1; // LDS row stride of the distance slab
+constexpr int kMaxSeg = 8;      // most candidate segments per query block
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -111,18 +119,28 @@ __device__ __forceinline__ void lex_insert(double (&vd)[CAP], int (&vi)[CAP], do
   }
 }
 
-template <int CAP>
+// NS slabs of 64 candidates per tile: 4 with CAP = 16; 2 with CAP = 32, whose
+// longer lists leave registers for only half the accumulators.
+template <int CAP, int NS>
 __global__ void __launch_bounds__(kKnnThreads)
-k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, int d, int K,
-            int* __restrict__ out_idx, double* __restrict__ out_d2) {
+k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, int d, int nqb,
+            int tiles_per_seg, int nseg, int* __restrict__ seg_idx, double* __restrict__ seg_d2) {
+  constexpr int kCT = kSlab * NS;  // candidates per tile
+  static_assert(kCT % kQT == 0, "the candidate tile is staged in rows of kQT");
   __shared__ double Qs[kQT * kDKP];
   __shared__ double Cs[kCT * kDKP];
   __shared__ double Ds[kQT * kDTP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
-  const int q0 = blockIdx.x * kQT;
-  // selection role: query qs of the tile, candidate quarter sub
+  // workgroups of one segment are consecutive, so the workgroups in flight
+  // sweep the same candidate tiles
+  const int qb = blockIdx.x % nqb, seg = blockIdx.x / nqb;
+  const int q0 = qb * kQT;
+  const long long cb = (long long)seg * tiles_per_seg * kCT;
+  const int cbeg = (int)(cb < N ? cb : N);
+  const int cend = (int)(cb + (long long)tiles_per_seg * kCT < N ? cb + (long long)tiles_per_seg * kCT : N);
+  // selection role: query qs of the tile, candidate quarter sub of a slab
   const int qs = tid >> 2, sub = tid & 3;
   const int qglob = q0 + qs;
   double vd[CAP];
@@ -143,29 +161,37 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
   }
   // (candidate tile, coordinate chunk) steps in order; the next step's
   // coordinates are loaded into registers before the current step's MFMAs,
-  // so their global-memory latency overlaps the matrix work
+  // so their global-memory latency overlaps the matrix work. Thread t stages
+  // row t / 4 of the query chunk and rows t / 4 + 128 j of the candidate
+  // chunk, coordinates 4 (t % 4) .. 4 (t % 4) + 3.
+  constexpr int CG = kCT / kQT;
   const int r_st = tid >> 2, cc_st = (tid & 3) * 4;
-  double qr[4], cr[4];
+  double qr[4], cr[CG][4];
   auto load_chunk = [&](int c0, int k0) {
-    const int qg = q0 + r_st, cg = c0 + r_st;
+    const int qg = q0 + r_st;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + cc_st + u;
       qr[u] = (qg < N && k < d) ? Y[(size_t)qg * d + k] : 0.0;
-      cr[u] = (r_st < kCT && cg < N && k < d) ? Y[(size_t)cg * d + k] : 0.0;
+#pragma unroll
+      for (int j = 0; j < CG; ++j) {
+        const int cg = c0 + r_st + kQT * j;
+        cr[j][u] = (cg < cend && k < d) ? Y[(size_t)cg * d + k] : 0.0;
+      }
     }
   };
-  d4 acc[4];
+  d4 acc[4 * NS];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  int c0 = 0, k0 = 0;
-  load_chunk(0, 0);
-  while (c0 < N) {
-    // stage the 64 x 16 coordinates of the queries and of the candidates
+  for (int t = 0; t < 4 * NS; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  int c0 = cbeg, k0 = 0;
+  if (c0 < cend) load_chunk(c0, 0);
+  while (c0 < cend) {
+    // stage the coordinates of the queries and of the candidates
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       Qs[r_st * kDKP + cc_st + u] = qr[u];
-      if (r_st < kCT) Cs[r_st * kDKP + cc_st + u] = cr[u];
+#pragma unroll
+      for (int j = 0; j < CG; ++j) Cs[(r_st + kQT * j) * kDKP + cc_st + u] = cr[j][u];
     }
     __syncthreads();
     int nk0 = k0 + kDK, nc0 = c0;
@@ -173,45 +199,50 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
       nk0 = 0;
       nc0 = c0 + kCT;
     }
-    if (nc0 < N) load_chunk(nc0, nk0);
+    if (nc0 < cend) load_chunk(nc0, nk0);
     const int ksteps = min(kDK, d4pad - k0) >> 2;
     for (int s = 0; s < ksteps; ++s) {
       // A: row lane % 16, k = lane / 16 of the 16 x 4 block; B likewise
       const double a = Qs[(16 * wid + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < 4 * NS; ++t) {
         const double b = Cs[(16 * t + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
     if (nk0 == 0) {
-      // tile complete: approximate squared distances into the tile, output
-      // row (lane / 16) + 4 v, column lane % 16 of each 16 x 16 block
+      // tile complete: slab by slab, the approximate squared distances go to
+      // the distance slab (output row (lane / 16) + 4 v, column lane % 16 of
+      // each 16 x 16 block) and are scanned by the selection threads
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int cl = 16 * t + (lane & 15);
-        const int c = c0 + cl;
-        const double sqc = c < N ? sq[c] : 0.0;
+      for (int sl = 0; sl < NS; ++sl) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int ql = 16 * wid + (lane >> 4) + 4 * v;
-          const int q = q0 + ql;
-          double dv = sqq[v] + sqc - 2.0 * acc[t][v];
-          if (c >= N || c == q) dv = __builtin_inf();
-          Ds[ql * kDTP + cl] = dv;
+        for (int t4 = 0; t4 < 4; ++t4) {
+          const int t = 4 * sl + t4;
+          const int cl = 16 * t4 + (lane & 15);
+          const int c = c0 + kSlab * sl + cl;
+          const double sqc = c < cend ? sq[c] : 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ql = 16 * wid + (lane >> 4) + 4 * v;
+            const int q = q0 + ql;
+            double dv = sqq[v] + sqc - 2.0 * acc[t][v];
+            if (c >= cend || c == q) dv = __builtin_inf();
+            Ds[ql * kDTP + cl] = dv;
+          }
+          acc[t] = d4{0.0, 0.0, 0.0, 0.0};
         }
-        acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-      }
-      __syncthreads();
-      // selection: this thread's 16 candidates, in increasing index
+        __syncthreads();
+        // selection: this thread's 16 candidates of the slab, in increasing index
 #pragma unroll 4
-      for (int m = 0; m < 16; ++m) {
-        const int cl = 16 * sub + m;
-        const double x = Ds[qs * kDTP + cl];
-        if (x < vd[CAP - 1]) list_insert<CAP>(vd, vi, x, c0 + cl);
+        for (int m = 0; m < 16; ++m) {
+          const int cl = 16 * sub + m;
+          const double x = Ds[qs * kDTP + cl];
+          if (x < vd[CAP - 1]) list_insert<CAP>(vd, vi, x, c0 + kSlab * sl + cl);
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     c0 = nc0;
     k0 = nk0;
@@ -237,24 +268,60 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
     }
   }
   if (sub == 0 && qglob < N) {
-    // re-rank by the directly computed squared distance
-    for (int k = 0; k < CAP; ++k) bd[k] = bi[k] < N ? direct_d2(Y, d, qglob, bi[k]) : __builtin_inf();
-    for (int a = 1; a < CAP; ++a) {
-      const double x = bd[a];
-      const int c = bi[a];
-      int pos = a;
-      while (pos > 0 && lex_less(x, c, bd[pos - 1], bi[pos - 1])) {
-        bd[pos] = bd[pos - 1];
-        bi[pos] = bi[pos - 1];
-        --pos;
-      }
-      bd[pos] = x;
-      bi[pos] = c;
+    const size_t o = ((size_t)qglob * nseg + seg) * CAP;
+#pragma unroll
+    for (int k = 0; k < CAP; ++k) {
+      seg_idx[o + k] = bi[k];
+      seg_d2[o + k] = bd[k];
     }
-    for (int k = 0; k < K; ++k) {
-      out_idx[(size_t)qglob * K + k] = bi[k];
-      out_d2[(size_t)qglob * K + k] = bd[k];
+  }
+}
+
+// One thread per query: the nseg segment lists (each ascending by
+// (approximate distance, index)) are merged into the CAP smallest, which are
+// re-ranked by the directly computed squared distance; the first K go out.
+template <int CAP>
+__global__ void __launch_bounds__(kThreads)
+k_knn_merge(const double* __restrict__ Y, int N, int d, int K, int nseg,
+            const int* __restrict__ seg_idx, const double* __restrict__ seg_d2,
+            int* __restrict__ out_idx, double* __restrict__ out_d2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N) return;
+  double bd[CAP];
+  int bi[CAP];
+  const size_t o0 = (size_t)q * nseg * CAP;
+#pragma unroll
+  for (int k = 0; k < CAP; ++k) {
+    bd[k] = seg_d2[o0 + k];
+    bi[k] = seg_idx[o0 + k];
+  }
+  for (int sg = 1; sg < nseg; ++sg) {
+    const size_t o = o0 + (size_t)sg * CAP;
+    for (int k = 0; k < CAP; ++k) {
+      const double x = seg_d2[o + k];
+      const int c = seg_idx[o + k];
+      // the list is ascending: once an entry does not make it, none after it does
+      if (c == 0x7fffffff || !lex_less(x, c, bd[CAP - 1], bi[CAP - 1])) break;
+      lex_insert<CAP>(bd, bi, x, c);
     }
+  }
+  // re-rank by the directly computed squared distance
+  for (int k = 0; k < CAP; ++k) bd[k] = bi[k] < N ? direct_d2(Y, d, q, bi[k]) : __builtin_inf();
+  for (int a = 1; a < CAP; ++a) {
+    const double x = bd[a];
+    const int c = bi[a];
+    int pos = a;
+    while (pos > 0 && lex_less(x, c, bd[pos - 1], bi[pos - 1])) {
+      bd[pos] = bd[pos - 1];
+      bi[pos] = bi[pos - 1];
+      --pos;
+    }
+    bd[pos] = x;
+    bi[pos] = c;
+  }
+  for (int k = 0; k < K; ++k) {
+    out_idx[(size_t)q * K + k] = bi[k];
+    out_d2[(size_t)q * K + k] = bd[k];
   }
 }
 
@@ -396,10 +463,37 @@ k_knn_values(int N, const int* __restrict__ rowptr, const int* __restrict__ coli
   }
 }
 
+// Number of candidate segments per query block: the one (at most kMaxSeg,
+// each segment at least 4 tiles) that fills the last round of workgroups
+// best, one resident workgroup per compute unit; ties go to fewer segments.
+int knn_segments(int nqb, int ntiles, int ncu) {
+  int best = 1;
+  double best_eff = 0.0;
+  for (int s = 1; s <= kMaxSeg; ++s) {
+    if (s > 1 && (ntiles + s - 1) / s < 4) break;
+    const long long wg = (long long)nqb * s;
+    const long long rounds = (wg + ncu - 1) / ncu;
+    const double eff = (double)wg / (double)(rounds * ncu);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = s;
+    }
+  }
+  return best;
+}
+
+template <int CAP, int NS>
+hipError_t launch_tiles(hipStream_t s, const double* Y, const double* sq, int N, int d, int nqb,
+                        int tps, int nseg, int* seg_idx, double* seg_d2) {
+  k_knn_tiles<CAP, NS><<<nqb * nseg, kKnnThreads, 0, s>>>(Y, sq, N, d, nqb, tps, nseg, seg_idx, seg_d2);
+  return hipGetLastError();
+}
+
 template <int CAP>
-hipError_t launch_tiles(hipStream_t s, const double* Y, const double* sq, int N, int d, int K,
-                        int* idx, double* d2) {
-  k_knn_tiles<CAP><<<(N + kQT - 1) / kQT, kKnnThreads, 0, s>>>(Y, sq, N, d, K, idx, d2);
+hipError_t launch_merge(hipStream_t s, const double* Y, int N, int d, int K, int nseg,
+                        const int* seg_idx, const double* seg_d2, int* idx, double* d2) {
+  k_knn_merge<CAP><<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(Y, N, d, K, nseg, seg_idx,
+                                                                      seg_d2, idx, d2);
   return hipGetLastError();
 }
 
@@ -427,9 +521,19 @@ extern "C" cpca_status cpca_knn_graph(cpca_handle h, const double* points, int64
   const int n = (int)N, dd = (int)d;
   const size_t NK = (size_t)N * K;
   const int nb = 256;
-  double *sq = nullptr, *d2 = nullptr, *part = nullptr, *deg = nullptr;
-  int *idx = nullptr, *extra = nullptr, *fill = nullptr;
+  const int cap = K <= 12 ? 16 : 32;
+  int ncu = 0;
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+  const int nqb = (n + kQT - 1) / kQT;
+  const int ct = cap == 16 ? 4 * kSlab : 2 * kSlab;  // candidates per tile
+  const int ntiles = (n + ct - 1) / ct;
+  const int nseg = knn_segments(nqb, ntiles, std::max(1, ncu));
+  const int tps = (ntiles + nseg - 1) / nseg;
+  double *sq = nullptr, *d2 = nullptr, *part = nullptr, *deg = nullptr, *sd2 = nullptr;
+  int *idx = nullptr, *extra = nullptr, *fill = nullptr, *sidx = nullptr;
   auto layout = [&](Arena& a) {
+    sd2 = a.take<double>((size_t)N * nseg * cap);
+    sidx = a.take<int>((size_t)N * nseg * cap);
     sq = a.take<double>((size_t)N);
     d2 = a.take<double>(NK);
     idx = a.take<int>(NK);
@@ -451,10 +555,13 @@ extern "C" cpca_status cpca_knn_graph(cpca_handle h, const double* points, int64
   k_sqnorm<<<g1, kThreads, 0, h->stream>>>(points, n, dd, sq);
   LAUNCHCHK();
   STCHK(prof_begin(h, FAM_OTHER));
-  hipError_t e = K <= 12 ? launch_tiles<16>(h->stream, points, sq, n, dd, K, idx, d2)
-                         : launch_tiles<32>(h->stream, points, sq, n, dd, K, idx, d2);
+  hipError_t e = cap == 16 ? launch_tiles<16, 4>(h->stream, points, sq, n, dd, nqb, tps, nseg, sidx, sd2)
+                           : launch_tiles<32, 2>(h->stream, points, sq, n, dd, nqb, tps, nseg, sidx, sd2);
   if (e != hipSuccess) return fail(CPCA_EHIP, std::string("launch: ") + hipGetErrorString(e));
   STCHK(prof_end(h));
+  e = cap == 16 ? launch_merge<16>(h->stream, points, n, dd, K, nseg, sidx, sd2, idx, d2)
+                : launch_merge<32>(h->stream, points, n, dd, K, nseg, sidx, sd2, idx, d2);
+  if (e != hipSuccess) return fail(CPCA_EHIP, std::string("launch: ") + hipGetErrorString(e));
   k_knn_sigma<<<nb, kThreads, 0, h->stream>>>(d2, NK, part);
   LAUNCHCHK();
   k_knn_sigma_final<<<1, kThreads, 0, h->stream>>>(part, nb, (double)NK, sig);
