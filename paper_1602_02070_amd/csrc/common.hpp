@@ -61,7 +61,9 @@ struct cpca_handle_s {
   bool prof = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   std::vector<int> ev_fam;
+  std::vector<int> ev_cnt;     // launches covered by each event pair
   size_t ev_used = 0;
+  bool prof_hold = false;      // per-launch events off (while a graph is captured)
   int64_t prof_n[FAM_COUNT] = {};
   double prof_ms[FAM_COUNT] = {};
   // staged operator image of the last decode on this handle, kept in its own
@@ -141,7 +143,9 @@ const double* host_results(cpca_handle h) {
 }
 
 // ---------------------------------------------------------------- profiling
-cpca_status prof_begin(cpca_handle h, int fam) {
+// A timed span on `stream` that covers `count` launches of family `fam`
+// (one launch, or a replayed graph of several).
+cpca_status prof_span_begin(cpca_handle h, int fam, hipStream_t stream) {
   if (!h->prof) return CPCA_OK;
   if (2 * h->ev_used + 2 > h->ev.size()) {
     hipEvent_t a, b;
@@ -150,16 +154,26 @@ cpca_status prof_begin(cpca_handle h, int fam) {
     h->ev.push_back(a);
     h->ev.push_back(b);
     h->ev_fam.push_back(fam);
+    h->ev_cnt.push_back(1);
   }
   h->ev_fam[h->ev_used] = fam;
-  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used], h->stream));
+  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used], stream));
   return CPCA_OK;
 }
-cpca_status prof_end(cpca_handle h) {
+cpca_status prof_span_end(cpca_handle h, hipStream_t stream, int count) {
   if (!h->prof) return CPCA_OK;
-  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream));
+  HIPCHK(hipEventRecord(h->ev[2 * h->ev_used + 1], stream));
+  h->ev_cnt[h->ev_used] = count;
   ++h->ev_used;
   return CPCA_OK;
+}
+cpca_status prof_begin(cpca_handle h, int fam) {
+  if (h->prof_hold) return CPCA_OK;
+  return prof_span_begin(h, fam, h->stream);
+}
+cpca_status prof_end(cpca_handle h) {
+  if (h->prof_hold) return CPCA_OK;
+  return prof_span_end(h, h->stream, 1);
 }
 // Only after the stream has been synchronised.
 cpca_status prof_collect(cpca_handle h) {
@@ -167,7 +181,7 @@ cpca_status prof_collect(cpca_handle h) {
   for (size_t k = 0; k < h->ev_used; ++k) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
-    h->prof_n[h->ev_fam[k]] += 1;
+    h->prof_n[h->ev_fam[k]] += h->ev_cnt[k];
     h->prof_ms[h->ev_fam[k]] += ms;
   }
   h->ev_used = 0;

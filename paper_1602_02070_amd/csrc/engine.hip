@@ -590,6 +590,64 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
   return done_status(done);
 }
 
+// FISTA runs of at least this many fixed iterations are replayed as a graph.
+constexpr int kFistaGraphMin = 16;
+
+// Algorithm 1 for exactly J iterations (no stopping test), captured on a
+// side stream as one HIP graph of J launches (the momentum coefficient and
+// the Z buffers of each iteration are fixed at capture) and replayed once.
+// Ordered after the work already on the handle's stream, and the handle's
+// stream waits for it. Per-launch profiling events are replaced by one span
+// that counts J launches. On return S holds S_J.
+cpca_status fista_graph(cpca_handle h, const ApplyCfg& cfg, const DevGraph<double>& g,
+                        const double* Y, double* S, double* Za, double* Zb, double gr, double gc,
+                        double lam, int J, int rho_r, int rho_c) {
+  FistaScal* fs = fista_ptr(h);
+  hipStream_t main = h->stream, cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipEvent_t ev = nullptr;
+  hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  cpca_status st = CPCA_OK;
+  if (err == hipSuccess) {
+    h->stream = cs;
+    h->prof_hold = true;
+    err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+      double t = 1.0;
+      for (int j = 1; j <= J && st == CPCA_OK; ++j) {
+        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        EpiFista<false> epi{Y, S, Zb, 2.0 * gr, 2.0 * gc, lam, (t - 1.0) / tn, 0.0, fs, j,
+                            nullptr, 0, nullptr};
+        st = launch_apply<double>(h, cfg, Za, rho_r, rho_c, g, epi, FAM_FISTA);
+        std::swap(Za, Zb);
+        t = tn;
+      }
+      const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      if (err == hipSuccess) err = e2;
+    }
+    h->stream = main;
+    h->prof_hold = false;
+  }
+  if (err == hipSuccess && st == CPCA_OK) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (err == hipSuccess && st == CPCA_OK) err = hipEventRecord(ev, main);
+  if (err == hipSuccess && st == CPCA_OK) err = hipStreamWaitEvent(cs, ev, 0);
+  if (err == hipSuccess && st == CPCA_OK) st = prof_span_begin(h, FAM_FISTA, cs);
+  if (err == hipSuccess && st == CPCA_OK) err = hipGraphLaunch(exec, cs);
+  if (err == hipSuccess && st == CPCA_OK) st = prof_span_end(h, cs, J);
+  if (err == hipSuccess && st == CPCA_OK) err = hipEventRecord(ev, cs);
+  if (err == hipSuccess && st == CPCA_OK) err = hipStreamWaitEvent(main, ev, 0);
+  const hipError_t e3 = hipStreamSynchronize(cs);
+  if (err == hipSuccess) err = e3;
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (ev) (void)hipEventDestroy(ev);
+  (void)hipStreamDestroy(cs);
+  if (err != hipSuccess) return fail(CPCA_EHIP, std::string("FISTA graph: ") + hipGetErrorString(err));
+  return st;
+}
+
 cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t rho_r,
                        int64_t rho_c, const cpca_csr* Lr_t, const cpca_csr* Lc_t, double gr,
                        double gc, double lmax_r, double lmax_c, int max_iter, double eps,
@@ -665,7 +723,13 @@ cpca_status run_frpcag(cpca_handle h, cpca_mode mode, const void* Ytil, int64_t 
     LAUNCHCHK();
     double t = 1.0;
     int since_check = 0, check = 8;
-    for (int j = 1; j <= max_iter; ++j) {
+    if (!reduce && max_iter >= kFistaGraphMin) {
+      // a fixed number of iterations: the whole loop is captured as one HIP
+      // graph and replayed once, so the launches do not wait on the host
+      STCHK(fista_graph(h, cfg, g, Y, S, Za, Zb, gr, gc, lam, max_iter, (int)rho_r, (int)rho_c));
+      ran = max_iter;
+    }
+    for (int j = ran + 1; j <= max_iter; ++j) {
       const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
       const double c = (t - 1.0) / tn;
       if (reduce) {

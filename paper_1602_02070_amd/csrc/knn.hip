@@ -164,19 +164,38 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
   // so their global-memory latency overlaps the matrix work. Thread t stages
   // row t / 4 of the query chunk and rows t / 4 + 128 j of the candidate
   // chunk, coordinates 4 (t % 4) .. 4 (t % 4) + 3.
+  // A row outside the range (queries past N, candidates past the segment)
+  // is read from row 0 instead: its Gram entries are never used (those
+  // distances are set to infinity, those queries are not written).
+  // Coordinates past d must be zero, since they would enter every dot
+  // product: only the last chunk checks them.
   constexpr int CG = kCT / kQT;
   const int r_st = tid >> 2, cc_st = (tid & 3) * 4;
   double qr[4], cr[CG][4];
-  auto load_chunk = [&](int c0, int k0) {
-    const int qg = q0 + r_st;
+  const double* qrow = Y + (size_t)(q0 + r_st < N ? q0 + r_st : 0) * d + cc_st;
+  const double* crow[CG];
+  auto set_rows = [&](int c0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + cc_st + u;
-      qr[u] = (qg < N && k < d) ? Y[(size_t)qg * d + k] : 0.0;
+    for (int j = 0; j < CG; ++j) {
+      const int cg = c0 + r_st + kQT * j;
+      crow[j] = Y + (size_t)(cg < cend ? cg : 0) * d + cc_st;
+    }
+  };
+  auto load_chunk = [&](int k0) {
+    if (k0 + kDK <= d) {
 #pragma unroll
-      for (int j = 0; j < CG; ++j) {
-        const int cg = c0 + r_st + kQT * j;
-        cr[j][u] = (cg < cend && k < d) ? Y[(size_t)cg * d + k] : 0.0;
+      for (int u = 0; u < 4; ++u) {
+        qr[u] = qrow[k0 + u];
+#pragma unroll
+        for (int j = 0; j < CG; ++j) cr[j][u] = crow[j][k0 + u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = k0 + cc_st + u < d;
+        qr[u] = in ? qrow[k0 + u] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CG; ++j) cr[j][u] = in ? crow[j][k0 + u] : 0.0;
       }
     }
   };
@@ -184,7 +203,10 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
 #pragma unroll
   for (int t = 0; t < 4 * NS; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
   int c0 = cbeg, k0 = 0;
-  if (c0 < cend) load_chunk(c0, 0);
+  if (c0 < cend) {
+    set_rows(c0);
+    load_chunk(0);
+  }
   while (c0 < cend) {
     // stage the coordinates of the queries and of the candidates
 #pragma unroll
@@ -199,17 +221,26 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
       nk0 = 0;
       nc0 = c0 + kCT;
     }
-    if (nc0 < cend) load_chunk(nc0, nk0);
-    const int ksteps = min(kDK, d4pad - k0) >> 2;
-    for (int s = 0; s < ksteps; ++s) {
-      // A: row lane % 16, k = lane / 16 of the 16 x 4 block; B likewise
-      const double a = Qs[(16 * wid + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
+    if (nc0 < cend) {
+      if (nc0 != c0) set_rows(nc0);
+      load_chunk(nk0);
+    }
+    // A: row lane % 16, k = lane / 16 of the 16 x 4 block; B likewise
+    const double* qa = &Qs[(16 * wid + (lane & 15)) * kDKP + (lane >> 4)];
+    const double* cb = &Cs[(lane & 15) * kDKP + (lane >> 4)];
+    auto kstep = [&](int s) {
+      const double a = qa[4 * s];
 #pragma unroll
       for (int t = 0; t < 4 * NS; ++t) {
-        const double b = Cs[(16 * t + (lane & 15)) * kDKP + 4 * s + (lane >> 4)];
+        const double b = cb[16 * t * kDKP + 4 * s];
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
       }
-    }
+    };
+    // (not unrolled: the hoisted operand reads of four steps would not fit
+    // in the registers next to the accumulators)
+    const int ksteps = min(kDK, d4pad - k0) >> 2;
+#pragma unroll 1
+    for (int s = 0; s < ksteps; ++s) kstep(s);
     __syncthreads();
     if (nk0 == 0) {
       // tile complete: slab by slab, the approximate squared distances go to
