@@ -77,6 +77,7 @@ namespace {
 // Layout of the `fixed` device block.
 constexpr size_t kOffCg = 256;             // CgScal[2]
 constexpr size_t kOffFista = 512;          // FistaScal
+static_assert(kOffCg + 2 * sizeof(CgScal) <= kOffFista, "CG scalar blocks overlap");
 constexpr size_t kOffResults = 768;        // double[32]
 constexpr size_t kFixedBytes = 1024;
 

@@ -14,6 +14,7 @@
 #include <mutex>
 #define CPCA_SPECTRAL_HOST
 #include "spectral.hpp"
+#include "pcg.hpp"
 
 // ------------------------------------------------------- no-allocation apply
 // Scratch of cpca_apply_noalloc: the staged operator image and the partial
@@ -164,6 +165,16 @@ k_hash_words(const uint32_t* __restrict__ w, size_t nw, uint64_t salt,
 }  // namespace
 
 // (global scope: the handle holds a pointer to it)
+// Host part of the two-level preconditioner's coarse space (pcg.hpp): row
+// aggregates grown breadth-first over L_r, the aggregated operators, counts
+// and sizes; the row lists and diagonals go into the operator image.
+struct PcHost {
+  bool on = false;
+  int kr = 0, kc = 0, K = 0;
+  size_t o_rows = 0, o_rptr = 0, o_ldr = 0, o_ldc = 0;
+  std::vector<double> Lra, Lca, sr, scn, wr, wc;
+};
+
 struct DecodeCache {
   uint64_t key = 0;
   bool valid = false;
@@ -173,6 +184,12 @@ struct DecodeCache {
   GraphImage<float> gi32{};
   ApplyCfg cfg64{}, cfg32{};
   int64_t nnz = 0;
+  PcHost pc;
+  // coarse inverse for (pc_gr, pc_gc) and the per-iteration work arrays
+  char* pc_buf = nullptr;
+  size_t pc_cap = 0;
+  bool pc_ready = false, pc_bad = false;
+  double pc_gr = 0.0, pc_gc = 0.0;
 };
 
 namespace {
@@ -180,6 +197,7 @@ namespace {
 void dcache_free(cpca_handle h) {
   if (!h->dcache) return;
   if (h->dcache->dev) (void)hipFree(h->dcache->dev);
+  if (h->dcache->pc_buf) (void)hipFree(h->dcache->pc_buf);
   delete h->dcache;
   h->dcache = nullptr;
 }
@@ -257,6 +275,84 @@ cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, int64_t nnz, const T
 // it in the mode's element type.
 // Builds the decoder's operator image from the validated host copies and
 // uploads it into the handle's image buffer (synchronous upload).
+// Coarse space of the two-level preconditioner: row aggregates of about
+// p kPcCols / (n kPcMaxCoarse) rows (at least kPcMinAgg), each grown
+// breadth-first over L_r from the lowest unassigned row, and column ranges
+// of kPcCols columns. Row lists and diagonals are appended to the image.
+void pc_build(PcHost& ph, Staging& stg, const HostCsr& Lr, const HostCsr& Lc,
+              const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int64_t p, int64_t n) {
+  ph = PcHost{};
+  if (p < 2 * kPcMinAgg) return;
+  const int kc = (int)((n + kPcCols - 1) / kPcCols);
+  const int64_t target_kr = std::max<int64_t>(1, kPcMaxCoarse / kc);
+  int64_t size = std::max<int64_t>(kPcMinAgg, (p + target_kr - 1) / target_kr);
+  std::vector<int32_t> lab, order, rptr, queue((size_t)p);
+  for (;;) {
+    lab.assign((size_t)p, -1);
+    order.clear();
+    rptr.assign(1, 0);
+    int kr = 0;
+    for (int64_t s0 = 0; s0 < p; ++s0) {
+      if (lab[s0] >= 0) continue;
+      int64_t head = 0, tail = 0, cnt = 1;
+      queue[tail++] = (int32_t)s0;
+      lab[s0] = kr;
+      order.push_back((int32_t)s0);
+      while (head < tail && cnt < size) {
+        const int32_t u = queue[head++];
+        for (int32_t e = Lr.rp[u]; e < Lr.rp[u + 1] && cnt < size; ++e) {
+          const int32_t v = Lr.ci[e];
+          if (lab[v] >= 0) continue;
+          lab[v] = kr;
+          order.push_back(v);
+          queue[tail++] = v;
+          ++cnt;
+        }
+      }
+      ++kr;
+      rptr.push_back((int32_t)order.size());
+    }
+    // small leftover aggregates can push the count up: grow the size instead
+    if ((int64_t)kr * kc <= 2 * kPcMaxCoarse || size >= p) {
+      ph.kr = kr;
+      break;
+    }
+    size = size + size / 2 + 1;
+  }
+  ph.kc = kc;
+  ph.K = ph.kr * kc;
+  const int kr = ph.kr;
+  ph.Lra.assign((size_t)kr * kr, 0.0);
+  ph.Lca.assign((size_t)kc * kc, 0.0);
+  ph.sr.assign(kr, 0.0);
+  ph.wr.assign(kr, 0.0);
+  ph.scn.assign(kc, 0.0);
+  ph.wc.assign(kc, 0.0);
+  std::vector<double> ldr((size_t)p, 0.0), ldc((size_t)n, 0.0);
+  for (int64_t i = 0; i < p; ++i) {
+    ph.sr[lab[i]] += mr[i];
+    ph.wr[lab[i]] += 1.0;
+    for (int32_t e = Lr.rp[i]; e < Lr.rp[i + 1]; ++e) {
+      ph.Lra[(size_t)lab[i] * kr + lab[Lr.ci[e]]] += Lr.v[e];
+      if (Lr.ci[e] == i) ldr[i] += Lr.v[e];
+    }
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    const int b = (int)(j / kPcCols);
+    ph.scn[b] += mc[j];
+    ph.wc[b] += 1.0;
+    for (int32_t e = Lc.rp[j]; e < Lc.rp[j + 1]; ++e) {
+      ph.Lca[(size_t)b * kc + Lc.ci[e] / kPcCols] += Lc.v[e];
+      if (Lc.ci[e] == j) ldc[j] += Lc.v[e];
+    }
+  }
+  ph.o_rows = stg.add(order.data(), sizeof(int32_t) * order.size());
+  ph.o_rptr = stg.add(rptr.data(), sizeof(int32_t) * rptr.size());
+  ph.o_ldr = stg.add(ldr.data(), sizeof(double) * ldr.size());
+  ph.o_ldc = stg.add(ldc.data(), sizeof(double) * ldc.size());
+  ph.on = true;
+}
+
 cpca_status stage_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64_t p, int64_t n,
                          uint64_t key) {
   TraceRange trace_("decode: stage image");
@@ -279,6 +375,9 @@ cpca_status stage_decode(cpca_handle h, cpca_mode mode, const Prepared& P, int64
                                  dc.cfg32.bw, dc.cfg32.panel || tables);
   set_panels(dc.cfg64, dc.gi64.npan);
   set_panels(dc.cfg32, dc.gi32.npan);
+  pc_build(dc.pc, stg, P.Lr, P.Lc, P.mr, P.mc, p, n);
+  dc.pc_ready = false;
+  dc.pc_bad = false;
   dc.nnz = P.Lr.nnz + P.Lc.nnz;
   dc.bytes = stg.buf.size();
   if (dc.bytes > dc.cap) {
@@ -315,6 +414,185 @@ cpca_status decode_operator(cpca_handle h, cpca_mode mode, const cpca_csr* Lr, c
   Prepared P;
   STCHK(prepare(h, Lr, Lc, om_r, rho_r, om_c, rho_c, p, n, P));
   return stage_decode(h, mode, P, p, n, key);
+}
+
+// Work arrays of the preconditioner in dc.pc_buf (K = coarse unknowns):
+// Einv K^2, tp 3K, C K, cpart K / 4 + 1, pivot row and column 2K, the
+// aggregated operators kr^2 + kc^2, counts and sizes 2 kr + 2 kc, a flag.
+struct PcLayout {
+  double *Einv, *tp, *C, *cpart, *colk, *rowk, *Lra, *Lca, *sr, *scn, *wr, *wc;
+  int* flag;
+};
+PcLayout pc_layout(char* base, const PcHost& ph, size_t* bytes) {
+  Arena a;
+  a.base = base;
+  PcLayout L;
+  const size_t K = (size_t)ph.K;
+  L.Einv = a.take<double>(K * K);
+  L.tp = a.take<double>(3 * K);
+  L.C = a.take<double>(K);
+  L.cpart = a.take<double>(K / kPcCoarseRows + 1);
+  L.colk = a.take<double>(K);
+  L.rowk = a.take<double>(K);
+  L.Lra = a.take<double>((size_t)ph.kr * ph.kr);
+  L.Lca = a.take<double>((size_t)ph.kc * ph.kc);
+  L.sr = a.take<double>(ph.kr);
+  L.scn = a.take<double>(ph.kc);
+  L.wr = a.take<double>(ph.kr);
+  L.wc = a.take<double>(ph.kc);
+  L.flag = a.take<int>(1);
+  if (bytes) *bytes = a.off;
+  return L;
+}
+
+// Whether decodes use the two-level preconditioner (CPCA_PRECOND=0: plain CG).
+bool pc_enabled() {
+  const char* s = std::getenv("CPCA_PRECOND");
+  return !(s && std::atoi(s) == 0);
+}
+
+// The coarse inverse for (gr, gc): assembled and inverted on the device
+// (Gauss-Jordan, K steps), kept while the operator and the gammas stay. A
+// non-positive pivot (E not positive definite: a singular decoder, e.g. a
+// gamma of 0) drops the coarse level for these gammas: the solve runs plain CG.
+cpca_status pc_prepare(cpca_handle h, double gr, double gc, bool* usable) {
+  DecodeCache& dc = *h->dcache;
+  *usable = false;
+  if (!dc.pc.on || !pc_enabled() || !(gr > 0.0) || !(gc > 0.0)) return CPCA_OK;
+  if (dc.pc_ready && dc.pc_gr == gr && dc.pc_gc == gc) {
+    *usable = !dc.pc_bad;
+    return CPCA_OK;
+  }
+  TraceRange trace_("decode: coarse operator");
+  const PcHost& ph = dc.pc;
+  size_t bytes = 0;
+  (void)pc_layout(nullptr, ph, &bytes);
+  if (bytes > dc.pc_cap) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (dc.pc_buf) HIPCHK(hipFree(dc.pc_buf));
+    dc.pc_buf = nullptr;
+    dc.pc_cap = 0;
+    HIPCHK(hipMalloc(&dc.pc_buf, bytes));
+    dc.pc_cap = bytes;
+  }
+  const PcLayout L = pc_layout(dc.pc_buf, ph, nullptr);
+  auto up = [&](double* dst, const std::vector<double>& v) -> hipError_t {
+    return hipMemcpyAsync(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, h->stream);
+  };
+  HIPCHK(up(L.Lra, ph.Lra));
+  HIPCHK(up(L.Lca, ph.Lca));
+  HIPCHK(up(L.sr, ph.sr));
+  HIPCHK(up(L.scn, ph.scn));
+  HIPCHK(up(L.wr, ph.wr));
+  HIPCHK(up(L.wc, ph.wc));
+  k_fill<int><<<1, kThreads, 0, h->stream>>>(L.flag, 0, 1);
+  LAUNCHCHK();
+  const int K = ph.K;
+  const size_t KK = (size_t)K * K;
+  const int g2 = (int)((KK + kThreads - 1) / kThreads), g1 = (K + kThreads - 1) / kThreads;
+  PcCoarseDev cd{L.Lra, L.Lca, L.sr, L.scn, L.wr, L.wc, ph.kr, ph.kc, K};
+  k_pc_assemble<<<g2, kThreads, 0, h->stream>>>(cd, gr, gc, L.Einv);
+  LAUNCHCHK();
+  for (int k = 0; k < K; ++k) {
+    k_gj_save<<<g1, kThreads, 0, h->stream>>>(L.Einv, K, k, L.colk, L.rowk);
+    k_gj_step<<<g2, kThreads, 0, h->stream>>>(L.Einv, K, k, L.colk, L.rowk, L.flag);
+  }
+  LAUNCHCHK();
+  k_symmetrize<<<g2, kThreads, 0, h->stream>>>(L.Einv, K);
+  LAUNCHCHK();
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, L.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  dc.pc_ready = true;
+  dc.pc_bad = flag != 0;
+  dc.pc_gr = gr;
+  dc.pc_gc = gc;
+  if (h->debug)
+    std::fprintf(stderr, "[cpca] coarse operator: %d x %d aggregates, K = %d%s\n", ph.kr, ph.kc, K,
+                 dc.pc_bad ? " (not positive definite: plain CG)" : "");
+  *usable = !dc.pc_bad;
+  return CPCA_OK;
+}
+
+PcDev pc_bind(cpca_handle h, double gr, double gc, int64_t p, int64_t n) {
+  const DecodeCache& dc = *h->dcache;
+  const PcHost& ph = dc.pc;
+  const PcLayout L = pc_layout(dc.pc_buf, ph, nullptr);
+  PcDev d;
+  d.rows = reinterpret_cast<const int32_t*>(dc.dev + ph.o_rows);
+  d.rptr = reinterpret_cast<const int32_t*>(dc.dev + ph.o_rptr);
+  d.ldr = reinterpret_cast<const double*>(dc.dev + ph.o_ldr);
+  d.ldc = reinterpret_cast<const double*>(dc.dev + ph.o_ldc);
+  d.mr = reinterpret_cast<const uint8_t*>(dc.dev + dc.gi64.o_mr);
+  d.mc = reinterpret_cast<const uint8_t*>(dc.dev + dc.gi64.o_mc);
+  d.Einv = L.Einv;
+  d.tp = L.tp;
+  d.C = L.C;
+  d.cpart = L.cpart;
+  d.gr = gr;
+  d.gc = gc;
+  d.kr = ph.kr;
+  d.kc = ph.kc;
+  d.K = ph.K;
+  d.p = (int)p;
+  d.n = (int)n;
+  return d;
+}
+
+int pc_coarse_grid(const PcDev& pc) { return (pc.K + kPcCoarseRows - 1) / kPcCoarseRows; }
+
+// Start of a preconditioned solve or segment, after k_cg_arm: rho = <r, M^-1 r>
+// and, with setp, the first direction p = M^-1 r.
+template <typename T>
+cpca_status pcg_arm(cpca_handle h, const PcDev& pc, const T* r, T* pv, bool setp) {
+  CgScal* sc = cg_ptr(h);
+  const int ncw = pc_coarse_grid(pc);
+  k_pcg_start<T><<<pc.K, kThreads, 0, h->stream>>>(r, pc, sc);
+  k_pcg_coarse<<<ncw, kThreads, 0, h->stream>>>(pc, sc, -1);
+  k_pcg_scalars<<<1, 1024, 0, h->stream>>>(pc, sc, -1, ncw);
+  if (setp) k_pcg_setp<T><<<pc.K, kThreads, 0, h->stream>>>(pv, r, sc, pc);
+  LAUNCHCHK();
+  return CPCA_OK;
+}
+
+// Preconditioned CG iterations (the counterpart of cg_iterate): the product,
+// the residual update with the tile sums, the coarse solve, the scalars and
+// the update of x and p.
+template <typename T>
+cpca_status pcg_iterate(cpca_handle h, const Operator<T>& op, const PcDev& pc, T* x, T* r, T* pv,
+                        T* q, int max_iter, const Partials& part) {
+  CgScal* sc = cg_ptr(h);
+  STCHK(read_fixed(h));
+  if (host_cg(h).done || host_cg(h).conv_it) return CPCA_OK;
+  int it = 0;
+  int chunk = 4;
+  const int ag = apply_grid(op.cfg, op.p, op.n);
+  const int ncw = pc_coarse_grid(pc);
+  while (it < max_iter) {
+    const int m = std::min(chunk, max_iter - it);
+    for (int k = 0; k < m; ++k, ++it) {
+      EpiCg<T> epi;
+      epi.Q = q;
+      epi.gr = op.gr;
+      epi.gc = op.gc;
+      epi.partials = part.a;
+      epi.sc = sc;
+      STCHK(launch_apply<T>(h, op.cfg, pv, op.p, op.n, op.g, epi, FAM_APPLY));
+      STCHK(prof_begin(h, FAM_UPDATE));
+      k_pcg_update<T><<<pc.K, kThreads, 0, h->stream>>>(r, q, sc, it, part.a, ag, pc);
+      LAUNCHCHK();
+      STCHK(prof_end(h));
+      k_pcg_coarse<<<ncw, kThreads, 0, h->stream>>>(pc, sc, it);
+      k_pcg_scalars<<<1, 1024, 0, h->stream>>>(pc, sc, it, ncw);
+      k_pcg_pupdate<T><<<pc.K, kThreads, 0, h->stream>>>(x, pv, r, sc, it, pc);
+      LAUNCHCHK();
+    }
+    STCHK(read_fixed(h));
+    STCHK(prof_collect(h));
+    if (host_cg(h).done || host_cg(h).conv_it) break;
+    chunk = std::min(chunk * 2, 64);
+  }
+  return CPCA_OK;
 }
 
 cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
@@ -431,8 +709,16 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
       k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
     LAUNCHCHK();
+    bool usepc = false;
+    STCHK(pc_prepare(h, gr, gc, &usepc));
     STCHK(tuned_cfg<double>(h, op, dc.nnz, p64, q64, pa, &op.cfg));
-    STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, part));
+    if (usepc) {
+      const PcDev pc = pc_bind(h, gr, gc, p, n);
+      STCHK(pcg_arm<double>(h, pc, r64, p64, true));
+      STCHK(pcg_iterate<double>(h, op, pc, X64, r64, p64, q64, max_iter, part));
+    } else {
+      STCHK(cg_iterate<double>(h, op, X64, r64, p64, q64, max_iter, part));
+    }
     so.iters = host_cg(h).iter;
     done = host_cg(h).done ? host_cg(h).done : (host_cg(h).conv_it ? 1 : 0);
   } else if (mode == CPCA_FP32) {
@@ -451,8 +737,16 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
       k_cg_arm<1><<<1, kThreads, 0, h->stream>>>(sc, pa, vg, thr, 0.0);
     }
     LAUNCHCHK();
+    bool usepc = false;
+    STCHK(pc_prepare(h, gr, gc, &usepc));
     STCHK(tuned_cfg<float>(h, op, dc.nnz, p32, q32, pa, &op.cfg));
-    STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
+    if (usepc) {
+      const PcDev pc = pc_bind(h, gr, gc, p, n);
+      STCHK(pcg_arm<float>(h, pc, r32, p32, true));
+      STCHK(pcg_iterate<float>(h, op, pc, x32, r32, p32, q32, max_iter, part));
+    } else {
+      STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter, part));
+    }
     so.iters = host_cg(h).iter;
     done = host_cg(h).done ? host_cg(h).done : (host_cg(h).conv_it ? 1 : 0);
     k_convert<float, double><<<vg, kThreads, 0, h->stream>>>(X64, x32, N);
@@ -487,8 +781,12 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
       EpiResidual<double, float> epi{B64, r32, p32, x32, gr, gc, pa};
       STCHK(launch_apply<double>(h, cfg64, X64, op.p, op.n, g64, epi, FAM_OTHER));
     }
+    bool usepc = false;
+    STCHK(pc_prepare(h, gr, gc, &usepc));
+    const PcDev pc = usepc ? pc_bind(h, gr, gc, p, n) : PcDev{};
     int total = 0, bad_run = 0, last_bad = 0;
-    bool keep = true;      // the first segment starts from p = r (set above)
+    bool keep = true;      // the first segment starts from p = r (set above; p = M^-1 r with
+                           // the preconditioner)
     bool restart = h->ir_restart;  // restarted-refinement mode
     constexpr double kSlow = 2.2;
     double rel_prev = HUGE_VAL, ipd_first = 0.0;  // iterations per decade, first segment
@@ -535,7 +833,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
       }
       rel_prev = rel;
       if (restart) keep = false;
-      if (!keep) {
+      if (!keep && !usepc) {
         k_convert<float, float><<<vg, kThreads, 0, h->stream>>>(p32, r32, N);  // p = r
         LAUNCHCHK();
       }
@@ -545,7 +843,13 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
         LAUNCHCHK();
       }
       if (seg == 0) STCHK(tuned_cfg<float>(h, op, dc.nnz, p32, q32, pa, &op.cfg));
-      STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part));
+      if (usepc) {
+        // rho = <r, M^-1 r> of the replaced residual; p = M^-1 r unless kept
+        STCHK(pcg_arm<float>(h, pc, r32, p32, seg == 0 || !keep));
+        STCHK(pcg_iterate<float>(h, op, pc, x32, r32, p32, q32, max_iter - total, part));
+      } else {
+        STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part));
+      }
       const CgScal ci = host_cg(h);
       if (h->debug)
         std::fprintf(stderr, "[cpca] segment %d: rel %.3e aux %.3e thr %.3e keep %d -> iters %d done %d conv %d\n",

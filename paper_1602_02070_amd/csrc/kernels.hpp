@@ -76,6 +76,7 @@ struct CgScal {
   // for a residual replacement; later iterations see conv_it and skip.
   int conv_it;
   int pad0;
+  double rho[2];  // preconditioned CG: <r, M^-1 r>, double-buffered like rr
 };
 
 // Device-resident scalars of one FISTA run.

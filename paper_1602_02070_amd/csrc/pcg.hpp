@@ -1,0 +1,364 @@
+// Two-level preconditioner for the alternate decoder's CG (not in the paper;
+// the paper solves the normal equations of its decoder, Section V-B, by
+// conjugate gradients, and any SPD preconditioner reaches the same unique
+// solution).
+//
+// Coarse space: Z = U (x) V with U the 0/1 indicator of row aggregates
+// (breadth-first groups of neighbouring L_r nodes) and V the indicator of
+// column ranges of kPcCols consecutive columns; a coarse vector is a
+// kr x kc matrix C and Z C = U C V^T is constant on every (aggregate, range)
+// tile. The preconditioner is the additive two-level one
+//
+//     M^-1 r = Z E^-1 Z^T r + D^-1 r,   E = Z^T A Z,   D = diag(A),
+//
+// with Z^T r the tile sums of r. For A(X) = (m_r m_c^T) o X + g_r L_r X +
+// g_c X L_c the coarse operator acting on C is
+//
+//     E(C) = diag(s_r) C diag(s_c) + g_r (U^T L_r U) C diag(w_c)
+//          + g_c diag(w_r) C (V^T L_c V),
+//
+// with s the sampled counts and w the sizes of the aggregates and ranges. E
+// (K = kr kc unknowns) is assembled and inverted on the device once per
+// operator and (g_r, g_c).
+//
+// The tile kernels map one workgroup to one (row aggregate, column range)
+// tile, so the tile sums need no atomics and the coarse correction is one
+// value per workgroup.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace cpca {
+
+constexpr int kPcCols = 64;          // columns per coarse column range
+constexpr int kPcMaxCoarse = 2048;   // target number of coarse unknowns
+constexpr int kPcMinAgg = 16;        // smallest row-aggregate size aimed at
+
+struct PcDev {
+  const int32_t* rows;   // row indices grouped by row aggregate
+  const int32_t* rptr;   // row aggregate a owns rows[rptr[a] .. rptr[a + 1])
+  const double* ldr;     // (L_r)_ii, p values
+  const double* ldc;     // (L_c)_jj, n values
+  const uint8_t* mr;     // row mask, p bytes
+  const uint8_t* mc;     // column mask, n bytes
+  const double* Einv;    // K x K inverse of the coarse operator, row-major
+  double* tp;            // per tile t: tp[3t] = W_t (tile sum of r), <r, r>, <r, D^-1 r>
+  double* C;             // K coarse coefficients E^-1 W
+  double* cpart;         // per coarse workgroup: <W, C>
+  double gr, gc;
+  int kr, kc, K;
+  int p, n;
+};
+
+// Rows of a coarse workgroup (one wave per row of E^-1).
+constexpr int kPcCoarseRows = kThreads / kWave;
+
+// D^-1 v for the diagonal of A at (i, j); a zero diagonal (an isolated,
+// unsampled entry: A is singular there) gives 0, the pseudo-inverse.
+template <typename T>
+__device__ __forceinline__ T pc_dinv(const PcDev& pc, int i, int j, T v) {
+  const double d = (double)(pc.mr[i] & pc.mc[j]) + pc.gr * pc.ldr[i] + pc.gc * pc.ldc[j];
+  return d > 0.0 ? v / (T)d : T(0);
+}
+
+// Walks the tile of this workgroup, VEC consecutive columns per thread:
+// f(i, j0, e0, full) with e0 = i n + j0; full: all VEC columns exist and
+// 16-byte aligned vector access is allowed (n a multiple of VEC), else the
+// caller handles the columns j0 + v < n one by one.
+template <typename T, class F>
+__device__ __forceinline__ void pc_tile_walk(const PcDev& pc, int tile, F&& f) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int LPR = kPcCols / VEC;    // lanes per row segment
+  constexpr int RP = kThreads / LPR;    // row segments in flight
+  const int a = tile / pc.kc, b = tile - a * pc.kc;
+  const int lane = threadIdx.x % LPR, slot = threadIdx.x / LPR;
+  const int j0 = b * kPcCols + lane * VEC;
+  if (j0 >= pc.n) return;
+  const bool full = (pc.n % VEC) == 0;
+  const int r0 = pc.rptr[a], r1 = pc.rptr[a + 1];
+  for (int k = r0 + slot; k < r1; k += RP) {
+    const int i = pc.rows[k];
+    f(i, j0, (size_t)i * pc.n + j0, full);
+  }
+}
+
+// Start of a preconditioned solve (and of every segment after a residual
+// replacement): tile sums W of r and the partials <r, r>, <r, D^-1 r>.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pcg_start(const T* __restrict__ r, PcDev pc, const CgScal* sc) {
+  if (sc->done != 0 || sc->conv_it != 0) return;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  double acc[3] = {0.0, 0.0, 0.0};
+  auto add = [&](int i, int j, T rv) {
+    acc[0] += (double)rv;
+    acc[1] += (double)rv * (double)rv;
+    acc[2] += (double)rv * (double)pc_dinv<T>(pc, i, j, rv);
+  };
+  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool full) {
+    if (full) {
+      T rv[VEC];
+      vld<T, VEC>(r + e0, rv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) add(i, j0 + v, rv[v]);
+    } else {
+      for (int v = 0; v < VEC && j0 + v < pc.n; ++v) add(i, j0 + v, r[e0 + v]);
+    }
+  });
+  block_partials<3>(acc, pc.tp);
+}
+
+// r -= alpha q with alpha = rho / <p, q> (rho = <r, z> of this iteration,
+// <p, q> from the product's partials); tile sums W of the new r and the
+// partials <r, r>, <r, D^-1 r>. Breakdown (<p, q> <= 0) or NaN ends the solve.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pcg_update(T* __restrict__ r, const T* __restrict__ q, CgScal* sc, int it,
+             const double* __restrict__ part_pq, int nb_pq, PcDev pc) {
+  if (sc->done != 0 || sc->conv_it != 0) return;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  double t[1];
+  sum_partials<1>(part_pq, nb_pq, t);
+  const double pq = t[0];
+  const double rho = sc->rho[it & 1];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (bad(pq) || !(pq > 0.0)) {
+    if (lead) {
+      sc->pq = pq;
+      sc->iter = it;
+      sc->done = bad(pq) ? 3 : 2;
+    }
+    return;
+  }
+  const double alpha_d = rho / pq;
+  if (lead) {
+    sc->pq = pq;
+    sc->alpha = alpha_d;
+  }
+  const T alpha = (T)alpha_d;
+  double acc[3] = {0.0, 0.0, 0.0};
+  auto add = [&](int i, int j, T rv) {
+    acc[0] += (double)rv;
+    acc[1] += (double)rv * (double)rv;
+    acc[2] += (double)rv * (double)pc_dinv<T>(pc, i, j, rv);
+  };
+  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool full) {
+    if (full) {
+      T rv[VEC], qv[VEC];
+      vld<T, VEC>(r + e0, rv);
+      vld<T, VEC>(q + e0, qv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        rv[v] -= alpha * qv[v];
+        add(i, j0 + v, rv[v]);
+      }
+      vst<T, VEC>(r + e0, rv);
+    } else {
+      for (int v = 0; v < VEC && j0 + v < pc.n; ++v) {
+        const T rn = r[e0 + v] - alpha * q[e0 + v];
+        r[e0 + v] = rn;
+        add(i, j0 + v, rn);
+      }
+    }
+  });
+  block_partials<3>(acc, pc.tp);
+}
+
+// C = E^-1 W, one wave per row; partials of <W, C> per workgroup. `it` < 0:
+// the start of a solve or segment.
+__global__ void __launch_bounds__(kThreads)
+k_pcg_coarse(PcDev pc, const CgScal* sc, int it) {
+  if (sc->done != 0) return;
+  if (it < 0 ? sc->conv_it != 0 : sc->conv_it != 0 && sc->conv_it <= it) return;
+  __shared__ double red[kPcCoarseRows];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int row = blockIdx.x * kPcCoarseRows + w;
+  double wc = 0.0;
+  if (row < pc.K) {
+    const double* e = pc.Einv + (size_t)row * pc.K;
+    double s = 0.0;
+    for (int k = lane; k < pc.K; k += kWave) s += e[k] * pc.tp[3 * k];
+    s = wave_sum(s);
+    if (lane == 0) pc.C[row] = s;
+    wc = s * pc.tp[3 * row];
+  }
+  if (lane == 0) red[w] = wc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < kPcCoarseRows; ++k) tot += red[k];
+    pc.cpart[blockIdx.x] = tot;
+  }
+}
+
+// One workgroup: rho_new = <W, C> + <r, D^-1 r> = <r, M^-1 r> and <r, r>
+// from the partials. it < 0 (start): rho[0] = rho_new. Else beta = rho_new /
+// rho, the convergence stamp (<r, r> <= thr: conv_it = it + 1) and, in an FP32
+// segment of a residual-replacement solve, the divergence test.
+__global__ void __launch_bounds__(1024)
+k_pcg_scalars(PcDev pc, CgScal* sc, int it, int ncw) {
+  if (sc->done != 0) return;
+  if (it < 0 ? sc->conv_it != 0 : sc->conv_it != 0 && sc->conv_it <= it) return;
+  __shared__ double red[3][1024 / kWave];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < pc.K; k += blockDim.x) {
+    a[0] += pc.tp[3 * k + 1];
+    a[1] += pc.tp[3 * k + 2];
+  }
+  for (int k = threadIdx.x; k < ncw; k += blockDim.x) a[2] += pc.cpart[k];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double s = wave_sum(a[c]);
+    if (lane == 0) red[c][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) tot[c] += red[c][k];
+  const double rr = tot[0], rho_new = tot[2] + tot[1];
+  if (it < 0) {
+    if (bad(rho_new) || bad(rr)) {
+      sc->done = 3;
+      return;
+    }
+    sc->rho[0] = rho_new;
+    sc->rho[1] = rho_new;
+    return;
+  }
+  if (bad(rr) || bad(rho_new)) {
+    sc->iter = it + 1;
+    sc->done = 3;
+    return;
+  }
+  if (sc->aux > 0.0 && rr > kDiverge * sc->aux) {
+    sc->iter = it + 1;
+    sc->done = 4;
+    return;
+  }
+  sc->beta = rho_new / sc->rho[it & 1];
+  sc->rho[(it + 1) & 1] = rho_new;
+  sc->rr[(it + 1) & 1] = rr;
+  sc->iter = it + 1;
+  if (rr <= sc->thr) sc->conv_it = it + 1;
+}
+
+// x += alpha p; p = z + beta p with z = C(tile) + D^-1 r. The converging
+// iteration still runs in full (see CgScal::conv_it).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pcg_pupdate(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ r, CgScal* sc, int it,
+              PcDev pc) {
+  if (sc->done != 0) return;
+  if (sc->conv_it != 0 && sc->conv_it <= it) return;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const T alpha = (T)sc->alpha, beta = (T)sc->beta;
+  const T c = (T)pc.C[blockIdx.x];
+  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool full) {
+    if (full) {
+      T xv[VEC], pv[VEC], rv[VEC];
+      vld<T, VEC>(x + e0, xv);
+      vld<T, VEC>(p + e0, pv);
+      vld<T, VEC>(r + e0, rv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        xv[v] += alpha * pv[v];
+        pv[v] = c + pc_dinv<T>(pc, i, j0 + v, rv[v]) + beta * pv[v];
+      }
+      vst<T, VEC>(x + e0, xv);
+      vst<T, VEC>(p + e0, pv);
+    } else {
+      for (int v = 0; v < VEC && j0 + v < pc.n; ++v) {
+        const size_t e = e0 + v;
+        const T pv = p[e];
+        x[e] += alpha * pv;
+        p[e] = c + pc_dinv<T>(pc, i, j0 + v, r[e]) + beta * pv;
+      }
+    }
+  });
+}
+
+// p = z = C(tile) + D^-1 r (start of a solve, or of a segment that does not
+// keep its direction).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pcg_setp(T* __restrict__ p, const T* __restrict__ r, const CgScal* sc, PcDev pc) {
+  if (sc->done != 0 || sc->conv_it != 0) return;
+  const T c = (T)pc.C[blockIdx.x];
+  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool) {
+    for (int v = 0; v < 16 / (int)sizeof(T) && j0 + v < pc.n; ++v)
+      p[e0 + v] = c + pc_dinv<T>(pc, i, j0 + v, r[e0 + v]);
+  });
+}
+
+// ------------------------------------------------- coarse operator set-up
+struct PcCoarseDev {
+  const double* Lra;   // kr x kr: U^T L_r U
+  const double* Lca;   // kc x kc: V^T L_c V
+  const double* sr;    // sampled rows per aggregate
+  const double* scn;   // sampled columns per range
+  const double* wr;    // rows per aggregate
+  const double* wc;    // columns per range
+  int kr, kc, K;
+};
+
+// E (K x K) from the aggregated operators.
+__global__ void __launch_bounds__(kThreads)
+k_pc_assemble(PcCoarseDev cd, double gr, double gc, double* __restrict__ E) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)cd.K * cd.K) return;
+  const int I = (int)(e / cd.K), J = (int)(e % cd.K);
+  const int a = I / cd.kc, b = I % cd.kc, a2 = J / cd.kc, b2 = J % cd.kc;
+  double v = 0.0;
+  if (b == b2) v += gr * cd.Lra[(size_t)a * cd.kr + a2] * cd.wc[b];
+  if (a == a2) v += gc * cd.wr[a] * cd.Lca[(size_t)b * cd.kc + b2];
+  if (I == J) v += cd.sr[a] * cd.scn[b];
+  E[e] = v;
+}
+
+// Gauss-Jordan inversion in place, step k: the pivot row and column are
+// saved first (k_gj_save), then every element is updated from the saved
+// copies (k_gj_step). E is symmetric positive definite, so the pivots are
+// positive and no pivoting is needed.
+__global__ void __launch_bounds__(kThreads)
+k_gj_save(const double* __restrict__ A, int K, int k, double* __restrict__ colk,
+          double* __restrict__ rowk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  colk[i] = A[(size_t)i * K + k];
+  rowk[i] = A[(size_t)k * K + i];
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_gj_step(double* __restrict__ A, int K, int k, const double* __restrict__ colk,
+          const double* __restrict__ rowk, int* __restrict__ bad_pivot) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)K * K) return;
+  const int i = (int)(e / K), j = (int)(e % K);
+  if (!(rowk[k] > 0.0)) {  // not positive definite: the caller drops the coarse level
+    if (e == 0) *bad_pivot = 1;
+    return;
+  }
+  const double pinv = 1.0 / rowk[k];
+  double v;
+  if (i == k && j == k) v = pinv;
+  else if (i == k) v = rowk[j] * pinv;
+  else if (j == k) v = -colk[i] * pinv;
+  else v = A[e] - colk[i] * rowk[j] * pinv;
+  A[e] = v;
+}
+
+// A = (A + A^T) / 2.
+__global__ void __launch_bounds__(kThreads)
+k_symmetrize(double* __restrict__ A, int K) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)K * K) return;
+  const int i = (int)(e / K), j = (int)(e % K);
+  if (j <= i) return;
+  const double v = 0.5 * (A[e] + A[(size_t)j * K + i]);
+  A[e] = v;
+  A[(size_t)j * K + i] = v;
+}
+
+}  // namespace cpca
