@@ -78,19 +78,38 @@ struct Partials {
 // Runs CG iterations on (x, r, p, q) whose scalars were armed on the device.
 // The host launches chunks of iterations and polls the device flag between
 // chunks; kernels of a finished solve return immediately.
+// Iterations launched between two polls of the device flags. `expect`: the
+// count the solve is likely to need (the previous segment's, 0 if unknown).
+// The first chunk stops a little short of it, then chunks start again at 4
+// and double up to 64, so a converged solve leaves few launches that return
+// at once.
+struct ChunkPlan {
+  int expect, chunk;
+  bool past;
+  explicit ChunkPlan(int e) : expect(e), chunk(e > 8 ? e - 4 : 4), past(e <= 8) {}
+  void next() {
+    if (!past) {
+      past = true;
+      chunk = 4;
+    } else {
+      chunk = std::min(chunk * 2, 64);
+    }
+  }
+};
+
 template <typename T>
 cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, T* q,
-                       int max_iter, const Partials& part) {
+                       int max_iter, const Partials& part, int expect = 0) {
   const size_t N = (size_t)op.p * op.n;
   CgScal* sc = cg_ptr(h);
   STCHK(read_fixed(h));
   if (host_cg(h).done || host_cg(h).conv_it) return CPCA_OK;
   int it = 0;
-  int chunk = 4;
+  ChunkPlan plan(expect);
   const int ag = apply_grid(op.cfg, op.p, op.n);
   const int vg = vec_grid(N / V16<T>::W + 1);
   while (it < max_iter) {
-    const int m = std::min(chunk, max_iter - it);
+    const int m = std::min(plan.chunk, max_iter - it);
     for (int k = 0; k < m; ++k, ++it) {
       EpiCg<T> epi;
       epi.Q = q;
@@ -109,7 +128,7 @@ cpca_status cg_iterate(cpca_handle h, const Operator<T>& op, T* x, T* r, T* pv, 
     STCHK(read_fixed(h));
     STCHK(prof_collect(h));
     if (host_cg(h).done || host_cg(h).conv_it) break;
-    chunk = std::min(chunk * 2, 64);
+    plan.next();
   }
   return CPCA_OK;
 }
@@ -279,12 +298,46 @@ cpca_status tuned_cfg(cpca_handle h, const Operator<T>& op, int64_t nnz, const T
 // p kPcCols / (n kPcMaxCoarse) rows (at least kPcMinAgg), each grown
 // breadth-first over L_r from the lowest unassigned row, and column ranges
 // of kPcCols columns. Row lists and diagonals are appended to the image.
+// Whether every connected component of the graph holds a sampled node.
+// Otherwise (gammas > 0) the decoder's operator is singular: its null space
+// holds matrices that are constant on a component without samples, and the
+// solution taken is the minimum-norm one that plain CG from zero reaches;
+// the coarse correction would add components along that null space.
+bool pc_components_sampled(const HostCsr& L, const std::vector<uint8_t>& m) {
+  const int64_t N = L.n;
+  std::vector<uint8_t> seen((size_t)N, 0);
+  std::vector<int32_t> stack;
+  for (int64_t s0 = 0; s0 < N; ++s0) {
+    if (seen[s0]) continue;
+    bool sampled = false;
+    seen[s0] = 1;
+    stack.assign(1, (int32_t)s0);
+    while (!stack.empty()) {
+      const int32_t u = stack.back();
+      stack.pop_back();
+      sampled = sampled || m[u] != 0;
+      for (int32_t e = L.rp[u]; e < L.rp[u + 1]; ++e) {
+        const int32_t v = L.ci[e];
+        if (!seen[v] && L.v[e] != 0.0) {
+          seen[v] = 1;
+          stack.push_back(v);
+        }
+      }
+    }
+    if (!sampled) return false;
+  }
+  return true;
+}
+
 void pc_build(PcHost& ph, Staging& stg, const HostCsr& Lr, const HostCsr& Lc,
               const std::vector<uint8_t>& mr, const std::vector<uint8_t>& mc, int64_t p, int64_t n) {
   ph = PcHost{};
   if (p < 2 * kPcMinAgg) return;
+  if (!pc_components_sampled(Lr, mr) || !pc_components_sampled(Lc, mc)) return;
   const int kc = (int)((n + kPcCols - 1) / kPcCols);
-  const int64_t target_kr = std::max<int64_t>(1, kPcMaxCoarse / kc);
+  int target_k = kPcMaxCoarse;  // CPCA_PC_COARSE: another target (for measurements)
+  if (const char* e = std::getenv("CPCA_PC_COARSE")) target_k = std::max(1, std::min(16384, std::atoi(e)));
+  const int64_t target_kr = std::max<int64_t>(1, target_k / kc);
   int64_t size = std::max<int64_t>(kPcMinAgg, (p + target_kr - 1) / target_kr);
   std::vector<int32_t> lab, order, rptr, queue((size_t)p);
   for (;;) {
@@ -313,7 +366,7 @@ void pc_build(PcHost& ph, Staging& stg, const HostCsr& Lr, const HostCsr& Lc,
       rptr.push_back((int32_t)order.size());
     }
     // small leftover aggregates can push the count up: grow the size instead
-    if ((int64_t)kr * kc <= 2 * kPcMaxCoarse || size >= p) {
+    if ((int64_t)kr * kc <= 2 * (int64_t)target_k || size >= p) {
       ph.kr = kr;
       break;
     }
@@ -346,6 +399,8 @@ void pc_build(PcHost& ph, Staging& stg, const HostCsr& Lr, const HostCsr& Lc,
       if (Lc.ci[e] == j) ldc[j] += Lc.v[e];
     }
   }
+  // rows of an aggregate in ascending order (nearby rows are read together)
+  for (int a = 0; a < kr; ++a) std::sort(order.begin() + rptr[a], order.begin() + rptr[a + 1]);
   ph.o_rows = stg.add(order.data(), sizeof(int32_t) * order.size());
   ph.o_rptr = stg.add(rptr.data(), sizeof(int32_t) * rptr.size());
   ph.o_ldr = stg.add(ldr.data(), sizeof(double) * ldr.size());
@@ -417,10 +472,12 @@ cpca_status decode_operator(cpca_handle h, cpca_mode mode, const cpca_csr* Lr, c
 }
 
 // Work arrays of the preconditioner in dc.pc_buf (K = coarse unknowns):
-// Einv K^2, tp 3K, C K, cpart K / 4 + 1, pivot row and column 2K, the
-// aggregated operators kr^2 + kc^2, counts and sizes 2 kr + 2 kc, a flag.
+// E (inverted in place, FP64) K^2, its FP32 copy K^2, tp 3K, C K, cpart
+// K / 4 + 1, pivot row and column 2K, the aggregated operators kr^2 + kc^2,
+// counts and sizes 2 kr + 2 kc, a flag.
 struct PcLayout {
-  double *Einv, *tp, *C, *cpart, *colk, *rowk, *Lra, *Lca, *sr, *scn, *wr, *wc;
+  double *E, *tp, *W, *C, *cpart, *colk, *rowk, *Lra, *Lca, *sr, *scn, *wr, *wc;
+  float* Einv;
   int* flag;
 };
 PcLayout pc_layout(char* base, const PcHost& ph, size_t* bytes) {
@@ -428,8 +485,11 @@ PcLayout pc_layout(char* base, const PcHost& ph, size_t* bytes) {
   a.base = base;
   PcLayout L;
   const size_t K = (size_t)ph.K;
-  L.Einv = a.take<double>(K * K);
-  L.tp = a.take<double>(3 * K);
+  L.E = a.take<double>(K * K);
+  L.Einv = a.take<float>(K * K);
+  // vector workgroups: kr ceil(kc / rg) split <= kr (kc / 2 + 1) 8, rg + 2 <= 6 partials each
+  L.tp = a.take<double>(((size_t)ph.kr * (ph.kc / 2 + 1) * 8) * 6);
+  L.W = a.take<double>(K);
   L.C = a.take<double>(K);
   L.cpart = a.take<double>(K / kPcCoarseRows + 1);
   L.colk = a.take<double>(K);
@@ -491,14 +551,14 @@ cpca_status pc_prepare(cpca_handle h, double gr, double gc, bool* usable) {
   const size_t KK = (size_t)K * K;
   const int g2 = (int)((KK + kThreads - 1) / kThreads), g1 = (K + kThreads - 1) / kThreads;
   PcCoarseDev cd{L.Lra, L.Lca, L.sr, L.scn, L.wr, L.wc, ph.kr, ph.kc, K};
-  k_pc_assemble<<<g2, kThreads, 0, h->stream>>>(cd, gr, gc, L.Einv);
+  k_pc_assemble<<<g2, kThreads, 0, h->stream>>>(cd, gr, gc, L.E);
   LAUNCHCHK();
   for (int k = 0; k < K; ++k) {
-    k_gj_save<<<g1, kThreads, 0, h->stream>>>(L.Einv, K, k, L.colk, L.rowk);
-    k_gj_step<<<g2, kThreads, 0, h->stream>>>(L.Einv, K, k, L.colk, L.rowk, L.flag);
+    k_gj_save<<<g1, kThreads, 0, h->stream>>>(L.E, K, k, L.colk, L.rowk);
+    k_gj_step<<<g2, kThreads, 0, h->stream>>>(L.E, K, k, L.colk, L.rowk, L.flag);
   }
   LAUNCHCHK();
-  k_symmetrize<<<g2, kThreads, 0, h->stream>>>(L.Einv, K);
+  k_symmetrize_f32<<<g2, kThreads, 0, h->stream>>>(L.E, K, L.Einv);
   LAUNCHCHK();
   int flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, L.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -514,7 +574,7 @@ cpca_status pc_prepare(cpca_handle h, double gr, double gc, bool* usable) {
   return CPCA_OK;
 }
 
-PcDev pc_bind(cpca_handle h, double gr, double gc, int64_t p, int64_t n) {
+PcDev pc_bind(cpca_handle h, double gr, double gc, int64_t p, int64_t n, size_t elem) {
   const DecodeCache& dc = *h->dcache;
   const PcHost& ph = dc.pc;
   const PcLayout L = pc_layout(dc.pc_buf, ph, nullptr);
@@ -527,6 +587,7 @@ PcDev pc_bind(cpca_handle h, double gr, double gc, int64_t p, int64_t n) {
   d.mc = reinterpret_cast<const uint8_t*>(dc.dev + dc.gi64.o_mc);
   d.Einv = L.Einv;
   d.tp = L.tp;
+  d.W = L.W;
   d.C = L.C;
   d.cpart = L.cpart;
   d.gr = gr;
@@ -536,6 +597,10 @@ PcDev pc_bind(cpca_handle h, double gr, double gc, int64_t p, int64_t n) {
   d.K = ph.K;
   d.p = (int)p;
   d.n = (int)n;
+  d.rg = (int)(16 / elem);
+  d.ng = (ph.kc + d.rg - 1) / d.rg;
+  // enough vector workgroups (about 4096) to keep many row segments in flight
+  d.split = std::max(1, std::min(8, (4096 + ph.kr * d.ng - 1) / (ph.kr * d.ng)));
   return d;
 }
 
@@ -547,10 +612,12 @@ template <typename T>
 cpca_status pcg_arm(cpca_handle h, const PcDev& pc, const T* r, T* pv, bool setp) {
   CgScal* sc = cg_ptr(h);
   const int ncw = pc_coarse_grid(pc);
-  k_pcg_start<T><<<pc.K, kThreads, 0, h->stream>>>(r, pc, sc);
+  const int gw = (pc.K + kThreads - 1) / kThreads;
+  k_pcg_start<T><<<pc_nwg(pc), kThreads, 0, h->stream>>>(r, pc, sc);
+  k_pcg_wsum<<<gw, kThreads, 0, h->stream>>>(pc, sc, -1);
   k_pcg_coarse<<<ncw, kThreads, 0, h->stream>>>(pc, sc, -1);
   k_pcg_scalars<<<1, 1024, 0, h->stream>>>(pc, sc, -1, ncw);
-  if (setp) k_pcg_setp<T><<<pc.K, kThreads, 0, h->stream>>>(pv, r, sc, pc);
+  if (setp) k_pcg_setp<T><<<pc_nwg(pc), kThreads, 0, h->stream>>>(pv, r, sc, pc);
   LAUNCHCHK();
   return CPCA_OK;
 }
@@ -560,16 +627,17 @@ cpca_status pcg_arm(cpca_handle h, const PcDev& pc, const T* r, T* pv, bool setp
 // the update of x and p.
 template <typename T>
 cpca_status pcg_iterate(cpca_handle h, const Operator<T>& op, const PcDev& pc, T* x, T* r, T* pv,
-                        T* q, int max_iter, const Partials& part) {
+                        T* q, int max_iter, const Partials& part, int expect = 0) {
   CgScal* sc = cg_ptr(h);
   STCHK(read_fixed(h));
   if (host_cg(h).done || host_cg(h).conv_it) return CPCA_OK;
   int it = 0;
-  int chunk = 4;
+  ChunkPlan plan(expect);
   const int ag = apply_grid(op.cfg, op.p, op.n);
   const int ncw = pc_coarse_grid(pc);
+  const int gw = (pc.K + kThreads - 1) / kThreads;
   while (it < max_iter) {
-    const int m = std::min(chunk, max_iter - it);
+    const int m = std::min(plan.chunk, max_iter - it);
     for (int k = 0; k < m; ++k, ++it) {
       EpiCg<T> epi;
       epi.Q = q;
@@ -579,18 +647,19 @@ cpca_status pcg_iterate(cpca_handle h, const Operator<T>& op, const PcDev& pc, T
       epi.sc = sc;
       STCHK(launch_apply<T>(h, op.cfg, pv, op.p, op.n, op.g, epi, FAM_APPLY));
       STCHK(prof_begin(h, FAM_UPDATE));
-      k_pcg_update<T><<<pc.K, kThreads, 0, h->stream>>>(r, q, sc, it, part.a, ag, pc);
+      k_pcg_update<T><<<pc_nwg(pc), kThreads, 0, h->stream>>>(r, q, sc, it, part.a, ag, pc);
       LAUNCHCHK();
       STCHK(prof_end(h));
+      k_pcg_wsum<<<gw, kThreads, 0, h->stream>>>(pc, sc, it);
       k_pcg_coarse<<<ncw, kThreads, 0, h->stream>>>(pc, sc, it);
       k_pcg_scalars<<<1, 1024, 0, h->stream>>>(pc, sc, it, ncw);
-      k_pcg_pupdate<T><<<pc.K, kThreads, 0, h->stream>>>(x, pv, r, sc, it, pc);
+      k_pcg_pupdate<T><<<pc_nwg(pc), kThreads, 0, h->stream>>>(x, pv, r, sc, it, pc);
       LAUNCHCHK();
     }
     STCHK(read_fixed(h));
     STCHK(prof_collect(h));
     if (host_cg(h).done || host_cg(h).conv_it) break;
-    chunk = std::min(chunk * 2, 64);
+    plan.next();
   }
   return CPCA_OK;
 }
@@ -713,7 +782,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
     STCHK(pc_prepare(h, gr, gc, &usepc));
     STCHK(tuned_cfg<double>(h, op, dc.nnz, p64, q64, pa, &op.cfg));
     if (usepc) {
-      const PcDev pc = pc_bind(h, gr, gc, p, n);
+      const PcDev pc = pc_bind(h, gr, gc, p, n, sizeof(double));
       STCHK(pcg_arm<double>(h, pc, r64, p64, true));
       STCHK(pcg_iterate<double>(h, op, pc, X64, r64, p64, q64, max_iter, part));
     } else {
@@ -741,7 +810,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
     STCHK(pc_prepare(h, gr, gc, &usepc));
     STCHK(tuned_cfg<float>(h, op, dc.nnz, p32, q32, pa, &op.cfg));
     if (usepc) {
-      const PcDev pc = pc_bind(h, gr, gc, p, n);
+      const PcDev pc = pc_bind(h, gr, gc, p, n, sizeof(float));
       STCHK(pcg_arm<float>(h, pc, r32, p32, true));
       STCHK(pcg_iterate<float>(h, op, pc, x32, r32, p32, q32, max_iter, part));
     } else {
@@ -783,7 +852,7 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
     }
     bool usepc = false;
     STCHK(pc_prepare(h, gr, gc, &usepc));
-    const PcDev pc = usepc ? pc_bind(h, gr, gc, p, n) : PcDev{};
+    const PcDev pc = usepc ? pc_bind(h, gr, gc, p, n, sizeof(float)) : PcDev{};
     int total = 0, bad_run = 0, last_bad = 0;
     bool keep = true;      // the first segment starts from p = r (set above; p = M^-1 r with
                            // the preconditioner)
@@ -846,9 +915,9 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
       if (usepc) {
         // rho = <r, M^-1 r> of the replaced residual; p = M^-1 r unless kept
         STCHK(pcg_arm<float>(h, pc, r32, p32, seg == 0 || !keep));
-        STCHK(pcg_iterate<float>(h, op, pc, x32, r32, p32, q32, max_iter - total, part));
+        STCHK(pcg_iterate<float>(h, op, pc, x32, r32, p32, q32, max_iter - total, part, seg_iters));
       } else {
-        STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part));
+        STCHK(cg_iterate<float>(h, op, x32, r32, p32, q32, max_iter - total, part, seg_iters));
       }
       const CgScal ci = host_cg(h);
       if (h->debug)

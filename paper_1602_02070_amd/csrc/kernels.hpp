@@ -1198,7 +1198,7 @@ k_cg_arm(CgScal* sc, const double* part, int nb, double thr_abs, double rel_tol2
   if (threadIdx.x != 0) return;
   const double rr = t[NV - 1];
   const double thr = thr_abs >= 0.0 ? thr_abs : rel_tol2 * rr;
-  if (NV == 2) {
+  if constexpr (NV == 2) {
     sc->res2 = t[0];
     sc->aux = t[1];
   } else {

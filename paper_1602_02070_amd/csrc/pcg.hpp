@@ -21,9 +21,11 @@
 // (K = kr kc unknowns) is assembled and inverted on the device once per
 // operator and (g_r, g_c).
 //
-// The tile kernels map one workgroup to one (row aggregate, column range)
-// tile, so the tile sums need no atomics and the coarse correction is one
-// value per workgroup.
+// The vector kernels map one workgroup to one row aggregate and a group of
+// column ranges that one wave covers in a row (4 ranges, 1 KiB of a row, in
+// FP32; 2 in FP64), split over `split` workgroups along the rows; each
+// writes one partial per range, so the tile sums need no atomics, and each
+// lane adds the coarse value of its own range.
 #pragma once
 
 #include "kernels.hpp"
@@ -31,24 +33,44 @@
 namespace cpca {
 
 constexpr int kPcCols = 64;          // columns per coarse column range
-constexpr int kPcMaxCoarse = 2048;   // target number of coarse unknowns
+constexpr int kPcMaxCoarse = 4096;   // target number of coarse unknowns
 constexpr int kPcMinAgg = 16;        // smallest row-aggregate size aimed at
 
 struct PcDev {
-  const int32_t* rows;   // row indices grouped by row aggregate
+  const int32_t* rows;   // row indices grouped by row aggregate (ascending within one)
   const int32_t* rptr;   // row aggregate a owns rows[rptr[a] .. rptr[a + 1])
   const double* ldr;     // (L_r)_ii, p values
   const double* ldc;     // (L_c)_jj, n values
   const uint8_t* mr;     // row mask, p bytes
   const uint8_t* mc;     // column mask, n bytes
-  const double* Einv;    // K x K inverse of the coarse operator, row-major
-  double* tp;            // per tile t: tp[3t] = W_t (tile sum of r), <r, r>, <r, D^-1 r>
+  const float* Einv;     // K x K inverse of the coarse operator, row-major (FP32: a
+                         // preconditioner needs no more)
+  double* tp;            // per vector workgroup: rg range sums of r, <r, r>, <r, D^-1 r>
+  double* W;             // K tile sums of r (Z^T r), from tp
   double* C;             // K coarse coefficients E^-1 W
   double* cpart;         // per coarse workgroup: <W, C>
   double gr, gc;
   int kr, kc, K;
   int p, n;
+  int rg;                // ranges per group: 4 (FP32) or 2 (FP64)
+  int ng;                // range groups, ceil(kc / rg)
+  int split;             // workgroups per (aggregate, group)
 };
+
+// Vector workgroups of a solve in element type T.
+template <typename T>
+constexpr int pc_rg() { return kWave * (16 / (int)sizeof(T)) / kPcCols; }
+__host__ __device__ inline int pc_nwg(const PcDev& pc) { return pc.kr * pc.ng * pc.split; }
+
+// Tile sum W_k of coarse unknown k = a kc + b from the partials.
+__device__ __forceinline__ double pc_w(const PcDev& pc, int k) {
+  const int a = k / pc.kc, b = k - a * pc.kc;
+  const int g = b / pc.rg, q = b - g * pc.rg;
+  const size_t base = ((size_t)a * pc.ng + g) * pc.split;
+  double s = 0.0;
+  for (int t = 0; t < pc.split; ++t) s += pc.tp[(base + t) * (pc.rg + 2) + q];
+  return s;
+}
 
 // Rows of a coarse workgroup (one wave per row of E^-1).
 constexpr int kPcCoarseRows = kThreads / kWave;
@@ -61,25 +83,69 @@ __device__ __forceinline__ T pc_dinv(const PcDev& pc, int i, int j, T v) {
   return d > 0.0 ? v / (T)d : T(0);
 }
 
-// Walks the tile of this workgroup, VEC consecutive columns per thread:
-// f(i, j0, e0, full) with e0 = i n + j0; full: all VEC columns exist and
-// 16-byte aligned vector access is allowed (n a multiple of VEC), else the
-// caller handles the columns j0 + v < n one by one.
-template <typename T, class F>
-__device__ __forceinline__ void pc_tile_walk(const PcDev& pc, int tile, F&& f) {
-  constexpr int VEC = 16 / (int)sizeof(T);
-  constexpr int LPR = kPcCols / VEC;    // lanes per row segment
-  constexpr int RP = kThreads / LPR;    // row segments in flight
-  const int a = tile / pc.kc, b = tile - a * pc.kc;
-  const int lane = threadIdx.x % LPR, slot = threadIdx.x / LPR;
-  const int j0 = b * kPcCols + lane * VEC;
-  if (j0 >= pc.n) return;
-  const bool full = (pc.n % VEC) == 0;
-  const int r0 = pc.rptr[a], r1 = pc.rptr[a + 1];
-  for (int k = r0 + slot; k < r1; k += RP) {
-    const int i = pc.rows[k];
-    f(i, j0, (size_t)i * pc.n + j0, full);
+// This thread's place in the vector kernels: workgroup -> (aggregate a,
+// range group g, row split s); lane -> range q of the group and the first
+// of its VEC columns, j0. The coarse unknown of the lane is a kc + g rg + q
+// (valid when that range exists).
+template <typename T>
+struct PcLoc {
+  int a, g, s, q, j0, k;
+  bool valid;
+  __device__ explicit PcLoc(const PcDev& pc) {
+    constexpr int VEC = 16 / (int)sizeof(T);
+    constexpr int RG = pc_rg<T>();
+    const int wg = blockIdx.x;
+    s = wg % pc.split;
+    const int ag = wg / pc.split;
+    a = ag / pc.ng;
+    g = ag - a * pc.ng;
+    const int lane = threadIdx.x & (kWave - 1);
+    q = lane * VEC / kPcCols;
+    j0 = g * RG * kPcCols + lane * VEC;
+    valid = g * RG + q < pc.kc;
+    k = a * pc.kc + g * RG + q;
   }
+};
+
+// Walks this workgroup's rows of its aggregate, one row segment (a wave's
+// rg ranges, VEC consecutive columns per lane) per wave at a time:
+// f(i, j0, e0, full) with e0 = i n + j0; full: all VEC columns exist and
+// 16-byte vector access is allowed (n a multiple of VEC), else the caller
+// handles the columns j0 + v < n one by one.
+template <typename T, class F>
+__device__ __forceinline__ void pc_walk(const PcDev& pc, const PcLoc<T>& L, F&& f) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int WPG = kThreads / kWave;
+  if (L.j0 >= pc.n) return;
+  const bool full = (pc.n % VEC) == 0;
+  const int w = threadIdx.x / kWave;
+  const int r0 = pc.rptr[L.a], r1 = pc.rptr[L.a + 1];
+  const int step = WPG * pc.split;
+  // two row segments per wave and step, so two loads per lane are in flight
+  int k = r0 + L.s * WPG + w;
+  for (; k + step < r1; k += 2 * step) {
+    const int i = pc.rows[k], i2 = pc.rows[k + step];
+    f(i, L.j0, (size_t)i * pc.n + L.j0, full);
+    f(i2, L.j0, (size_t)i2 * pc.n + L.j0, full);
+  }
+  if (k < r1) {
+    const int i = pc.rows[k];
+    f(i, L.j0, (size_t)i * pc.n + L.j0, full);
+  }
+}
+
+// The partials of a vector workgroup: the lane's range sum in slot q, then
+// <r, r> and <r, D^-1 r>.
+template <typename T>
+__device__ __forceinline__ void pc_partials(const PcDev& pc, int q, double wsum, double rr,
+                                            double rz) {
+  constexpr int RG = pc_rg<T>();
+  double acc[RG + 2];
+#pragma unroll
+  for (int k = 0; k < RG; ++k) acc[k] = k == q ? wsum : 0.0;
+  acc[RG] = rr;
+  acc[RG + 1] = rz;
+  block_partials<RG + 2>(acc, pc.tp);
 }
 
 // Start of a preconditioned solve (and of every segment after a residual
@@ -95,7 +161,8 @@ k_pcg_start(const T* __restrict__ r, PcDev pc, const CgScal* sc) {
     acc[1] += (double)rv * (double)rv;
     acc[2] += (double)rv * (double)pc_dinv<T>(pc, i, j, rv);
   };
-  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool full) {
+  const PcLoc<T> L(pc);
+  pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool full) {
     if (full) {
       T rv[VEC];
       vld<T, VEC>(r + e0, rv);
@@ -105,7 +172,7 @@ k_pcg_start(const T* __restrict__ r, PcDev pc, const CgScal* sc) {
       for (int v = 0; v < VEC && j0 + v < pc.n; ++v) add(i, j0 + v, r[e0 + v]);
     }
   });
-  block_partials<3>(acc, pc.tp);
+  pc_partials<T>(pc, L.q, acc[0], acc[1], acc[2]);
 }
 
 // r -= alpha q with alpha = rho / <p, q> (rho = <r, z> of this iteration,
@@ -142,7 +209,8 @@ k_pcg_update(T* __restrict__ r, const T* __restrict__ q, CgScal* sc, int it,
     acc[1] += (double)rv * (double)rv;
     acc[2] += (double)rv * (double)pc_dinv<T>(pc, i, j, rv);
   };
-  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool full) {
+  const PcLoc<T> L(pc);
+  pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool full) {
     if (full) {
       T rv[VEC], qv[VEC];
       vld<T, VEC>(r + e0, rv);
@@ -161,7 +229,17 @@ k_pcg_update(T* __restrict__ r, const T* __restrict__ q, CgScal* sc, int it,
       }
     }
   });
-  block_partials<3>(acc, pc.tp);
+  pc_partials<T>(pc, L.q, acc[0], acc[1], acc[2]);
+}
+
+// W = Z^T r from the vector workgroups' partials (one thread per coarse
+// unknown; `it` < 0: the start of a solve or segment).
+__global__ void __launch_bounds__(kThreads)
+k_pcg_wsum(PcDev pc, const CgScal* sc, int it) {
+  if (sc->done != 0) return;
+  if (it < 0 ? sc->conv_it != 0 : sc->conv_it != 0 && sc->conv_it <= it) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < pc.K) pc.W[k] = pc_w(pc, k);
 }
 
 // C = E^-1 W, one wave per row; partials of <W, C> per workgroup. `it` < 0:
@@ -175,12 +253,21 @@ k_pcg_coarse(PcDev pc, const CgScal* sc, int it) {
   const int row = blockIdx.x * kPcCoarseRows + w;
   double wc = 0.0;
   if (row < pc.K) {
-    const double* e = pc.Einv + (size_t)row * pc.K;
+    const float* e = pc.Einv + (size_t)row * pc.K;
     double s = 0.0;
-    for (int k = lane; k < pc.K; k += kWave) s += e[k] * pc.tp[3 * k];
+    const double* W = pc.W;
+    if ((pc.K & 3) == 0) {  // rows 16-byte aligned: four values per lane and load
+      for (int k = 4 * lane; k < pc.K; k += 4 * kWave) {
+        const float4 v = *reinterpret_cast<const float4*>(e + k);
+        s += (double)v.x * W[k] + (double)v.y * W[k + 1] + (double)v.z * W[k + 2] +
+             (double)v.w * W[k + 3];
+      }
+    } else {
+      for (int k = lane; k < pc.K; k += kWave) s += (double)e[k] * W[k];
+    }
     s = wave_sum(s);
     if (lane == 0) pc.C[row] = s;
-    wc = s * pc.tp[3 * row];
+    wc = s * W[row];
   }
   if (lane == 0) red[w] = wc;
   __syncthreads();
@@ -201,9 +288,10 @@ k_pcg_scalars(PcDev pc, CgScal* sc, int it, int ncw) {
   if (it < 0 ? sc->conv_it != 0 : sc->conv_it != 0 && sc->conv_it <= it) return;
   __shared__ double red[3][1024 / kWave];
   double a[3] = {0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < pc.K; k += blockDim.x) {
-    a[0] += pc.tp[3 * k + 1];
-    a[1] += pc.tp[3 * k + 2];
+  const int nwg = pc_nwg(pc);
+  for (int k = threadIdx.x; k < nwg; k += blockDim.x) {
+    a[0] += pc.tp[(size_t)k * (pc.rg + 2) + pc.rg];
+    a[1] += pc.tp[(size_t)k * (pc.rg + 2) + pc.rg + 1];
   }
   for (int k = threadIdx.x; k < ncw; k += blockDim.x) a[2] += pc.cpart[k];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -254,8 +342,9 @@ k_pcg_pupdate(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ r, CgS
   if (sc->conv_it != 0 && sc->conv_it <= it) return;
   constexpr int VEC = 16 / (int)sizeof(T);
   const T alpha = (T)sc->alpha, beta = (T)sc->beta;
-  const T c = (T)pc.C[blockIdx.x];
-  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool full) {
+  const PcLoc<T> L(pc);
+  const T c = L.valid ? (T)pc.C[L.k] : T(0);
+  pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool full) {
     if (full) {
       T xv[VEC], pv[VEC], rv[VEC];
       vld<T, VEC>(x + e0, xv);
@@ -285,8 +374,9 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_pcg_setp(T* __restrict__ p, const T* __restrict__ r, const CgScal* sc, PcDev pc) {
   if (sc->done != 0 || sc->conv_it != 0) return;
-  const T c = (T)pc.C[blockIdx.x];
-  pc_tile_walk<T>(pc, blockIdx.x, [&](int i, int j0, size_t e0, bool) {
+  const PcLoc<T> L(pc);
+  const T c = L.valid ? (T)pc.C[L.k] : T(0);
+  pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool) {
     for (int v = 0; v < 16 / (int)sizeof(T) && j0 + v < pc.n; ++v)
       p[e0 + v] = c + pc_dinv<T>(pc, i, j0 + v, r[e0 + v]);
   });
@@ -349,16 +439,13 @@ k_gj_step(double* __restrict__ A, int K, int k, const double* __restrict__ colk,
   A[e] = v;
 }
 
-// A = (A + A^T) / 2.
+// B = (A + A^T) / 2 rounded to FP32 (the inverse the iterations use).
 __global__ void __launch_bounds__(kThreads)
-k_symmetrize(double* __restrict__ A, int K) {
+k_symmetrize_f32(const double* __restrict__ A, int K, float* __restrict__ B) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)K * K) return;
   const int i = (int)(e / K), j = (int)(e % K);
-  if (j <= i) return;
-  const double v = 0.5 * (A[e] + A[(size_t)j * K + i]);
-  A[e] = v;
-  A[(size_t)j * K + i] = v;
+  B[e] = (float)(0.5 * (A[e] + A[(size_t)j * K + i]));
 }
 
 }  // namespace cpca
