@@ -119,10 +119,29 @@ def oracle_sample_error(workload, X):
     return float(np.linalg.norm(got - g["vals"]) / np.linalg.norm(g["vals"]))
 
 
-def cpu_baseline(P, J, tol, gpu_fp64_iters, max_seconds=25.0):
+def plain_cg_iterations(Xt, om_r, om_c, P, Lr, Lc, tol):
+    """Iterations plain (unpreconditioned) FP64 CG from zero needs to reach
+    `tol` on this system: the oracle's CG, whose time is extrapolated, is
+    plain CG with the same stopping rule. Counted by one plain FP64 solve on
+    the GPU, outside the timed region."""
+    import paper_1602_02070_amd as cp
+    old = os.environ.get("CPCA_PRECOND")
+    os.environ["CPCA_PRECOND"] = "0"
+    try:
+        _, info = cp.decode(Xt.double(), om_r, om_c, P.p, P.n, Lr, Lc, P.gamma_r, P.gamma_c,
+                            tol=tol, max_iter=50000, mode="fp64")
+    finally:
+        if old is None:
+            del os.environ["CPCA_PRECOND"]
+        else:
+            os.environ["CPCA_PRECOND"] = old
+    return info["iters"]
+
+
+def cpu_baseline(P, J, tol, plain_iters, max_seconds=25.0):
     """Time the oracle on a bounded sample: the whole FISTA on Y~ plus a few
-    CG iterations of the full-size decoder, extrapolated to the number of CG
-    iterations the plain-FP64 solve needs."""
+    CG iterations of the full-size decoder, extrapolated to the number of
+    iterations plain CG needs at this tolerance."""
     from threadpoolctl import threadpool_limits
 
     from oracle import decoder as OD
@@ -143,13 +162,14 @@ def cpu_baseline(P, J, tol, gpu_fp64_iters, max_seconds=25.0):
     t0 = time.perf_counter()
     OD.solve_cg(B, m_r, m_c, P.Lr, P.Lc, P.gamma_r, P.gamma_c, tol=tol, max_iter=k)
     t_it = (time.perf_counter() - t0) / k
-    total = t_fista + t_it * gpu_fp64_iters
+    total = t_fista + t_it * plain_iters
     limiter.unregister()
     return {"value": P.p * P.n / total, "unit": "entries/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle: FISTA {J} it on Y~ {P.rho_r}x{P.rho_c} timed whole "
                        f"({t_fista:.2f} s); decoder CG timed for {k} iterations at full size "
-                       f"({t_it:.3f} s/it) and extrapolated to the {gpu_fp64_iters} iterations "
-                       f"of the plain-FP64 GPU solve; est. {total:.1f} s per step")}
+                       f"({t_it:.3f} s/it) and extrapolated to the {plain_iters} iterations "
+                       f"plain CG needs to reach tol {tol:g} (counted by a plain FP64 CG solve "
+                       f"on the GPU); est. {total:.1f} s per step")}
 
 
 def batch_cpu_baseline(probs, tasks, iters, J, tol, max_seconds=25.0):
@@ -752,9 +772,11 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": bytes_apply},
         "extra": extra,
     }
-    if not args.no_cpu_baseline and fp64_iters is not None:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(P, J, tol, fp64_iters)
+    if not args.no_cpu_baseline:
+        plain = plain_cg_iterations(infos["Xt"], om_r, om_c, P, Lr, Lc, tol)
+        log(f"[bench] plain FP64 CG needs {plain} iterations at tol {tol:g}; "
+            "timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(P, J, tol, plain)
     print(json.dumps(line), flush=True)
     return 1 if failed else 0
 

@@ -1,5 +1,6 @@
 """The decoder's two-level preconditioned CG (aggregation coarse space,
-pcg.hpp) against the FP64 oracle and against plain CG (CPCA_PRECOND=0).
+pcg.hpp; forced on at every size here with CPCA_PRECOND=1) against the FP64
+oracle and against plain CG (CPCA_PRECOND=0).
 
 Both reach the unique solution of the decoder's normal equations, so both are
 held to the oracle at the same tolerance; the preconditioned solve must need
@@ -22,9 +23,9 @@ pytestmark = pytest.mark.gpu
 
 
 @contextlib.contextmanager
-def plain_cg():
+def precond(value):
     old = os.environ.get("CPCA_PRECOND")
-    os.environ["CPCA_PRECOND"] = "0"
+    os.environ["CPCA_PRECOND"] = value
     try:
         yield
     finally:
@@ -32,6 +33,18 @@ def plain_cg():
             del os.environ["CPCA_PRECOND"]
         else:
             os.environ["CPCA_PRECOND"] = old
+
+
+def plain_cg():
+    return precond("0")
+
+
+@pytest.fixture(autouse=True)
+def preconditioned_at_every_size():
+    # these problems are smaller than the default threshold of the coarse
+    # level (2^20 entries): force it on, plain CG is asked for explicitly
+    with precond("1"):
+        yield
 
 
 def _solve(P, d, Xtil, gam, mode, tol):
