@@ -487,8 +487,14 @@ PcLayout pc_layout(char* base, const PcHost& ph, size_t* bytes) {
   const size_t K = (size_t)ph.K;
   L.E = a.take<double>(K * K);
   L.Einv = a.take<float>(K * K);
-  // vector workgroups: kr ceil(kc / rg) split <= kr (kc / 2 + 1) 8, rg + 2 <= 6 partials each
-  L.tp = a.take<double>(((size_t)ph.kr * (ph.kc / 2 + 1) * 8) * 6);
+  // vector workgroups kr ceil(kc / rg) split (split <= 8), rg + 2 partials each,
+  // for the larger of the FP32 and FP64 range groups
+  size_t tpn = 0;
+  for (size_t elem : {sizeof(float), sizeof(double)}) {
+    const size_t rg = (size_t)kWave * (16 / elem) / kPcCols;
+    tpn = std::max(tpn, (size_t)ph.kr * ((ph.kc + rg - 1) / rg) * 8 * (rg + 2));
+  }
+  L.tp = a.take<double>(tpn);
   L.W = a.take<double>(K);
   L.C = a.take<double>(K);
   L.cpart = a.take<double>(K / kPcCoarseRows + 1);
@@ -605,7 +611,7 @@ PcDev pc_bind(cpca_handle h, double gr, double gc, int64_t p, int64_t n, size_t 
   d.K = ph.K;
   d.p = (int)p;
   d.n = (int)n;
-  d.rg = (int)(16 / elem);
+  d.rg = (int)(kWave * (16 / elem) / kPcCols);  // as pc_rg<T>() on the device
   d.ng = (ph.kc + d.rg - 1) / d.rg;
   // enough vector workgroups (about 4096) to keep many row segments in flight
   d.split = std::max(1, std::min(8, (4096 + ph.kr * d.ng - 1) / (ph.kr * d.ng)));

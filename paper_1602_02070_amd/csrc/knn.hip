@@ -44,7 +44,8 @@ constexpr int kKnnThreads = 512;
 constexpr int kSlab = 64;       // candidates per selection slab
 constexpr int kDK = 16;         // coordinates per staged chunk
 constexpr int kDKP = kDK + 1;   // LDS row stride of the staged chunks (doubles)
-constexpr int kDTP = kSlab + 1; // LDS row stride of the distance slab
+constexpr int kDS = 32;         // candidates per distance slab (selection pass)
+constexpr int kDTP = kDS + 1;   // LDS row stride of the distance slab
 constexpr int kMaxSeg = 8;      // most candidate segments per query block
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -127,8 +128,10 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
             int tiles_per_seg, int nseg, int* __restrict__ seg_idx, double* __restrict__ seg_d2) {
   constexpr int kCT = kSlab * NS;  // candidates per tile
   static_assert(kCT % kQT == 0, "the candidate tile is staged in rows of kQT");
-  __shared__ double Qs[kQT * kDKP];
-  __shared__ double Cs[kCT * kDKP];
+  // staged chunks, double-buffered: chunk i is computed from one buffer while
+  // chunk i + 1 is stored into the other, one barrier per chunk
+  __shared__ double Qs[2][kQT * kDKP];
+  __shared__ double Cs[2][kCT * kDKP];
   __shared__ double Ds[kQT * kDTP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -202,32 +205,40 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
   d4 acc[4 * NS];
 #pragma unroll
   for (int t = 0; t < 4 * NS; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  int c0 = cbeg, k0 = 0;
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      Qs[buf][r_st * kDKP + cc_st + u] = qr[u];
+#pragma unroll
+      for (int j = 0; j < CG; ++j) Cs[buf][(r_st + kQT * j) * kDKP + cc_st + u] = cr[j][u];
+    }
+  };
+  // the chunk after (c, k): the next 16 coordinates, or the next tile
+  auto advance = [&](int c, int k, int& nc, int& nk) {
+    nk = k + kDK;
+    nc = c;
+    if (nk >= d4pad) {
+      nk = 0;
+      nc = c + kCT;
+    }
+  };
+  int c0 = cbeg, k0 = 0, cur = 0, nc0 = cend, nk0 = 0;
   if (c0 < cend) {
     set_rows(c0);
     load_chunk(0);
-  }
-  while (c0 < cend) {
-    // stage the coordinates of the queries and of the candidates
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      Qs[r_st * kDKP + cc_st + u] = qr[u];
-#pragma unroll
-      for (int j = 0; j < CG; ++j) Cs[(r_st + kQT * j) * kDKP + cc_st + u] = cr[j][u];
-    }
-    __syncthreads();
-    int nk0 = k0 + kDK, nc0 = c0;
-    if (nk0 >= d4pad) {
-      nk0 = 0;
-      nc0 = c0 + kCT;
-    }
+    store_chunk(0);
+    advance(c0, k0, nc0, nk0);
     if (nc0 < cend) {
       if (nc0 != c0) set_rows(nc0);
       load_chunk(nk0);
     }
+  }
+  __syncthreads();
+  while (c0 < cend) {
+    // buffer cur holds chunk (c0, k0); the registers hold chunk (nc0, nk0)
     // A: row lane % 16, k = lane / 16 of the 16 x 4 block; B likewise
-    const double* qa = &Qs[(16 * wid + (lane & 15)) * kDKP + (lane >> 4)];
-    const double* cb = &Cs[(lane & 15) * kDKP + (lane >> 4)];
+    const double* qa = &Qs[cur][(16 * wid + (lane & 15)) * kDKP + (lane >> 4)];
+    const double* cb = &Cs[cur][(lane & 15) * kDKP + (lane >> 4)];
     auto kstep = [&](int s) {
       const double a = qa[4 * s];
 #pragma unroll
@@ -241,18 +252,21 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
     const int ksteps = min(kDK, d4pad - k0) >> 2;
 #pragma unroll 1
     for (int s = 0; s < ksteps; ++s) kstep(s);
+    // the other buffer was last read by the previous chunk, before the
+    // barrier every wave has passed since
+    if (nc0 < cend) store_chunk(cur ^ 1);
     __syncthreads();
     if (nk0 == 0) {
       // tile complete: slab by slab, the approximate squared distances go to
       // the distance slab (output row (lane / 16) + 4 v, column lane % 16 of
       // each 16 x 16 block) and are scanned by the selection threads
 #pragma unroll
-      for (int sl = 0; sl < NS; ++sl) {
+      for (int sl = 0; sl < kCT / kDS; ++sl) {
 #pragma unroll
-        for (int t4 = 0; t4 < 4; ++t4) {
-          const int t = 4 * sl + t4;
-          const int cl = 16 * t4 + (lane & 15);
-          const int c = c0 + kSlab * sl + cl;
+        for (int t2 = 0; t2 < kDS / 16; ++t2) {
+          const int t = (kDS / 16) * sl + t2;
+          const int cl = 16 * t2 + (lane & 15);
+          const int c = c0 + kDS * sl + cl;
           const double sqc = c < cend ? sq[c] : 0.0;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -265,18 +279,27 @@ k_knn_tiles(const double* __restrict__ Y, const double* __restrict__ sq, int N, 
           acc[t] = d4{0.0, 0.0, 0.0, 0.0};
         }
         __syncthreads();
-        // selection: this thread's 16 candidates of the slab, in increasing index
-#pragma unroll 4
-        for (int m = 0; m < 16; ++m) {
-          const int cl = 16 * sub + m;
+        // selection: this thread's kDS / 4 candidates of the slab, in
+        // increasing index
+#pragma unroll
+        for (int m = 0; m < kDS / 4; ++m) {
+          const int cl = (kDS / 4) * sub + m;
           const double x = Ds[qs * kDTP + cl];
-          if (x < vd[CAP - 1]) list_insert<CAP>(vd, vi, x, c0 + kSlab * sl + cl);
+          if (x < vd[CAP - 1]) list_insert<CAP>(vd, vi, x, c0 + kDS * sl + cl);
         }
         __syncthreads();
       }
     }
     c0 = nc0;
     k0 = nk0;
+    cur ^= 1;
+    if (c0 < cend) {
+      advance(c0, k0, nc0, nk0);
+      if (nc0 < cend) {
+        if (nc0 != c0) set_rows(nc0);
+        load_chunk(nk0);
+      }
+    }
   }
   // merge the four quarter lists of each query (lanes 4 qs .. 4 qs + 3 of
   // the wave) into the first one by (approximate distance, index)

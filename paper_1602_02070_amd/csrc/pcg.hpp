@@ -60,6 +60,8 @@ struct PcDev {
 // Vector workgroups of a solve in element type T.
 template <typename T>
 constexpr int pc_rg() { return kWave * (16 / (int)sizeof(T)) / kPcCols; }
+static_assert(kWave * 2 % kPcCols == 0 && kPcCols % 4 == 0,
+              "a wave's row segment must hold whole column ranges in FP32 and FP64");
 __host__ __device__ inline int pc_nwg(const PcDev& pc) { return pc.kr * pc.ng * pc.split; }
 
 // Tile sum W_k of coarse unknown k = a kc + b from the partials.
