@@ -217,6 +217,14 @@ cpca_status cpca_kron_reduce(cpca_handle h, const cpca_csr* L, const int32_t* om
  *   (m_r m_c^T) o X + gamma_r L_r X + gamma_c X L_c = M_r^T X~ M_c^T,
  *
  * where m_r / m_c are the 0/1 indicators of Omega_r / Omega_c.
+ * From 2^20 entries on (environment CPCA_PRECOND=1: at every size, =0:
+ * never) CG is preconditioned by a two-level aggregation coarse space (row
+ * aggregates of L_r times ranges of 64 columns; the coarse operator is built
+ * and inverted on the device on the first call for an operator and gamma
+ * pair, then reused). The solution is the same; info.iters counts the
+ * preconditioned iterations. Operators that are singular (a gamma of 0, a
+ * connected component of either graph without a sampled node) are solved by
+ * plain CG.
  * Xtil        rho_r x rho_c (row a, column b belongs at (omega_r[a], omega_c[b])).
  * omega_r/_c  rho_r / rho_c distinct int32 indices in [0, p) / [0, n).
  * Lr, Lc      p x p and n x n Laplacians; gamma_r/_c >= 0 and finite.

@@ -476,7 +476,7 @@ cpca_status decode_operator(cpca_handle h, cpca_mode mode, const cpca_csr* Lr, c
 // K / 4 + 1, pivot row and column 2K, the aggregated operators kr^2 + kc^2,
 // counts and sizes 2 kr + 2 kc, a flag.
 struct PcLayout {
-  double *E, *tp, *W, *C, *cpart, *colk, *rowk, *Lra, *Lca, *sr, *scn, *wr, *wc;
+  double *E, *tp, *W, *C, *cpart, *colk, *rowk, *trow, *dinv, *Lra, *Lca, *sr, *scn, *wr, *wc;
   float* Einv;
   int* flag;
 };
@@ -498,8 +498,10 @@ PcLayout pc_layout(char* base, const PcHost& ph, size_t* bytes) {
   L.W = a.take<double>(K);
   L.C = a.take<double>(K);
   L.cpart = a.take<double>(K / kPcCoarseRows + 1);
-  L.colk = a.take<double>(K);
-  L.rowk = a.take<double>(K);
+  L.colk = a.take<double>(K * kGjB);  // block column, then D^-1 and T'
+  L.rowk = a.take<double>(K * kGjB);  // block row
+  L.trow = a.take<double>(K * kGjB);
+  L.dinv = a.take<double>(kGjB * kGjB);
   L.Lra = a.take<double>((size_t)ph.kr * ph.kr);
   L.Lca = a.take<double>((size_t)ph.kc * ph.kc);
   L.sr = a.take<double>(ph.kr);
@@ -526,7 +528,8 @@ bool pc_enabled(int64_t entries) {
 }
 
 // The coarse inverse for (gr, gc): assembled and inverted on the device
-// (Gauss-Jordan, K steps), kept while the operator and the gammas stay. A
+// (blocked Gauss-Jordan, K / kGjB block steps), kept while the operator and
+// the gammas stay. A
 // non-positive pivot (E not positive definite: a singular decoder, e.g. a
 // gamma of 0) drops the coarse level for these gammas: the solve runs plain CG.
 cpca_status pc_prepare(cpca_handle h, double gr, double gc, int64_t entries, bool* usable) {
@@ -538,6 +541,7 @@ cpca_status pc_prepare(cpca_handle h, double gr, double gc, int64_t entries, boo
     return CPCA_OK;
   }
   TraceRange trace_("decode: coarse operator");
+  const auto t0 = std::chrono::steady_clock::now();
   const PcHost& ph = dc.pc;
   size_t bytes = 0;
   (void)pc_layout(nullptr, ph, &bytes);
@@ -563,13 +567,18 @@ cpca_status pc_prepare(cpca_handle h, double gr, double gc, int64_t entries, boo
   LAUNCHCHK();
   const int K = ph.K;
   const size_t KK = (size_t)K * K;
-  const int g2 = (int)((KK + kThreads - 1) / kThreads), g1 = (K + kThreads - 1) / kThreads;
+  const int g2 = (int)((KK + kThreads - 1) / kThreads);
   PcCoarseDev cd{L.Lra, L.Lca, L.sr, L.scn, L.wr, L.wc, ph.kr, ph.kc, K};
   k_pc_assemble<<<g2, kThreads, 0, h->stream>>>(cd, gr, gc, L.E);
   LAUNCHCHK();
-  for (int k = 0; k < K; ++k) {
-    k_gj_save<<<g1, kThreads, 0, h->stream>>>(L.E, K, k, L.colk, L.rowk);
-    k_gj_step<<<g2, kThreads, 0, h->stream>>>(L.E, K, k, L.colk, L.rowk, L.flag);
+  const int gb = (int)(((size_t)K * kGjB + kThreads - 1) / kThreads);
+  const int nt = (K + kGjT - 1) / kGjT;
+  for (int kb = 0; kb < K; kb += kGjB) {
+    const int bb = std::min(kGjB, K - kb);
+    k_gj_save<<<gb, kThreads, 0, h->stream>>>(L.E, K, kb, bb, L.colk, L.rowk);
+    k_gj_diag<<<1, kThreads, 0, h->stream>>>(L.rowk, K, kb, bb, L.dinv, L.flag);
+    k_gj_trow<<<gb, kThreads, 0, h->stream>>>(L.rowk, L.dinv, K, kb, bb, L.trow);
+    k_gj_update<<<nt * nt, kThreads, 0, h->stream>>>(L.E, K, kb, bb, L.colk, L.trow, L.flag);
   }
   LAUNCHCHK();
   k_symmetrize_f32<<<g2, kThreads, 0, h->stream>>>(L.E, K, L.Einv);
@@ -582,7 +591,9 @@ cpca_status pc_prepare(cpca_handle h, double gr, double gc, int64_t entries, boo
   dc.pc_gr = gr;
   dc.pc_gc = gc;
   if (h->debug)
-    std::fprintf(stderr, "[cpca] coarse operator: %d x %d aggregates, K = %d%s\n", ph.kr, ph.kc, K,
+    std::fprintf(stderr, "[cpca] coarse operator: %d x %d aggregates, K = %d, %.1f ms%s\n", ph.kr,
+                 ph.kc, K,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
                  dc.pc_bad ? " (not positive definite: plain CG)" : "");
   *usable = !dc.pc_bad;
   return CPCA_OK;

@@ -409,36 +409,139 @@ k_pc_assemble(PcCoarseDev cd, double gr, double gc, double* __restrict__ E) {
   E[e] = v;
 }
 
-// Gauss-Jordan inversion in place, step k: the pivot row and column are
-// saved first (k_gj_save), then every element is updated from the saved
-// copies (k_gj_step). E is symmetric positive definite, so the pivots are
-// positive and no pivoting is needed.
+// Blocked Gauss-Jordan inversion in place (E is symmetric positive
+// definite: no pivoting). Block step kb, with bb = min(kGjB, K - kb) pivots:
+// the block column Ccol = A(:, kb..) and block row Rrow = A(kb.., :) are
+// saved (k_gj_save); one workgroup inverts the diagonal block D (k_gj_diag);
+// T' = D^-1 Rrow outside the block and D^-1 inside it (k_gj_trow); then
+//   rows of the block:      A(kb + l, j) = T'(l, j)
+//   other rows, block cols: A(i, j) = -(Ccol T')(i, j)
+//   other rows and cols:    A(i, j) -= (Ccol T')(i, j)
+// (k_gj_update, 64 x 64 tiles, each thread 4 x 4 outputs). This is the
+// scalar step A -= A(:, k) A(k, :) / A(k, k) applied to kGjB pivots at once.
+constexpr int kGjB = 32;
+constexpr int kGjT = 64;   // output tile of k_gj_update
+
 __global__ void __launch_bounds__(kThreads)
-k_gj_save(const double* __restrict__ A, int K, int k, double* __restrict__ colk,
-          double* __restrict__ rowk) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K) return;
-  colk[i] = A[(size_t)i * K + k];
-  rowk[i] = A[(size_t)k * K + i];
+k_gj_save(const double* __restrict__ A, int K, int kb, int bb, double* __restrict__ Ccol,
+          double* __restrict__ Rrow) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)K * kGjB) return;
+  const int i = (int)(e / kGjB), l = (int)(e % kGjB);
+  Ccol[e] = l < bb ? A[(size_t)i * K + kb + l] : 0.0;                  // K x kGjB
+  Rrow[(size_t)l * K + i] = l < bb ? A[(size_t)(kb + l) * K + i] : 0.0;  // kGjB x K
+}
+
+// One workgroup: D^-1 of the bb x bb diagonal block (from Rrow) by scalar
+// Gauss-Jordan in LDS; a non-positive pivot sets *bad.
+__global__ void __launch_bounds__(kThreads)
+k_gj_diag(const double* __restrict__ Rrow, int K, int kb, int bb, double* __restrict__ Dinv,
+          int* __restrict__ bad) {
+  __shared__ double D[kGjB][kGjB + 1];
+  __shared__ double col[kGjB], row[kGjB];
+  for (int e = threadIdx.x; e < kGjB * kGjB; e += blockDim.x) {
+    const int l = e / kGjB, m = e % kGjB;
+    D[l][m] = (l < bb && m < bb) ? Rrow[(size_t)l * K + kb + m] : (l == m ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < bb; ++k) {
+    if (threadIdx.x < kGjB) {
+      col[threadIdx.x] = D[threadIdx.x][k];
+      row[threadIdx.x] = D[k][threadIdx.x];
+    }
+    __syncthreads();
+    const double piv = row[k];
+    if (!(piv > 0.0)) {
+      if (threadIdx.x == 0) *bad = 1;
+      return;  // uniform: every thread read the same pivot
+    }
+    const double pinv = 1.0 / piv;
+    for (int e = threadIdx.x; e < kGjB * kGjB; e += blockDim.x) {
+      const int l = e / kGjB, m = e % kGjB;
+      double v;
+      if (l == k && m == k) v = pinv;
+      else if (l == k) v = row[m] * pinv;
+      else if (m == k) v = -col[l] * pinv;
+      else v = D[l][m] - col[l] * row[m] * pinv;
+      D[l][m] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kGjB * kGjB; e += blockDim.x) {
+    const int l = e / kGjB, m = e % kGjB;
+    Dinv[e] = (l < bb && m < bb) ? D[l][m] : 0.0;
+  }
+}
+
+// T'(l, j) = (D^-1 Rrow)(l, j) for columns outside the block, D^-1(l, j - kb)
+// inside it (kGjB x K).
+__global__ void __launch_bounds__(kThreads)
+k_gj_trow(const double* __restrict__ Rrow, const double* __restrict__ Dinv, int K, int kb,
+          int bb, double* __restrict__ T) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)K * kGjB) return;
+  const int l = (int)(e / K), j = (int)(e % K);
+  double v = 0.0;
+  if (l < bb) {
+    if (j >= kb && j < kb + bb) {
+      v = Dinv[l * kGjB + (j - kb)];
+    } else {
+      for (int m = 0; m < bb; ++m) v += Dinv[l * kGjB + m] * Rrow[(size_t)m * K + j];
+    }
+  }
+  T[e] = v;
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_gj_step(double* __restrict__ A, int K, int k, const double* __restrict__ colk,
-          const double* __restrict__ rowk, int* __restrict__ bad_pivot) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (size_t)K * K) return;
-  const int i = (int)(e / K), j = (int)(e % K);
-  if (!(rowk[k] > 0.0)) {  // not positive definite: the caller drops the coarse level
-    if (e == 0) *bad_pivot = 1;
-    return;
+k_gj_update(double* __restrict__ A, int K, int kb, int bb, const double* __restrict__ Ccol,
+            const double* __restrict__ T, const int* __restrict__ bad) {
+  __shared__ double Cs[kGjT][kGjB + 1];
+  __shared__ double Ts[kGjB][kGjT + 1];
+  if (*bad) return;
+  const int ntj = (K + kGjT - 1) / kGjT;
+  const int i0 = (blockIdx.x / ntj) * kGjT, j0 = (blockIdx.x % ntj) * kGjT;
+  for (int e = threadIdx.x; e < kGjT * kGjB; e += blockDim.x) {
+    const int r = e / kGjB, l = e % kGjB;
+    Cs[r][l] = i0 + r < K ? Ccol[(size_t)(i0 + r) * kGjB + l] : 0.0;
+    const int l2 = e / kGjT, c = e % kGjT;
+    Ts[l2][c] = j0 + c < K ? T[(size_t)l2 * K + j0 + c] : 0.0;
   }
-  const double pinv = 1.0 / rowk[k];
-  double v;
-  if (i == k && j == k) v = pinv;
-  else if (i == k) v = rowk[j] * pinv;
-  else if (j == k) v = -colk[i] * pinv;
-  else v = A[e] - colk[i] * rowk[j] * pinv;
-  A[e] = v;
+  __syncthreads();
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int l = 0; l < kGjB; ++l) {
+    double ca[4], tb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ca[a] = Cs[ty * 4 + a][l];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) tb[b] = Ts[l][tx * 4 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += ca[a] * tb[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + ty * 4 + a;
+    if (i >= K) continue;
+    const bool irow = i >= kb && i < kb + bb;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + tx * 4 + b;
+      if (j >= K) continue;
+      const size_t e = (size_t)i * K + j;
+      if (irow) {
+        A[e] = Ts[i - kb][tx * 4 + b];
+      } else {
+        const bool jcol = j >= kb && j < kb + bb;
+        A[e] = (jcol ? 0.0 : A[e]) - acc[a][b];
+      }
+    }
+  }
 }
 
 // B = (A + A^T) / 2 rounded to FP32 (the inverse the iterations use).
