@@ -707,6 +707,8 @@ def main(argv=None):
     elapsed = time.perf_counter() - t0
     n_apply, ms_apply = cp.get_profile("apply")
     n_upd, ms_upd = cp.get_profile("update")
+    n_pup, ms_pup = cp.get_profile("pupdate")
+    n_crs, ms_crs = cp.get_profile("coarse")
     n_fista, ms_fista = cp.get_profile("fista")
     cp.profiling(False)
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
@@ -738,6 +740,21 @@ def main(argv=None):
              "apply_ms_avg": avg_apply,
              "update_ms_avg": ms_upd / max(n_work, 1),
              "fista_ms_avg": ms_fista / max(n_fista, 1)}
+    if n_pup and n_work:
+        # every kernel of a preconditioned CG iteration, per working launch
+        # (HIP events on the library stream over the timed region); the
+        # vector kernels stream r and q (update: 12 B per FP32 entry) and
+        # x, p and r (pupdate: 20 B), the coarse level reads E^-1 in FP32
+        entries = P.p * P.n
+        rows = {"product": (avg_apply, bytes_apply),
+                "update": (ms_upd / n_work, 3 * elem * entries),
+                "pupdate": (ms_pup / n_work, 5 * elem * entries),
+                "coarse": (ms_crs / n_work, None)}
+        extra["iteration_kernels"] = {
+            k: {"ms": ms, "algorithmic_bytes": b,
+                "frac_of_hbm_peak": (b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if b else None}
+            for k, (ms, b) in rows.items()}
+        extra["iteration_ms"] = sum(ms for ms, _ in rows.values())
     fp64_iters = None
     if not args.no_fp64_check:
         Xt64 = infos["Xt"].double()

@@ -467,7 +467,10 @@ cpca_status cpca_check_index_set_host(int64_t count, int64_t dim,
  * two-sided sparse product with the CG epilogue), "update" (the CG x/r
  * update), "fista" (the fused FISTA step), "other" (the fused product with
  * any other epilogue: residual, objective, adjoint dots, plain apply),
- * "rankk" (the rank-k output product of cpca_approx_decode).
+ * "rankk" (the rank-k output product of cpca_approx_decode); with the
+ * coarse-level preconditioner "update" is the r update with the coarse
+ * partial sums, "pupdate" the x/p update and "coarse" the three small
+ * coarse-level launches of an iteration, timed as one span.
  * Enabling resets the counters.
  * cpca_get_profile returns the number of timed launches and their summed
  * duration in milliseconds.

@@ -25,7 +25,10 @@ using namespace cpca;
 namespace {
 
 // apply: the CG operator application; other: residual / objective / dot launches
-enum Family { FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_RANKK = 4, FAM_COUNT = 5 };
+enum Family {
+  FAM_APPLY = 0, FAM_UPDATE = 1, FAM_FISTA = 2, FAM_OTHER = 3, FAM_RANKK = 4, FAM_PUPDATE = 5,
+  FAM_COARSE = 6, FAM_COUNT = 7
+};
 
 }  // namespace
 

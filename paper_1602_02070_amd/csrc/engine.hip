@@ -675,11 +675,17 @@ cpca_status pcg_iterate(cpca_handle h, const Operator<T>& op, const PcDev& pc, T
       k_pcg_update<T><<<pc_nwg(pc), kThreads, 0, h->stream>>>(r, q, sc, it, part.a, ag, pc);
       LAUNCHCHK();
       STCHK(prof_end(h));
+      // the three coarse-level launches are timed as one span
+      STCHK(prof_begin(h, FAM_COARSE));
       k_pcg_wsum<<<gw, kThreads, 0, h->stream>>>(pc, sc, it);
       k_pcg_coarse<<<ncw, kThreads, 0, h->stream>>>(pc, sc, it);
       k_pcg_scalars<<<1, 1024, 0, h->stream>>>(pc, sc, it, ncw);
+      LAUNCHCHK();
+      STCHK(prof_end(h));
+      STCHK(prof_begin(h, FAM_PUPDATE));
       k_pcg_pupdate<T><<<pc_nwg(pc), kThreads, 0, h->stream>>>(x, pv, r, sc, it, pc);
       LAUNCHCHK();
+      STCHK(prof_end(h));
     }
     STCHK(read_fixed(h));
     STCHK(prof_collect(h));
@@ -1263,6 +1269,8 @@ extern "C" cpca_status cpca_get_profile(cpca_handle h, const char* family, int64
   if (!std::strcmp(family, "fista")) k = FAM_FISTA;
   if (!std::strcmp(family, "other")) k = FAM_OTHER;
   if (!std::strcmp(family, "rankk")) k = FAM_RANKK;
+  if (!std::strcmp(family, "pupdate")) k = FAM_PUPDATE;
+  if (!std::strcmp(family, "coarse")) k = FAM_COARSE;
   if (k < 0) return fail(CPCA_EINVAL, "unknown kernel family");
   if (launches) *launches = h->prof_n[k];
   if (total_ms) *total_ms = h->prof_ms[k];

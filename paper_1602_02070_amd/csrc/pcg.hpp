@@ -77,13 +77,39 @@ __device__ __forceinline__ double pc_w(const PcDev& pc, int k) {
 // Rows of a coarse workgroup (one wave per row of E^-1).
 constexpr int kPcCoarseRows = kThreads / kWave;
 
-// D^-1 v for the diagonal of A at (i, j); a zero diagonal (an isolated,
-// unsampled entry: A is singular there) gives 0, the pseudo-inverse.
+// The Jacobi part of the preconditioner for one lane's VEC consecutive
+// columns j0.. : D^-1 with D(i, j) = m_r(i) m_c(j) + g_r (L_r)_ii + g_c (L_c)_jj,
+// the diagonal of A. It is formed in T (FP32: the hardware reciprocal), since
+// a preconditioner only has to be the same fixed positive diagonal in every
+// application of a solve. The column parts are read once per thread, the row
+// parts once per row segment. A zero diagonal (an isolated, unsampled entry:
+// A is singular there) gives 0, the pseudo-inverse.
 template <typename T>
-__device__ __forceinline__ T pc_dinv(const PcDev& pc, int i, int j, T v) {
-  const double d = (double)(pc.mr[i] & pc.mc[j]) + pc.gr * pc.ldr[i] + pc.gc * pc.ldc[j];
-  return d > 0.0 ? v / (T)d : T(0);
-}
+struct PcJacobi {
+  static constexpr int VEC = 16 / (int)sizeof(T);
+  T cp[VEC];
+  uint32_t mc[VEC];
+  __device__ PcJacobi(const PcDev& pc, int j0) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const bool in = j0 + v < pc.n;
+      cp[v] = in ? (T)(pc.gc * pc.ldc[j0 + v]) : T(0);
+      mc[v] = in ? pc.mc[j0 + v] : 0u;
+    }
+  }
+  __device__ __forceinline__ void row(const PcDev& pc, int i, T (&dinv)[VEC]) const {
+    const T rp = (T)(pc.gr * pc.ldr[i]);
+    const uint32_t m = pc.mr[i];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const T d = (T)(m & mc[v]) + rp + cp[v];
+      if constexpr (sizeof(T) == 4)
+        dinv[v] = d > T(0) ? __builtin_amdgcn_rcpf(d) : T(0);
+      else
+        dinv[v] = d > T(0) ? T(1) / d : T(0);
+    }
+  }
+};
 
 // This thread's place in the vector kernels: workgroup -> (aggregate a,
 // range group g, row split s); lane -> range q of the group and the first
@@ -158,20 +184,23 @@ k_pcg_start(const T* __restrict__ r, PcDev pc, const CgScal* sc) {
   if (sc->done != 0 || sc->conv_it != 0) return;
   constexpr int VEC = 16 / (int)sizeof(T);
   double acc[3] = {0.0, 0.0, 0.0};
-  auto add = [&](int i, int j, T rv) {
+  auto add = [&](T rv, T dv) {
     acc[0] += (double)rv;
     acc[1] += (double)rv * (double)rv;
-    acc[2] += (double)rv * (double)pc_dinv<T>(pc, i, j, rv);
+    acc[2] += (double)rv * (double)(dv * rv);
   };
   const PcLoc<T> L(pc);
+  const PcJacobi<T> J(pc, L.j0);
   pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool full) {
+    T dv[VEC];
+    J.row(pc, i, dv);
     if (full) {
       T rv[VEC];
       vld<T, VEC>(r + e0, rv);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) add(i, j0 + v, rv[v]);
+      for (int v = 0; v < VEC; ++v) add(rv[v], dv[v]);
     } else {
-      for (int v = 0; v < VEC && j0 + v < pc.n; ++v) add(i, j0 + v, r[e0 + v]);
+      for (int v = 0; v < VEC && j0 + v < pc.n; ++v) add(r[e0 + v], dv[v]);
     }
   });
   pc_partials<T>(pc, L.q, acc[0], acc[1], acc[2]);
@@ -206,13 +235,16 @@ k_pcg_update(T* __restrict__ r, const T* __restrict__ q, CgScal* sc, int it,
   }
   const T alpha = (T)alpha_d;
   double acc[3] = {0.0, 0.0, 0.0};
-  auto add = [&](int i, int j, T rv) {
+  auto add = [&](T rv, T dv) {
     acc[0] += (double)rv;
     acc[1] += (double)rv * (double)rv;
-    acc[2] += (double)rv * (double)pc_dinv<T>(pc, i, j, rv);
+    acc[2] += (double)rv * (double)(dv * rv);
   };
   const PcLoc<T> L(pc);
+  const PcJacobi<T> J(pc, L.j0);
   pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool full) {
+    T dv[VEC];
+    J.row(pc, i, dv);
     if (full) {
       T rv[VEC], qv[VEC];
       vld<T, VEC>(r + e0, rv);
@@ -220,14 +252,14 @@ k_pcg_update(T* __restrict__ r, const T* __restrict__ q, CgScal* sc, int it,
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         rv[v] -= alpha * qv[v];
-        add(i, j0 + v, rv[v]);
+        add(rv[v], dv[v]);
       }
       vst<T, VEC>(r + e0, rv);
     } else {
       for (int v = 0; v < VEC && j0 + v < pc.n; ++v) {
         const T rn = r[e0 + v] - alpha * q[e0 + v];
         r[e0 + v] = rn;
-        add(i, j0 + v, rn);
+        add(rn, dv[v]);
       }
     }
   });
@@ -345,8 +377,11 @@ k_pcg_pupdate(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ r, CgS
   constexpr int VEC = 16 / (int)sizeof(T);
   const T alpha = (T)sc->alpha, beta = (T)sc->beta;
   const PcLoc<T> L(pc);
+  const PcJacobi<T> J(pc, L.j0);
   const T c = L.valid ? (T)pc.C[L.k] : T(0);
   pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool full) {
+    T dv[VEC];
+    J.row(pc, i, dv);
     if (full) {
       T xv[VEC], pv[VEC], rv[VEC];
       vld<T, VEC>(x + e0, xv);
@@ -355,7 +390,7 @@ k_pcg_pupdate(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ r, CgS
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         xv[v] += alpha * pv[v];
-        pv[v] = c + pc_dinv<T>(pc, i, j0 + v, rv[v]) + beta * pv[v];
+        pv[v] = c + dv[v] * rv[v] + beta * pv[v];
       }
       vst<T, VEC>(x + e0, xv);
       vst<T, VEC>(p + e0, pv);
@@ -364,7 +399,7 @@ k_pcg_pupdate(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ r, CgS
         const size_t e = e0 + v;
         const T pv = p[e];
         x[e] += alpha * pv;
-        p[e] = c + pc_dinv<T>(pc, i, j0 + v, r[e]) + beta * pv;
+        p[e] = c + dv[v] * r[e] + beta * pv;
       }
     }
   });
@@ -377,10 +412,13 @@ __global__ void __launch_bounds__(kThreads)
 k_pcg_setp(T* __restrict__ p, const T* __restrict__ r, const CgScal* sc, PcDev pc) {
   if (sc->done != 0 || sc->conv_it != 0) return;
   const PcLoc<T> L(pc);
+  const PcJacobi<T> J(pc, L.j0);
   const T c = L.valid ? (T)pc.C[L.k] : T(0);
   pc_walk<T>(pc, L, [&](int i, int j0, size_t e0, bool) {
+    T dv[PcJacobi<T>::VEC];
+    J.row(pc, i, dv);
     for (int v = 0; v < 16 / (int)sizeof(T) && j0 + v < pc.n; ++v)
-      p[e0 + v] = c + pc_dinv<T>(pc, i, j0 + v, r[e0 + v]);
+      p[e0 + v] = c + dv[v] * r[e0 + v];
   });
 }
 
