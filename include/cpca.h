@@ -221,7 +221,7 @@ cpca_status cpca_kron_reduce(cpca_handle h, const cpca_csr* L, const int32_t* om
  * never) CG is preconditioned by a two-level aggregation coarse space (row
  * aggregates of L_r times ranges of 64 columns; the coarse operator is built
  * and inverted on the device on the first call for an operator and gamma
- * pair, then reused). The solution is the same; info.iters counts the
+ * pair, then reused) plus a weighted Jacobi part. The solution is the same; info.iters counts the
  * preconditioned iterations. Operators that are singular (a gamma of 0, a
  * connected component of either graph without a sampled node) are solved by
  * plain CG.

@@ -50,6 +50,7 @@ struct PcDev {
   double* C;             // K coarse coefficients E^-1 W
   double* cpart;         // per coarse workgroup: <W, C>
   double gr, gc;
+  double omega;          // weight of the Jacobi part: M^-1 = Z E^-1 Z^T + omega D^-1
   int kr, kc, K;
   int p, n;
   int rg;                // ranges per group: 4 (FP32) or 2 (FP64)
@@ -78,8 +79,8 @@ __device__ __forceinline__ double pc_w(const PcDev& pc, int k) {
 constexpr int kPcCoarseRows = kThreads / kWave;
 
 // The Jacobi part of the preconditioner for one lane's VEC consecutive
-// columns j0.. : D^-1 with D(i, j) = m_r(i) m_c(j) + g_r (L_r)_ii + g_c (L_c)_jj,
-// the diagonal of A. It is formed in T (FP32: the hardware reciprocal), since
+// columns j0.. : omega D^-1 with D(i, j) = m_r(i) m_c(j) + g_r (L_r)_ii +
+// g_c (L_c)_jj, the diagonal of A (every D^-1 below stands for omega D^-1). It is formed in T (FP32: the hardware reciprocal), since
 // a preconditioner only has to be the same fixed positive diagonal in every
 // application of a solve. The column parts are read once per thread, the row
 // parts once per row segment. A zero diagonal (an isolated, unsampled entry:
@@ -99,14 +100,15 @@ struct PcJacobi {
   }
   __device__ __forceinline__ void row(const PcDev& pc, int i, T (&dinv)[VEC]) const {
     const T rp = (T)(pc.gr * pc.ldr[i]);
+    const T om = (T)pc.omega;
     const uint32_t m = pc.mr[i];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       const T d = (T)(m & mc[v]) + rp + cp[v];
       if constexpr (sizeof(T) == 4)
-        dinv[v] = d > T(0) ? __builtin_amdgcn_rcpf(d) : T(0);
+        dinv[v] = d > T(0) ? om * __builtin_amdgcn_rcpf(d) : T(0);
       else
-        dinv[v] = d > T(0) ? T(1) / d : T(0);
+        dinv[v] = d > T(0) ? om / d : T(0);
     }
   }
 };
