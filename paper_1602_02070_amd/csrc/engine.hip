@@ -873,7 +873,8 @@ cpca_status solve_decode(cpca_handle h, cpca_mode mode, int64_t p, int64_t n,
     // restarting is faster). From then on the solve runs as restarted refinement (p = r
     // at every segment, inner tolerance clamp(0.5 tol / rel, 1e-5, 0.25)),
     // which measured faster there; kMaxBad failed segments in a row end it.
-    constexpr double kReplace = 1e-2;
+    double kReplace = 1e-2;  // CPCA_IR_REPLACE sets another (for measurements)
+    if (const char* e = std::getenv("CPCA_IR_REPLACE")) kReplace = std::max(1e-6, std::min(0.5, std::atof(e)));
     constexpr int kMaxBad = 3;
     Operator<float> op{(int)p, (int)n, g32, (float)gr, (float)gc, cfg32};
     if (X0)
