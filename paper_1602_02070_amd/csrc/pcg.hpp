@@ -80,11 +80,12 @@ constexpr int kPcCoarseRows = kThreads / kWave;
 
 // The Jacobi part of the preconditioner for one lane's VEC consecutive
 // columns j0.. : omega D^-1 with D(i, j) = m_r(i) m_c(j) + g_r (L_r)_ii +
-// g_c (L_c)_jj, the diagonal of A (every D^-1 below stands for omega D^-1). It is formed in T (FP32: the hardware reciprocal), since
-// a preconditioner only has to be the same fixed positive diagonal in every
-// application of a solve. The column parts are read once per thread, the row
-// parts once per row segment. A zero diagonal (an isolated, unsampled entry:
-// A is singular there) gives 0, the pseudo-inverse.
+// g_c (L_c)_jj, the diagonal of A (every D^-1 below stands for omega D^-1).
+// It is formed in T (FP32: the hardware reciprocal), since a preconditioner
+// only has to be the same fixed positive diagonal in every application of a
+// solve. The column parts are read once per thread, the row parts once per
+// row segment. A zero diagonal (an isolated, unsampled entry: A is singular
+// there) gives 0, the pseudo-inverse.
 template <typename T>
 struct PcJacobi {
   static constexpr int VEC = 16 / (int)sizeof(T);
